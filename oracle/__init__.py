@@ -1,0 +1,8 @@
+"""FP64 CPU oracle for the k-means Lloyd iteration -- test infrastructure only.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this
+package.  It shares no code with the GPU library and imports nothing from it.
+"""
+from .oracle import (  # noqa: F401
+    build, assign, update, lloyd, near_tie_margin, num_threads, LIB_PATH,
+)
