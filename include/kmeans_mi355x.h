@@ -1,0 +1,164 @@
+/*
+ * kmeans_mi355x.h -- C ABI of the MI355X (gfx950) k-means Lloyd library.
+ *
+ * The operation is one Lloyd iteration (S. P. Lloyd, "Least squares
+ * quantization in PCM", IEEE Trans. Inf. Theory 28(2), 1982) expressed as the
+ * paper's fused data-parallel loop (section 2.3: a parallel loop over the
+ * sample range whose body runs once per index in no fixed order, with a
+ * collect body and predicated reduce bodies; section 3.5: loops over the same
+ * range fused into one pass, side-by-side reductions sharing one traversal):
+ *
+ *   map     for every sample i: d_ij = sum_f (x_if - c_jf)^2 for all j,
+ *           L(i) = the smallest j attaining min_j d_ij            (collect)
+ *   reduce  S_j = sum_{i: L(i)=j} x_i (FP64), cnt_j = |{i: L(i)=j}|,
+ *           J = sum_i d_{i,L(i)} (FP64)                           (reduce)
+ *   update  c_j = S_j / cnt_j rounded once to FP32 (the vector mean as sum
+ *           divided by length, section 2.1); an empty cluster keeps c_j.
+ *
+ * Conventions for every call:
+ *   - X is n x d, C is k x d, both FP32, row-major with row stride d, and
+ *     16-byte aligned.  Labels are int32, counts int64, objectives FP64.
+ *   - Every array argument is a DEVICE pointer owned by the caller, borrowed
+ *     until the work enqueued on `stream` completes, unless marked host.
+ *   - Calls are asynchronous on `stream` (NULL = the null stream): KM_OK means
+ *     "enqueued".  Only kmeans_lloyd with tol >= 0 synchronises `stream`
+ *     (to return iters_done).
+ *   - The library never allocates device memory.  Scratch comes from a
+ *     caller-provided workspace of km_plan_workspace_bytes() bytes bound with
+ *     km_plan_set_workspace().
+ *   - On any error nothing is enqueued, outputs are untouched, the status is
+ *     returned and km_last_error() describes it.  No exception crosses the ABI.
+ *   - Shape limits: 1 <= k <= n < 2^31, 1 <= d <= 1024 (the FP32 path
+ *     currently supports d <= 128 and returns KM_ENOTSUP above that).
+ *   - Inputs must be finite; NaN/Inf are not checked on the hot path.
+ *   - A plan is not thread-safe; distinct plans are independent.  Calls that
+ *     share one plan (one workspace) must be ordered on one stream.
+ *
+ * Distances: the FP32 path evaluates every d_ij in direct form, features in
+ * chunks of 8 accumulated by fused multiply-add, chunk partials summed by a
+ * fixed pairwise tree.  Its error is at most (2 + 8 + ceil(log2(ceil(d/8))))
+ * units of 2^-24 relative to d_ij, so a label can differ from the exact
+ * argmin only where the top-2 distances are within that relative margin.
+ * Ties go to the lowest centroid index.  Results are deterministic: the same
+ * inputs on the same plan give bit-identical outputs.
+ */
+#ifndef KMEANS_MI355X_H
+#define KMEANS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KM_OK = 0,
+    KM_EINVAL = -1,      /* bad shape, null or misaligned pointer, bad value */
+    KM_ENOTSUP = -2,     /* valid request this build does not implement      */
+    KM_EHIP = -3,        /* a HIP runtime call failed (message has the text) */
+    KM_EWORKSPACE = -4   /* no workspace bound, or it is too small           */
+} km_status;
+
+typedef enum {
+    KM_FP32 = 0,         /* direct-form FP32 distances (the plain path)      */
+    KM_BF16 = 1,         /* BF16 MFMA distances + proven-band FP32 recheck    */
+    KM_FP8_E4M3 = 2      /* FP8 e4m3 MFMA distances + FP32 recheck           */
+} km_precision;
+
+typedef struct km_plan km_plan;
+
+/*
+ * Create a plan for n samples of dimension d and k centroids on the current
+ * HIP device.  Validates the shape (KM_EINVAL) and precision (KM_ENOTSUP),
+ * then queries the device (KM_EHIP without one).  *out receives the plan
+ * (host memory owned by the library; free it with km_plan_destroy).
+ */
+km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec,
+                         km_plan **out);
+
+/* Bytes of device workspace the plan needs (0 for a NULL plan). */
+size_t km_plan_workspace_bytes(const km_plan *plan);
+
+/*
+ * Bind caller-owned device memory as the plan's workspace.  `ws` must be
+ * 256-byte aligned and at least km_plan_workspace_bytes() long
+ * (KM_EWORKSPACE otherwise).  The workspace is borrowed until the plan is
+ * destroyed or another workspace is bound.
+ */
+km_status km_plan_set_workspace(km_plan *plan, void *ws, size_t bytes);
+
+/* Release a plan (host memory and any captured graph).  NULL is ignored. */
+void km_plan_destroy(km_plan *plan);
+
+/* Text of the last error on the calling thread ("" if none).  Valid until the
+ * next library call on that thread. */
+const char *km_last_error(void);
+
+/*
+ * Assign step (the map of section 2.3): for every sample, the nearest
+ * centroid under squared Euclidean distance, lowest index on ties.
+ *   X        [n x d] FP32 samples
+ *   C        [k x d] FP32 centroids
+ *   labels   [n] int32 output, L(i) in [0, k)
+ *   mindist  [n] FP32 output d_{i,L(i)} as computed, or NULL
+ *   objective [1] FP64 output J = sum_i d_{i,L(i)} (FP64 sum), or NULL
+ */
+km_status kmeans_assign(km_plan *plan, const float *X, const float *C,
+                        int32_t *labels, float *mindist, double *objective,
+                        hipStream_t stream);
+
+/*
+ * Update step (the predicated per-label reduce of section 2.3 and the mean of
+ * section 2.1) from given labels.
+ *   X       [n x d] FP32 samples
+ *   labels  [n] int32 labels; entries outside [0, k) are ignored
+ *   C_old   [k x d] FP32 centroids kept for empty clusters
+ *   C_new   [k x d] FP32 output: fl32(S_j / cnt_j) or C_old[j] if cnt_j = 0
+ *           (may alias C_old)
+ *   counts  [k] int64 output cnt_j, or NULL
+ */
+km_status kmeans_update(km_plan *plan, const float *X, const int32_t *labels,
+                        const float *C_old, float *C_new, int64_t *counts,
+                        hipStream_t stream);
+
+/*
+ * Lloyd iterations, each one assign (with C_t) fused with the reduce and
+ * followed by the update to C_{t+1}, all on the device.
+ *   X          [n x d] FP32 samples
+ *   C          [k x d] FP32 in: C_0, out: C_T
+ *   labels     [n] int32 out: L_{T-1} (the labels C_T is the mean of)
+ *   counts     [k] int64 out: member counts of L_{T-1}, or NULL
+ *   obj_hist   [max_iter] FP64 out: J_t for t < T, or NULL
+ *   max_iter   >= 1
+ *   tol        < 0: run exactly max_iter iterations.
+ *              >= 0: stop after iteration t >= 1 once
+ *              J_{t-1} - J_t <= tol * J_{t-1} or no label changed.
+ *   iters_done HOST int32 out: T, or NULL.  With tol >= 0 the call waits on
+ *              `stream` to read it.
+ */
+km_status kmeans_lloyd(km_plan *plan, const float *X, float *C, int32_t *labels,
+                       int64_t *counts, double *obj_hist, int32_t max_iter,
+                       double tol, int32_t *iters_done, hipStream_t stream);
+
+/*
+ * Diagnostics: per-launch duration of the per-sample pass (the kernel that
+ * computes the distances, labels and per-label partial sums; it dominates
+ * every call).  km_plan_enable_timing(plan, cap) makes the plan record a pair
+ * of HIP events on the call's stream around each such launch, for up to
+ * `cap` launches (cap = 0 turns timing off and releases the events; events are
+ * host-side HIP objects, no device memory is allocated).  Recording restarts
+ * at every enable call.  km_plan_kernel_times() waits for the recorded events
+ * and writes up to `cap` durations in milliseconds into the HOST array `ms`,
+ * and the number recorded into *count.
+ */
+km_status km_plan_enable_timing(km_plan *plan, int32_t cap);
+km_status km_plan_kernel_times(km_plan *plan, float *ms, int32_t cap,
+                               int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KMEANS_MI355X_H */

@@ -1,0 +1,179 @@
+"""Thin ctypes binding of ``libkmeans_mi355x.so`` (argument marshalling only).
+
+Every function mirrors the C entry point of the same name in
+``include/kmeans_mi355x.h``: tensors are passed as device pointers, the stream
+is torch's current HIP stream unless one is given, and a non-OK status raises
+``KMeansError`` carrying ``km_last_error()``.  PyTorch provides device memory
+(tensors, the plan workspace) and streams; all arithmetic runs in the
+library's kernels.  There is no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkmeans_mi355x.so")
+
+KM_OK, KM_EINVAL, KM_ENOTSUP, KM_EHIP, KM_EWORKSPACE = 0, -1, -2, -3, -4
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+
+# Entry points the header declares (checked by the ABI tests).
+EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
+           "km_plan_destroy", "km_last_error", "kmeans_assign", "kmeans_update",
+           "kmeans_lloyd", "km_plan_enable_timing", "km_plan_kernel_times"]
+
+
+class KMeansError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1109_0778_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, F64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.km_plan_create.restype = I32
+        L.km_plan_create.argtypes = [I64, I32, I32, I32, ctypes.POINTER(P)]
+        L.km_plan_workspace_bytes.restype = ctypes.c_size_t
+        L.km_plan_workspace_bytes.argtypes = [P]
+        L.km_plan_set_workspace.restype = I32
+        L.km_plan_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+        L.km_plan_destroy.restype = None
+        L.km_plan_destroy.argtypes = [P]
+        L.km_last_error.restype = ctypes.c_char_p
+        L.km_last_error.argtypes = []
+        L.kmeans_assign.restype = I32
+        L.kmeans_assign.argtypes = [P, P, P, P, P, P, P]
+        L.kmeans_update.restype = I32
+        L.kmeans_update.argtypes = [P, P, P, P, P, P, P]
+        L.kmeans_lloyd.restype = I32
+        L.kmeans_lloyd.argtypes = [P, P, P, P, P, P, I32, F64, ctypes.POINTER(I32), P]
+        L.km_plan_enable_timing.restype = I32
+        L.km_plan_enable_timing.argtypes = [P, I32]
+        L.km_plan_kernel_times.restype = I32
+        L.km_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(I32)]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != KM_OK:
+        raise KMeansError(status, lib().km_last_error().decode())
+
+
+def _ptr(t, dtype, what, numel=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Plan:
+    """km_plan plus a workspace tensor it owns (allocated by torch)."""
+
+    def __init__(self, n: int, d: int, k: int, precision: str = "fp32", device=None):
+        import torch
+        self.n, self.d, self.k, self.precision = int(n), int(d), int(k), precision
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        with torch.cuda.device(dev):
+            h = ctypes.c_void_p()
+            _check(lib().km_plan_create(self.n, self.d, self.k, PRECISIONS[precision], ctypes.byref(h)))
+            self._h = h
+            nbytes = int(lib().km_plan_workspace_bytes(h))
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            off = (-raw.data_ptr()) % 256
+            self.workspace = raw[off:off + nbytes]
+            _check(lib().km_plan_set_workspace(h, self.workspace.data_ptr(), nbytes))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().km_plan_workspace_bytes(self._h))
+
+    def enable_timing(self, cap: int):
+        """km_plan_enable_timing: time up to ``cap`` launches of the per-sample pass."""
+        _check(lib().km_plan_enable_timing(self._h, int(cap)))
+
+    def kernel_times(self, cap: int = 4096):
+        """km_plan_kernel_times: per-launch durations (ms) recorded so far."""
+        buf = (ctypes.c_float * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().km_plan_kernel_times(self._h, buf, cap, ctypes.byref(cnt)))
+        return [float(buf[i]) for i in range(min(cap, cnt.value))]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().km_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kmeans_assign(plan: Plan, X, C, labels, mindist=None, objective=None, stream=None):
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    _check(lib().kmeans_assign(
+        plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(C, torch.float32, "C", k * d),
+        _ptr(labels, torch.int32, "labels", n), _ptr(mindist, torch.float32, "mindist", n),
+        _ptr(objective, torch.float64, "objective", 1), _stream(stream)))
+
+
+def kmeans_update(plan: Plan, X, labels, C_old, C_new, counts=None, stream=None):
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    _check(lib().kmeans_update(
+        plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(labels, torch.int32, "labels", n),
+        _ptr(C_old, torch.float32, "C_old", k * d), _ptr(C_new, torch.float32, "C_new", k * d),
+        _ptr(counts, torch.int64, "counts", k), _stream(stream)))
+
+
+def kmeans_lloyd(plan: Plan, X, C, labels, counts=None, obj_hist=None, max_iter: int = 1,
+                 tol: float = -1.0, stream=None) -> int:
+    """Runs Lloyd iterations in place on C; returns iters_done."""
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    if obj_hist is not None and obj_hist.numel() < max_iter:
+        raise ValueError("obj_hist needs max_iter entries")
+    it = ctypes.c_int32(0)
+    _check(lib().kmeans_lloyd(
+        plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(C, torch.float32, "C", k * d),
+        _ptr(labels, torch.int32, "labels", n), _ptr(counts, torch.int64, "counts", k),
+        _ptr(obj_hist, torch.float64, "obj_hist"), int(max_iter), float(tol), ctypes.byref(it),
+        _stream(stream)))
+    return int(it.value)

@@ -1,0 +1,317 @@
+// Host side of the C ABI declared in include/kmeans_mi355x.h: argument
+// validation, plans and their workspaces, and the launch sequences.
+#include "kmeans_mi355x.h"
+#include "km_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace km;
+
+namespace {
+
+thread_local std::string g_err;
+
+km_status fail(km_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+km_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(KM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct km_plan {
+    int64_t n;
+    int32_t d, k;
+    km_precision prec;
+    int device;
+    int num_cu;
+    int D8, D;           // padded feature count (8-feature chunks)
+    int grid;            // blocks of the per-sample pass = partial slots
+    size_t lds_fused;    // dynamic LDS of the fused / update pass
+    // workspace
+    unsigned char* ws;
+    size_t ws_bytes;
+    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, off_pbad, total;
+    // optional per-launch timing of the per-sample pass
+    std::vector<hipEvent_t> ev;   // 2 per launch
+    int32_t ev_used = 0;
+    ~km_plan()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+km_status check_plan(const km_plan* p)
+{
+    if (!p) return fail(KM_EINVAL, "plan is NULL");
+    if (!p->ws) return fail(KM_EWORKSPACE, "no workspace bound to the plan (km_plan_set_workspace)");
+    return KM_OK;
+}
+
+Partials partials_of(const km_plan* p)
+{
+    Partials pt;
+    pt.S = reinterpret_cast<double*>(p->ws + p->off_pS);
+    pt.cnt = reinterpret_cast<int32_t*>(p->ws + p->off_pcnt);
+    pt.J = reinterpret_cast<double*>(p->ws + p->off_pJ);
+    pt.changed = reinterpret_cast<int32_t*>(p->ws + p->off_pch);
+    pt.bad = reinterpret_cast<int32_t*>(p->ws + p->off_pbad);
+    return pt;
+}
+
+// Launch the per-sample pass, bracketed by timing events when enabled.
+hipError_t timed_pass(km_plan* p, Mode mode, const PassArgs& a, size_t lds, hipStream_t s)
+{
+    const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
+    hipError_t e;
+    if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
+    e = launch_plain_pass(p->D8, mode, a, p->grid, lds, s);
+    if (e != hipSuccess) return e;
+    if (timed) {
+        if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
+        ++p->ev_used;
+    }
+    return hipSuccess;
+}
+
+Ctrl* ctrl_of(const km_plan* p) { return reinterpret_cast<Ctrl*>(p->ws + p->off_ctrl); }
+float* cp_of(const km_plan* p) { return reinterpret_cast<float*>(p->ws + p->off_cp); }
+
+km_status set_device(const km_plan* p)
+{
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device) return fail(KM_EINVAL, "plan was created on device %d but device %d is current", p->device, cur);
+    return KM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* km_last_error(void) { return g_err.c_str(); }
+
+km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_plan** out)
+{
+    g_err.clear();
+    if (!out) return fail(KM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(KM_EINVAL, "n = %lld outside [1, 2^31)", (long long)n);
+    if (d < 1 || d > 1024) return fail(KM_EINVAL, "d = %d outside [1, 1024]", d);
+    if (k < 1 || (int64_t)k > n) return fail(KM_EINVAL, "k = %d outside [1, n]", k);
+    if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3)
+        return fail(KM_EINVAL, "unknown precision %d", (int)prec);
+    if (prec != KM_FP32) return fail(KM_ENOTSUP, "precision %d is not available in this build", (int)prec);
+    if (d > 8 * kMaxD8Plain) return fail(KM_ENOTSUP, "FP32 path supports d <= %d (got %d)", 8 * kMaxD8Plain, d);
+    const size_t lds = plain_lds_bytes(k, d, MODE_FUSED);
+    if (lds > 160 * 1024 - 1024)
+        return fail(KM_ENOTSUP, "k*d = %lld needs %zu bytes of LDS per block; the FP32 path holds at most 159 KiB",
+                    (long long)k * d, lds);
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(multiProcessorCount)");
+
+    km_plan* p = new (std::nothrow) km_plan();
+    if (!p) return fail(KM_EINVAL, "out of host memory");
+    p->n = n; p->d = d; p->k = k; p->prec = prec; p->device = dev; p->num_cu = ncu;
+    p->D8 = (d + 7) / 8;
+    p->D = 8 * p->D8;
+    p->lds_fused = lds;
+    // Blocks resident per CU: LDS-limited, at most 4 (16 waves per CU).
+    const size_t lds_cu = 160 * 1024;
+    int per_cu = (int)std::min<size_t>(4, std::max<size_t>(1, lds_cu / std::max<size_t>(lds + 512, 1)));
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
+
+    size_t off = 0;
+    p->off_ctrl = off; off = align256(off + sizeof(Ctrl));
+    p->off_cp = off;   off = align256(off + (size_t)k * p->D * sizeof(float));
+    p->off_pS = off;   off = align256(off + (size_t)p->grid * k * d * sizeof(double));
+    p->off_pcnt = off; off = align256(off + (size_t)p->grid * k * sizeof(int32_t));
+    p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
+    p->off_pch = off;  off = align256(off + (size_t)p->grid * sizeof(int32_t));
+    p->off_pbad = off; off = align256(off + (size_t)p->grid * sizeof(int32_t));
+    p->total = off;
+    *out = p;
+    return KM_OK;
+}
+
+size_t km_plan_workspace_bytes(const km_plan* plan) { return plan ? plan->total : 0; }
+
+km_status km_plan_set_workspace(km_plan* plan, void* ws, size_t bytes)
+{
+    g_err.clear();
+    if (!plan) return fail(KM_EINVAL, "plan is NULL");
+    if (!ws) return fail(KM_EWORKSPACE, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(KM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < plan->total)
+        return fail(KM_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu the plan needs", bytes, plan->total);
+    plan->ws = static_cast<unsigned char*>(ws);
+    plan->ws_bytes = bytes;
+    return KM_OK;
+}
+
+void km_plan_destroy(km_plan* plan) { delete plan; }
+
+km_status kmeans_assign(km_plan* plan, const float* X, const float* C, int32_t* labels, float* mindist,
+                        double* objective, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    if (!X || !C || !labels) return fail(KM_EINVAL, "X, C and labels must be non-NULL");
+    if (!aligned16(X) || !aligned16(C)) return fail(KM_EINVAL, "X and C must be 16-byte aligned");
+    if ((st = set_device(plan)) != KM_OK) return st;
+
+    hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, cp_of(plan), nullptr, stream);
+    if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
+    PassArgs a{};
+    a.X = X; a.Cp = cp_of(plan); a.labels = labels; a.mindist = mindist;
+    a.part = partials_of(plan); a.ctrl = nullptr;
+    a.n = plan->n; a.d = plan->d; a.k = plan->k; a.iter = 0;
+    e = timed_pass(plan, MODE_ASSIGN, a, 0, stream);
+    if (e != hipSuccess) return hip_fail(e, "assign pass launch");
+    if (objective) {
+        e = launch_reduce_objective(a.part.J, plan->grid, objective, stream);
+        if (e != hipSuccess) return hip_fail(e, "objective reduce launch");
+    }
+    return KM_OK;
+}
+
+km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, const float* C_old, float* C_new,
+                        int64_t* counts, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    if (!X || !labels || !C_old || !C_new) return fail(KM_EINVAL, "X, labels, C_old and C_new must be non-NULL");
+    if (!aligned16(X)) return fail(KM_EINVAL, "X must be 16-byte aligned");
+    if ((st = set_device(plan)) != KM_OK) return st;
+
+    PassArgs a{};
+    a.X = X; a.Cp = nullptr; a.labels = const_cast<int32_t*>(labels); a.mindist = nullptr;
+    a.part = partials_of(plan); a.ctrl = nullptr;
+    a.n = plan->n; a.d = plan->d; a.k = plan->k; a.iter = 0;
+    hipError_t e = timed_pass(plan, MODE_UPDATE, a, plan->lds_fused, stream);
+    if (e != hipSuccess) return hip_fail(e, "update pass launch");
+    FinArgs f{};
+    f.part = a.part; f.G = plan->grid; f.k = plan->k; f.d = plan->d; f.D = plan->D;
+    f.C_old = C_old; f.ld_old = plan->d; f.C_new = C_new; f.ld_new = plan->d; f.Cp_out = nullptr;
+    f.counts = counts; f.ctrl = nullptr; f.obj_hist = nullptr; f.iter = 0; f.tol = -1.0; f.want_J = 0;
+    e = launch_finalize(f, stream);
+    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    return KM_OK;
+}
+
+km_status kmeans_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
+                       double* obj_hist, int32_t max_iter, double tol, int32_t* iters_done, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    if (!X || !C || !labels) return fail(KM_EINVAL, "X, C and labels must be non-NULL");
+    if (!aligned16(X) || !aligned16(C)) return fail(KM_EINVAL, "X and C must be 16-byte aligned");
+    if (max_iter < 1) return fail(KM_EINVAL, "max_iter = %d must be >= 1", max_iter);
+    if (tol != tol) return fail(KM_EINVAL, "tol is NaN");
+    if ((st = set_device(plan)) != KM_OK) return st;
+
+    Ctrl* ctrl = ctrl_of(plan);
+    float* Cp = cp_of(plan);
+    hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, Cp, ctrl, stream);
+    if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
+
+    PassArgs a{};
+    a.X = X; a.Cp = Cp; a.labels = labels; a.mindist = nullptr;
+    a.part = partials_of(plan); a.ctrl = (tol >= 0.0) ? ctrl : nullptr;
+    a.n = plan->n; a.d = plan->d; a.k = plan->k;
+    FinArgs f{};
+    f.part = a.part; f.G = plan->grid; f.k = plan->k; f.d = plan->d; f.D = plan->D;
+    f.C_old = Cp; f.ld_old = plan->D; f.C_new = C; f.ld_new = plan->d; f.Cp_out = Cp;
+    f.counts = counts; f.ctrl = ctrl; f.obj_hist = obj_hist; f.tol = tol; f.want_J = 1;
+    for (int32_t t = 0; t < max_iter; ++t) {
+        a.iter = t;
+        f.iter = t;
+        e = timed_pass(plan, MODE_FUSED, a, plan->lds_fused, stream);
+        if (e != hipSuccess) return hip_fail(e, "fused pass launch");
+        e = launch_finalize(f, stream);
+        if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    }
+    if (iters_done) {
+        if (tol < 0.0) {
+            *iters_done = max_iter;
+        } else {
+            int32_t v = 0;
+            e = hipMemcpyAsync(&v, &ctrl->iters_done, sizeof v, hipMemcpyDeviceToHost, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(iters_done)");
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            *iters_done = v;
+        }
+    }
+    return KM_OK;
+}
+
+km_status km_plan_enable_timing(km_plan* plan, int32_t cap)
+{
+    g_err.clear();
+    if (!plan) return fail(KM_EINVAL, "plan is NULL");
+    if (cap < 0) return fail(KM_EINVAL, "cap = %d must be >= 0", cap);
+    for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
+    plan->ev.clear();
+    plan->ev_used = 0;
+    for (int32_t i = 0; i < 2 * cap; ++i) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+        plan->ev.push_back(e);
+    }
+    return KM_OK;
+}
+
+km_status km_plan_kernel_times(km_plan* plan, float* ms, int32_t cap, int32_t* count)
+{
+    g_err.clear();
+    if (!plan) return fail(KM_EINVAL, "plan is NULL");
+    if (!count || (cap > 0 && !ms)) return fail(KM_EINVAL, "count and ms must be non-NULL");
+    int32_t m = std::min(cap, plan->ev_used);
+    for (int32_t i = 0; i < m; ++i) {
+        hipError_t r = hipEventSynchronize(plan->ev[2 * i + 1]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+        r = hipEventElapsedTime(&ms[i], plan->ev[2 * i], plan->ev[2 * i + 1]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+    }
+    *count = plan->ev_used;
+    return KM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Finalize of one Lloyd iteration: the "combine" of the per-block activation
+// records (section 2.3's generated loop merges partial records with the
+// reduce function) in a fixed order, then the mean as sum / length
+// (section 2.1) with the empty-cluster rule, the objective, the changed-label
+// count and the tolerance decision.  Also the small helper kernels.
+#include "km_internal.h"
+
+#include <climits>
+
+namespace km {
+
+// One block per 64 consecutive elements of the flat k*d sum array.  Wave w of
+// the block sums partial slots [w*G/16, (w+1)*G/16) in increasing order for
+// its 64 elements (coalesced 512-byte rows); the 16 wave sums are then added
+// in wave order.  Block 0 also reduces the objective and drives the control
+// block.
+__global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
+{
+    __shared__ double sS[kFinWaves][64];
+    __shared__ int32_t sC[kFinWaves][64];
+
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t kd = (int64_t)a.k * a.d;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = e < kd;
+    const int j = valid ? (int)(e / a.d) : 0;
+    const int f = valid ? (int)(e - (int64_t)j * a.d) : 0;
+
+    const int s0 = (int)(((int64_t)wave * a.G) / kFinWaves);
+    const int s1 = (int)(((int64_t)(wave + 1) * a.G) / kFinWaves);
+    double acc = 0.0;
+    int32_t cacc = 0;
+    if (valid) {
+        const double* p = a.part.S + e;
+        const int32_t* pc = a.part.cnt + j;
+#pragma unroll 8
+        for (int b = s0; b < s1; ++b) {
+            acc += p[(size_t)b * kd];
+            cacc += pc[(size_t)b * a.k];
+        }
+    }
+    sS[wave][lane] = acc;
+    sC[wave][lane] = cacc;
+    __syncthreads();
+
+    if (wave == 0 && valid) {
+        double S = sS[0][lane];
+        int64_t c = sC[0][lane];
+        for (int w = 1; w < kFinWaves; ++w) { S += sS[w][lane]; c += sC[w][lane]; }
+        float v;
+        if (c > 0) v = (float)(S / (double)c);
+        else v = a.C_old[(size_t)j * a.ld_old + f];
+        a.C_new[(size_t)j * a.ld_new + f] = v;
+        if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
+        if (a.counts && f == 0) a.counts[j] = c;
+    }
+
+    if (blockIdx.x == 0 && a.want_J && wave == 1) {
+        // objective and changed count: lane-strided slots, then xor tree
+        double J = 0.0;
+        int64_t ch = 0;
+        for (int b = lane; b < a.G; b += 64) { J += a.part.J[b]; ch += a.part.changed[b]; }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            J += __shfl_xor(J, off);
+            ch += __shfl_xor(ch, off);
+        }
+        if (lane == 0) {
+            const int t = a.iter;
+            if (a.obj_hist) a.obj_hist[t] = J;
+            if (a.ctrl) {
+                Ctrl* c = a.ctrl;
+                if (a.tol >= 0.0 && t >= 1) {
+                    const double Jp = c->J_prev;
+                    if ((Jp - J) <= a.tol * Jp || ch == 0) c->stop_iter = t;
+                }
+                c->J_prev = J;
+                c->changed_last = ch;
+                c->iters_done = t + 1;
+            }
+        }
+    }
+}
+
+// Pads C (k x d) into Cp (k x D, zero columns d..D-1); optionally resets the
+// control block.
+__global__ void pad_centroids_kernel(const float* __restrict__ C, int32_t k, int32_t d, int32_t D,
+                                     float* __restrict__ Cp, Ctrl* ctrl)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (int64_t)k * D) {
+        const int j = (int)(e / D);
+        const int f = (int)(e - (int64_t)j * D);
+        Cp[e] = (f < d) ? C[(size_t)j * d + f] : 0.0f;
+    }
+    if (ctrl != nullptr && e == 0) {
+        ctrl->stop_iter = INT_MAX;
+        ctrl->iters_done = 0;
+        ctrl->bad_labels = 0;
+        ctrl->J_prev = 0.0;
+        ctrl->changed_last = 0;
+    }
+}
+
+// Objective of an assign-only pass: slot partials in fixed lane-strided order.
+__global__ void reduce_objective_kernel(const double* __restrict__ part_J, int32_t G, double* out)
+{
+    const int lane = threadIdx.x;
+    double J = 0.0;
+    for (int b = lane; b < G; b += 64) J += part_J[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) J += __shfl_xor(J, off);
+    if (lane == 0) *out = J;
+}
+
+__global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s)
+{
+    const int64_t kd = (int64_t)a.k * a.d;
+    const int grid = (int)((kd + 63) / 64);
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(64 * kFinWaves), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_centroids(const float* C, int32_t k, int32_t d, int32_t D, float* Cp, Ctrl* ctrl,
+                                hipStream_t s)
+{
+    const int64_t total = (int64_t)k * D;
+    const int grid = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(pad_centroids_kernel, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, C, k, d, D, Cp, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_objective_kernel, dim3(1), dim3(64), 0, s, part_J, G, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace km

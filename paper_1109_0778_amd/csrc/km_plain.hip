@@ -1,0 +1,287 @@
+// Plain FP32 Lloyd pass for gfx950: assign (map) fused with the per-label
+// reduce, following the parallel-loop contract of section 2.3 (the body runs
+// once per sample index, in no fixed order; writes to shared state happen only
+// at disjoint places) and the fusion of section 3.5 (the assign loop and the
+// reduce loop share the sample range, so they run as one pass and the label
+// vector is consumed in place; the objective is a side-by-side reduction in
+// the same traversal).
+//
+// Layout of one block (256 lanes = 4 wave64s):
+//   * a tile is 256 consecutive samples, one per lane; the block walks tiles
+//     blockIdx.x, blockIdx.x + gridDim.x, ...  (a fixed, schedule-independent
+//     partition of the sample range);
+//   * each lane holds its sample row in VGPRs (zero-padded to D = 8 * D8);
+//     centroid rows are wave-uniform, so they are read with scalar loads and
+//     enter the VALU as SGPR operands: no LDS traffic and no VGPRs for C;
+//   * distances are the canonical direct form (see dist_canonical below);
+//   * the block's activation record -- FP64 per-label sums S[k][d] and counts
+//     -- is private to the block in LDS ("alloc" zeroes it, "process" adds a
+//     sample, and it is merged once per block into a fixed partial slot);
+//   * within a block, wave w owns the labels L with L % 4 == w and adds its
+//     samples in tile order with LDS atomics that it alone issues, so the
+//     order of every FP64 sum is fixed and results are bit-reproducible.
+#include "km_internal.h"
+
+#include <climits>
+
+namespace km {
+
+// Canonical FP32 squared distance: diff = fl(x - c); features in chunks of 8
+// accumulated with fused multiply-add starting from 0; chunk partials summed
+// by the pairwise tree (p += p + s for s = 1, 2, 4, ...).  Zero padding adds
+// exact zeros and does not change the value.  Error <= (2 + 8 + ceil(log2 P))
+// units of 2^-24 of the exact distance (P = number of chunks).
+// Centroids are read through the constant address space: every lane of a
+// wave reads the same row, so the loads become scalar (SMEM) loads and the
+// values enter the VALU as SGPR operands.
+typedef __attribute__((address_space(4))) const float cfloat;
+
+template <int D8>
+__device__ __forceinline__ float dist_canonical(const float (&x)[8 * D8], cfloat* __restrict__ c)
+{
+    float part[D8];
+#pragma unroll
+    for (int p = 0; p < D8; ++p) {
+        float a = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float df = x[8 * p + q] - c[8 * p + q];
+            a = __builtin_fmaf(df, df, a);
+        }
+        part[p] = a;
+    }
+#pragma unroll
+    for (int s = 1; s < D8; s *= 2) {
+#pragma unroll
+        for (int p = 0; p + s < D8; p += 2 * s) part[p] = part[p] + part[p + s];
+    }
+    return part[0];
+}
+
+template <int D8>
+__device__ __forceinline__ void load_row(const float* __restrict__ row, int d, bool valid, float (&x)[8 * D8])
+{
+    constexpr int D = 8 * D8;
+    if (valid && (d & 3) == 0) {
+#pragma unroll
+        for (int q = 0; q < D / 4; ++q) {
+            if (4 * q < d) {
+                const float4 v = *reinterpret_cast<const float4*>(row + 4 * q);
+                x[4 * q + 0] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+            } else {
+                x[4 * q + 0] = 0.f; x[4 * q + 1] = 0.f; x[4 * q + 2] = 0.f; x[4 * q + 3] = 0.f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < D; ++f) x[f] = (valid && f < d) ? row[f] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void lds_add_f64(double* p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Add the samples of one 64-sample group that wave `wave` owns to the block's
+// activation record, in increasing sample order, eight rows in flight.
+template <int D8>
+__device__ __forceinline__ void accumulate_group(const float* __restrict__ Xg, int d, int lab_lane,
+                                                 uint64_t mask, double* S, int32_t* cnt, int lane)
+{
+    constexpr int FPL = (8 * D8 + 63) / 64;  // features per lane
+    constexpr int B = 8;
+    while (mask) {
+        int p[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (mask) {
+                p[u] = __builtin_ctzll(mask);
+                mask &= mask - 1;
+            } else {
+                p[u] = -1;
+            }
+        }
+        float v[B][FPL];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (p[u] >= 0) {
+                const float* row = Xg + (int64_t)p[u] * d;
+#pragma unroll
+                for (int m = 0; m < FPL; ++m) {
+                    const int f = lane + 64 * m;
+                    v[u][m] = (f < d) ? row[f] : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (p[u] >= 0) {
+                const int L = __builtin_amdgcn_readlane(lab_lane, p[u]);
+                double* s = S + (size_t)L * d;
+#pragma unroll
+                for (int m = 0; m < FPL; ++m) {
+                    const int f = lane + 64 * m;
+                    if (f < d) lds_add_f64(s + f, (double)v[u][m]);
+                }
+                if (lane == 0) __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+}
+
+template <int D8, int MODE>
+__global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
+{
+    constexpr int D = 8 * D8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double redJ[kWaves];
+    __shared__ int32_t redC[kWaves];
+    __shared__ int32_t redB[kWaves];
+
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;  // converged earlier
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int k = a.k, d = a.d;
+    const int64_t n = a.n;
+
+    double* S = reinterpret_cast<double*>(smem);
+    int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)k * d);
+    int32_t* lbl = cnt + (((size_t)k + 3) & ~(size_t)3);
+
+    if (MODE != MODE_ASSIGN) {
+        for (int e = tid; e < k * d; e += kBlock) S[e] = 0.0;
+        for (int j = tid; j < k; j += kBlock) cnt[j] = 0;
+    }
+    __syncthreads();
+
+    double Jl = 0.0;
+    int32_t changed = 0, bad = 0;
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    int buf = 0;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t gp = t * kTile + tid;
+        const bool valid = gp < n;
+        int lab = -1;
+        if (MODE == MODE_UPDATE) {
+            if (valid) {
+                lab = a.labels[gp];
+                if (lab < 0 || lab >= k) { ++bad; lab = -1; }
+            }
+        } else {
+            float x[D];
+            load_row<D8>(a.X + (valid ? gp : 0) * d, d, valid, x);
+            float best = __builtin_huge_valf();
+            int bj = 0;
+            cfloat* Cc = (cfloat*)a.Cp;
+            for (int j = 0; j < k; ++j) {
+                const float dist = dist_canonical<D8>(x, Cc + (size_t)j * D);
+                if (dist < best) { best = dist; bj = j; }
+            }
+            if (valid) {
+                if (MODE == MODE_FUSED) changed += (a.iter == 0) ? 1 : (a.labels[gp] != bj);
+                a.labels[gp] = bj;
+                if (a.mindist) a.mindist[gp] = best;
+                Jl += (double)best;
+                lab = bj;
+            }
+        }
+        if (MODE != MODE_ASSIGN) {
+            int32_t* lb = lbl + buf * kTile;
+            lb[tid] = lab;
+            __syncthreads();
+            const float* Xt = a.X + t * kTile * (int64_t)d;
+#pragma unroll 1
+            for (int g = 0; g < kTile / 64; ++g) {
+                const int L = lb[g * 64 + lane];
+                const uint64_t mask = __ballot(L >= 0 && (L & (kWaves - 1)) == wave);
+                accumulate_group<D8>(Xt + (int64_t)g * 64 * d, d, L, mask, S, cnt, lane);
+            }
+            buf ^= 1;
+        }
+    }
+
+    // Merge once per block: the activation record goes to this block's slot.
+    __syncthreads();
+    const int G = gridDim.x;
+    const int b = blockIdx.x;
+    if (MODE != MODE_ASSIGN) {
+        double* dst = a.part.S + (size_t)b * k * d;
+        for (int e = tid; e < k * d; e += kBlock) dst[e] = S[e];
+        int32_t* dc = a.part.cnt + (size_t)b * k;
+        for (int j = tid; j < k; j += kBlock) dc[j] = cnt[j];
+    }
+    // Fixed-order reductions of the scalar partials: xor tree inside the
+    // wave (lane 0's value), then waves in index order.
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Jl += __shfl_xor(Jl, off);
+        changed += __shfl_xor(changed, off);
+        bad += __shfl_xor(bad, off);
+    }
+    if (lane == 0) { redJ[wave] = Jl; redC[wave] = changed; redB[wave] = bad; }
+    __syncthreads();
+    if (tid == 0) {
+        double J = redJ[0];
+        int32_t c = redC[0], bb = redB[0];
+        for (int w = 1; w < kWaves; ++w) { J += redJ[w]; c += redC[w]; bb += redB[w]; }
+        a.part.J[b] = J;
+        a.part.changed[b] = c;
+        a.part.bad[b] = bb;
+    }
+    (void)G;
+}
+
+template <int D8, int MODE>
+static hipError_t allow_lds(size_t lds)
+{
+    // Dynamic LDS above 64 KiB must be opted into per kernel (gfx950 has 160 KiB per CU).
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&plain_pass<D8, MODE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int D8>
+static hipError_t launch_d8(Mode mode, const PassArgs& a, int grid, size_t lds, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    switch (mode) {
+    case MODE_ASSIGN: e = allow_lds<D8, MODE_ASSIGN>(lds); break;
+    case MODE_UPDATE: e = allow_lds<D8, MODE_UPDATE>(lds); break;
+    case MODE_FUSED:  e = allow_lds<D8, MODE_FUSED>(lds); break;
+    }
+    if (e != hipSuccess) return e;
+    switch (mode) {
+    case MODE_ASSIGN: hipLaunchKernelGGL((plain_pass<D8, MODE_ASSIGN>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case MODE_UPDATE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case MODE_FUSED:  hipLaunchKernelGGL((plain_pass<D8, MODE_FUSED>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, int grid, size_t lds, hipStream_t s)
+{
+    switch (D8) {
+    case 1: return launch_d8<1>(mode, a, grid, lds, s);
+    case 2: return launch_d8<2>(mode, a, grid, lds, s);
+    case 3: return launch_d8<3>(mode, a, grid, lds, s);
+    case 4: return launch_d8<4>(mode, a, grid, lds, s);
+    case 5: return launch_d8<5>(mode, a, grid, lds, s);
+    case 6: return launch_d8<6>(mode, a, grid, lds, s);
+    case 7: return launch_d8<7>(mode, a, grid, lds, s);
+    case 8: return launch_d8<8>(mode, a, grid, lds, s);
+    case 9: return launch_d8<9>(mode, a, grid, lds, s);
+    case 10: return launch_d8<10>(mode, a, grid, lds, s);
+    case 11: return launch_d8<11>(mode, a, grid, lds, s);
+    case 12: return launch_d8<12>(mode, a, grid, lds, s);
+    case 13: return launch_d8<13>(mode, a, grid, lds, s);
+    case 14: return launch_d8<14>(mode, a, grid, lds, s);
+    case 15: return launch_d8<15>(mode, a, grid, lds, s);
+    case 16: return launch_d8<16>(mode, a, grid, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace km
