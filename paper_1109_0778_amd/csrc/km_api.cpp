@@ -52,7 +52,7 @@ struct km_plan {
     // workspace
     unsigned char* ws;
     size_t ws_bytes;
-    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, off_pbad, total;
+    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, off_pbad, off_stS, off_stC, total;
     // optional per-launch timing of the per-sample pass
     std::vector<hipEvent_t> ev;   // 2 per launch
     int32_t ev_used = 0;
@@ -147,10 +147,12 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->D8 = (d + 7) / 8;
     p->D = 8 * p->D8;
     p->lds_fused = lds;
-    // Blocks resident per CU: LDS-limited, at most 4 (16 waves per CU).
-    const size_t lds_cu = 160 * 1024;
-    int per_cu = (int)std::min<size_t>(4, std::max<size_t>(1, lds_cu / std::max<size_t>(lds + 512, 1)));
-    const int64_t ntiles = (n + kTile - 1) / kTile;
+    // One resident wave of blocks (the pass walks its tiles persistently): the
+    // smaller residency of the fused and assign-only variants, capped at 4.
+    int per_cu = std::min(plain_blocks_per_cu(p->D8, MODE_FUSED, lds), plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0));
+    if (per_cu < 1) { delete p; return fail(KM_EHIP, "occupancy query for the per-sample pass failed"); }
+    per_cu = std::min(per_cu, 4);
+    const int64_t ntiles = (n + plain_tile(p->D8) - 1) / plain_tile(p->D8);
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
 
     size_t off = 0;
@@ -161,6 +163,8 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
     p->off_pch = off;  off = align256(off + (size_t)p->grid * sizeof(int32_t));
     p->off_pbad = off; off = align256(off + (size_t)p->grid * sizeof(int32_t));
+    p->off_stS = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(double));
+    p->off_stC = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(int32_t));
     p->total = off;
     *out = p;
     return KM_OK;
@@ -225,6 +229,8 @@ km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, co
     hipError_t e = timed_pass(plan, MODE_UPDATE, a, plan->lds_fused, stream);
     if (e != hipSuccess) return hip_fail(e, "update pass launch");
     FinArgs f{};
+    f.stageS = reinterpret_cast<double*>(plan->ws + plan->off_stS);
+    f.stageC = reinterpret_cast<int32_t*>(plan->ws + plan->off_stC);
     f.part = a.part; f.G = plan->grid; f.k = plan->k; f.d = plan->d; f.D = plan->D;
     f.C_old = C_old; f.ld_old = plan->d; f.C_new = C_new; f.ld_new = plan->d; f.Cp_out = nullptr;
     f.counts = counts; f.ctrl = nullptr; f.obj_hist = nullptr; f.iter = 0; f.tol = -1.0; f.want_J = 0;
@@ -255,6 +261,8 @@ km_status kmeans_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels,
     a.part = partials_of(plan); a.ctrl = (tol >= 0.0) ? ctrl : nullptr;
     a.n = plan->n; a.d = plan->d; a.k = plan->k;
     FinArgs f{};
+    f.stageS = reinterpret_cast<double*>(plan->ws + plan->off_stS);
+    f.stageC = reinterpret_cast<int32_t*>(plan->ws + plan->off_stC);
     f.part = a.part; f.G = plan->grid; f.k = plan->k; f.d = plan->d; f.D = plan->D;
     f.C_old = Cp; f.ld_old = plan->D; f.C_new = C; f.ld_new = plan->d; f.Cp_out = Cp;
     f.counts = counts; f.ctrl = ctrl; f.obj_hist = obj_hist; f.tol = tol; f.want_J = 1;

@@ -9,16 +9,15 @@
 
 namespace km {
 
-// One block per 64 consecutive elements of the flat k*d sum array.  Wave w of
-// the block sums partial slots [w*G/16, (w+1)*G/16) in increasing order for
-// its 64 elements (coalesced 512-byte rows); the 16 wave sums are then added
-// in wave order.  Block 0 also reduces the objective and drives the control
-// block.
-__global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
+// Stage 1: block (c, s) sums partial slots [s*G/S, (s+1)*G/S) for the 64
+// elements 64c .. 64c+63 of the flat k*d sum array (S = kFinSplit).  Its 4
+// waves take consecutive quarters of that slot range, each in increasing slot
+// order over coalesced 512-byte rows; the quarters are then added in wave
+// order.  Counts travel alongside (per element, from its label's slots).
+__global__ __launch_bounds__(256) void finalize_partial_kernel(FinArgs a)
 {
-    __shared__ double sS[kFinWaves][64];
-    __shared__ int32_t sC[kFinWaves][64];
-
+    __shared__ double sS[4][64];
+    __shared__ int32_t sC[4][64];
     if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
 
     const int lane = threadIdx.x & 63;
@@ -27,16 +26,17 @@ __global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
     const int64_t e = (int64_t)blockIdx.x * 64 + lane;
     const bool valid = e < kd;
     const int j = valid ? (int)(e / a.d) : 0;
-    const int f = valid ? (int)(e - (int64_t)j * a.d) : 0;
-
-    const int s0 = (int)(((int64_t)wave * a.G) / kFinWaves);
-    const int s1 = (int)(((int64_t)(wave + 1) * a.G) / kFinWaves);
+    const int split = blockIdx.y;
+    const int lo = (int)(((int64_t)split * a.G) / kFinSplit);
+    const int hi = (int)(((int64_t)(split + 1) * a.G) / kFinSplit);
+    const int s0 = lo + (int)(((int64_t)wave * (hi - lo)) / 4);
+    const int s1 = lo + (int)(((int64_t)(wave + 1) * (hi - lo)) / 4);
     double acc = 0.0;
     int32_t cacc = 0;
     if (valid) {
         const double* p = a.part.S + e;
         const int32_t* pc = a.part.cnt + j;
-#pragma unroll 8
+#pragma unroll 16
         for (int b = s0; b < s1; ++b) {
             acc += p[(size_t)b * kd];
             cacc += pc[(size_t)b * a.k];
@@ -45,20 +45,44 @@ __global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
     sS[wave][lane] = acc;
     sC[wave][lane] = cacc;
     __syncthreads();
-
     if (wave == 0 && valid) {
-        double S = sS[0][lane];
-        int64_t c = sC[0][lane];
-        for (int w = 1; w < kFinWaves; ++w) { S += sS[w][lane]; c += sC[w][lane]; }
-        float v;
-        if (c > 0) v = (float)(S / (double)c);
-        else v = a.C_old[(size_t)j * a.ld_old + f];
-        a.C_new[(size_t)j * a.ld_new + f] = v;
-        if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
-        if (a.counts && f == 0) a.counts[j] = c;
+        const double S = ((sS[0][lane] + sS[1][lane]) + sS[2][lane]) + sS[3][lane];
+        const int32_t c = sC[0][lane] + sC[1][lane] + sC[2][lane] + sC[3][lane];
+        a.stageS[(size_t)split * kd + e] = S;
+        a.stageC[(size_t)split * kd + e] = c;
     }
+}
 
-    if (blockIdx.x == 0 && a.want_J && wave == 1) {
+// Stage 2: the kFinSplit stage sums of each element in split order, then the
+// mean with the empty-cluster rule.  Block 0's second wave reduces the
+// objective and the changed count and drives the control block.
+__global__ __launch_bounds__(128) void finalize_combine_kernel(FinArgs a)
+{
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t kd = (int64_t)a.k * a.d;
+    if (wave == 0) {
+        const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+        if (e < kd) {
+            const int j = (int)(e / a.d);
+            const int f = (int)(e - (int64_t)j * a.d);
+            double S = a.stageS[e];
+            int64_t c = a.stageC[e];
+#pragma unroll
+            for (int s = 1; s < kFinSplit; ++s) {
+                S += a.stageS[(size_t)s * kd + e];
+                c += a.stageC[(size_t)s * kd + e];
+            }
+            float v;
+            if (c > 0) v = (float)(S / (double)c);
+            else v = a.C_old[(size_t)j * a.ld_old + f];
+            a.C_new[(size_t)j * a.ld_new + f] = v;
+            if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
+            if (a.counts && f == 0) a.counts[j] = c;
+        }
+    } else if (blockIdx.x == 0 && a.want_J) {
         // objective and changed count: lane-strided slots, then xor tree
         double J = 0.0;
         int64_t ch = 0;
@@ -126,7 +150,10 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t s)
 {
     const int64_t kd = (int64_t)a.k * a.d;
     const int grid = (int)((kd + 63) / 64);
-    hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(64 * kFinWaves), 0, s, a);
+    hipLaunchKernelGGL(finalize_partial_kernel, dim3(grid, kFinSplit), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_combine_kernel, dim3(grid), dim3(128), 0, s, a);
     return hipGetLastError();
 }
 

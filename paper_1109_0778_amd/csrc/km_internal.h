@@ -10,11 +10,11 @@ namespace km {
 // Plain-path launch geometry: one sample per lane, 256 lanes per block.
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kTile = kBlock;
 constexpr int kMaxD8Plain = 16;       // plain path: d <= 128 (eight-feature chunks)
 
-// Finalize geometry: 64 elements per block, 16 waves split the partial slots.
-constexpr int kFinWaves = 16;
+// Finalize geometry: 64 elements per block; the partial slots are split
+// kFinSplit ways in a first stage, whose sums a second stage adds in order.
+constexpr int kFinSplit = 16;
 
 enum Mode : int { MODE_ASSIGN = 0, MODE_UPDATE = 1, MODE_FUSED = 2 };
 
@@ -54,6 +54,8 @@ struct PassArgs {
 
 struct FinArgs {
     Partials part;
+    double* stageS;       // [kFinSplit][k*d] first-stage sums
+    int32_t* stageC;      // [kFinSplit][k*d] first-stage counts (per element)
     int32_t G;            // number of partial slots
     int32_t k, d, D;
     const float* C_old; int32_t ld_old;   // centroids kept for empty clusters
@@ -73,8 +75,17 @@ hipError_t launch_pad_centroids(const float* C, int32_t k, int32_t d, int32_t D,
 hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, int grid, size_t lds_bytes,
                              hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+// Resident blocks per CU of the plain pass (HIP occupancy query), -1 on error.
+int plain_blocks_per_cu(int D8, Mode mode, size_t lds_bytes);
 hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStream_t s);
+
+// Samples per lane in the plain pass.  One: measured on MI355X at d = 64,
+// k = 64, two samples per lane (sharing each SGPR centroid operand) ran 18%
+// slower (3 instead of 4 resident waves per SIMD), and LDS-broadcast centroid
+// operands 13% slower than SGPR operands.
+constexpr int plain_rows_per_lane(int) { return 1; }
+inline int plain_tile(int D8) { return kBlock * plain_rows_per_lane(D8); }
 
 // LDS bytes the plain pass needs for given k, d (activation record + label buffers).
 inline size_t plain_lds_bytes(int k, int d, Mode mode)
@@ -83,7 +94,7 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
     if (mode != MODE_ASSIGN) {
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
-        b += 2 * kTile * sizeof(int32_t);
+        b += 2 * (size_t)kBlock * 2 * sizeof(int32_t);
     }
     return b;
 }

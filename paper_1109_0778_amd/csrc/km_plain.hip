@@ -130,10 +130,59 @@ __device__ __forceinline__ void accumulate_group(const float* __restrict__ Xg, i
     }
 }
 
+// R distances against one centroid row; the row's values are shared by the R
+// samples a lane holds.
+template <int D8, int R, typename CP>
+__device__ __forceinline__ void dist_rows(const float (&x)[R][8 * D8], CP c, float (&out)[R])
+{
+    float part[R][D8];
+#pragma unroll
+    for (int p = 0; p < D8; ++p) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[r][p] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float cv = c[8 * p + q];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float df = x[r][8 * p + q] - cv;
+                part[r][p] = __builtin_fmaf(df, df, part[r][p]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int s = 1; s < D8; s *= 2) {
+#pragma unroll
+            for (int p = 0; p + s < D8; p += 2 * s) part[r][p] = part[r][p] + part[r][p + s];
+        }
+        out[r] = part[r][0];
+    }
+}
+
+// Nearest centroid of each of the R rows a lane holds, over all k centroids,
+// with the canonical distance.  Ties keep the lower index.
+template <int D8, int R, typename CP>
+__device__ __forceinline__ void nearest(const float (&x)[R][8 * D8], CP C, int k, float (&best)[R], int (&bj)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) { best[r] = __builtin_huge_valf(); bj[r] = 0; }
+    for (int j = 0; j < k; ++j) {
+        float dist[R];
+        dist_rows<D8, R>(x, C + (size_t)j * (8 * D8), dist);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (dist[r] < best[r]) { best[r] = dist[r]; bj[r] = j; }
+    }
+}
+
 template <int D8, int MODE>
 __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
 {
     constexpr int D = 8 * D8;
+    constexpr int R = plain_rows_per_lane(D8);
+    constexpr int TILE = kBlock * R;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double redJ[kWaves];
     __shared__ int32_t redC[kWaves];
@@ -151,6 +200,7 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)k * d);
     int32_t* lbl = cnt + (((size_t)k + 3) & ~(size_t)3);
 
+    // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
         for (int e = tid; e < k * d; e += kBlock) S[e] = 0.0;
         for (int j = tid; j < k; j += kBlock) cnt[j] = 0;
@@ -159,42 +209,54 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
 
     double Jl = 0.0;
     int32_t changed = 0, bad = 0;
-    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
     int buf = 0;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t gp = t * kTile + tid;
-        const bool valid = gp < n;
-        int lab = -1;
+        // lane holds samples t*TILE + r*256 + tid, r < R
+        int lab[R];
         if (MODE == MODE_UPDATE) {
-            if (valid) {
-                lab = a.labels[gp];
-                if (lab < 0 || lab >= k) { ++bad; lab = -1; }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t gp = t * TILE + r * kBlock + tid;
+                lab[r] = -1;
+                if (gp < n) {
+                    lab[r] = a.labels[gp];
+                    if (lab[r] < 0 || lab[r] >= k) { ++bad; lab[r] = -1; }
+                }
             }
         } else {
-            float x[D];
-            load_row<D8>(a.X + (valid ? gp : 0) * d, d, valid, x);
-            float best = __builtin_huge_valf();
-            int bj = 0;
-            cfloat* Cc = (cfloat*)a.Cp;
-            for (int j = 0; j < k; ++j) {
-                const float dist = dist_canonical<D8>(x, Cc + (size_t)j * D);
-                if (dist < best) { best = dist; bj = j; }
+            float x[R][D];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t gp = t * TILE + r * kBlock + tid;
+                const bool valid = gp < n;
+                load_row<D8>(a.X + (valid ? gp : 0) * d, d, valid, x[r]);
             }
-            if (valid) {
-                if (MODE == MODE_FUSED) changed += (a.iter == 0) ? 1 : (a.labels[gp] != bj);
-                a.labels[gp] = bj;
-                if (a.mindist) a.mindist[gp] = best;
-                Jl += (double)best;
-                lab = bj;
+            float best[R];
+            int bj[R];
+            nearest<D8, R>(x, (cfloat*)a.Cp, k, best, bj);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t gp = t * TILE + r * kBlock + tid;
+                lab[r] = -1;
+                if (gp < n) {
+                    if (MODE == MODE_FUSED) changed += (a.iter == 0) ? 1 : (a.labels[gp] != bj[r]);
+                    a.labels[gp] = bj[r];
+                    if (a.mindist) a.mindist[gp] = best[r];
+                    Jl += (double)best[r];
+                    lab[r] = bj[r];
+                }
             }
         }
         if (MODE != MODE_ASSIGN) {
-            int32_t* lb = lbl + buf * kTile;
-            lb[tid] = lab;
+            // "process": every sample of the tile into the activation record
+            int32_t* lb = lbl + buf * TILE;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lb[r * kBlock + tid] = lab[r];
             __syncthreads();
-            const float* Xt = a.X + t * kTile * (int64_t)d;
+            const float* Xt = a.X + t * TILE * (int64_t)d;
 #pragma unroll 1
-            for (int g = 0; g < kTile / 64; ++g) {
+            for (int g = 0; g < TILE / 64; ++g) {
                 const int L = lb[g * 64 + lane];
                 const uint64_t mask = __ballot(L >= 0 && (L & (kWaves - 1)) == wave);
                 accumulate_group<D8>(Xt + (int64_t)g * 64 * d, d, L, mask, S, cnt, lane);
@@ -205,7 +267,6 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
 
     // Merge once per block: the activation record goes to this block's slot.
     __syncthreads();
-    const int G = gridDim.x;
     const int b = blockIdx.x;
     if (MODE != MODE_ASSIGN) {
         double* dst = a.part.S + (size_t)b * k * d;
@@ -231,7 +292,6 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
         a.part.changed[b] = c;
         a.part.bad[b] = bb;
     }
-    (void)G;
 }
 
 template <int D8, int MODE>
@@ -259,6 +319,30 @@ static hipError_t launch_d8(Mode mode, const PassArgs& a, int grid, size_t lds, 
     case MODE_FUSED:  hipLaunchKernelGGL((plain_pass<D8, MODE_FUSED>), dim3(grid), dim3(kBlock), lds, s, a); break;
     }
     return hipGetLastError();
+}
+
+template <int D8>
+static int occupancy_d8(Mode mode, size_t lds)
+{
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    switch (mode) {
+    case MODE_ASSIGN: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_ASSIGN>, kBlock, lds); break;
+    case MODE_UPDATE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_UPDATE>, kBlock, lds); break;
+    case MODE_FUSED:  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_FUSED>, kBlock, lds); break;
+    }
+    return e == hipSuccess ? nb : -1;
+}
+
+int plain_blocks_per_cu(int D8, Mode mode, size_t lds)
+{
+    switch (D8) {
+#define KM_OCC(N) case N: return occupancy_d8<N>(mode, lds);
+    KM_OCC(1) KM_OCC(2) KM_OCC(3) KM_OCC(4) KM_OCC(5) KM_OCC(6) KM_OCC(7) KM_OCC(8)
+    KM_OCC(9) KM_OCC(10) KM_OCC(11) KM_OCC(12) KM_OCC(13) KM_OCC(14) KM_OCC(15) KM_OCC(16)
+#undef KM_OCC
+    default: return -1;
+    }
 }
 
 hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, int grid, size_t lds, hipStream_t s)
