@@ -47,8 +47,19 @@ struct km_plan {
     int device;
     int num_cu;
     int D8, D;           // padded feature count (8-feature chunks)
-    int grid;            // blocks of the per-sample pass = partial slots
-    size_t lds_fused;    // dynamic LDS of the fused / update pass
+    int grid;            // blocks of the assign / fused pass (one resident wave)
+    bool split;          // per-label record too large for one block: assign, then chunked update
+    int kc, nch;         // update: labels per chunk, chunks
+    int grid_upd;        // update: slots (point ranges) per chunk
+    size_t lds_fused;    // dynamic LDS of the fused pass (whole record)
+    size_t lds_upd;      // dynamic LDS of the update pass (one chunk of the record)
+    int GS() const { return split ? grid_upd : grid; }
+    // mixed precision (BF16 MFMA + FP32 recheck)
+    bool mixed = false;
+    int D16 = 0, DP = 0, kpad = 0, IB = 0;
+    int grid_mfma = 0, grid_rc = 0;
+    size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
+           off_rqc = 0, off_jt = 0;
     // workspace
     unsigned char* ws;
     size_t ws_bytes;
@@ -85,18 +96,95 @@ Partials partials_of(const km_plan* p)
 }
 
 // Launch the per-sample pass, bracketed by timing events when enabled.
-hipError_t timed_pass(km_plan* p, Mode mode, const PassArgs& a, size_t lds, hipStream_t s)
+hipError_t timed_pass(km_plan* p, Mode mode, const PassArgs& a, dim3 grid, size_t lds, hipStream_t s)
 {
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
     hipError_t e;
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
-    e = launch_plain_pass(p->D8, mode, a, p->grid, lds, s);
+    e = launch_plain_pass(p->D8, mode, a, grid, lds, s);
     if (e != hipSuccess) return e;
     if (timed) {
         if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
         ++p->ev_used;
     }
     return hipSuccess;
+}
+
+PassArgs pass_args(const km_plan* p, const float* X, const float* Cp, int32_t* labels)
+{
+    PassArgs a{};
+    a.X = X; a.Cp = Cp; a.labels = labels; a.mindist = nullptr;
+    a.part = partials_of(p); a.ctrl = nullptr;
+    a.n = p->n; a.d = p->d; a.k = p->k; a.iter = 0; a.count_changed = 0; a.kc = p->kc;
+    return a;
+}
+
+FinArgs fin_args(const km_plan* p)
+{
+    FinArgs f{};
+    f.part = partials_of(p);
+    f.stageS = reinterpret_cast<double*>(p->ws + p->off_stS);
+    f.stageC = reinterpret_cast<int32_t*>(p->ws + p->off_stC);
+    f.G = p->GS(); f.GJ = p->grid; f.k = p->k; f.d = p->d; f.D = p->D;
+    f.tol = -1.0;
+    f.jmode = p->mixed ? 1 : 0;
+    f.Jterm = reinterpret_cast<double*>(p->ws + p->off_jt);
+    f.sum_xn2 = p->mixed ? &reinterpret_cast<const XStats*>(p->ws + p->off_xs)->sum_xn2 : nullptr;
+    f.GC = p->mixed ? p->grid_mfma + p->grid_rc : p->grid;
+    return f;
+}
+
+// The reduce from stored labels: one pass (whole record) or a 2-D grid of
+// label chunks.
+hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
+{
+    if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_fused, s);
+    return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
+}
+
+// Mixed path: the MFMA pass (timed) and the exact recheck of its queue.
+hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, const Ctrl* ctrl, int iter,
+                                int count_changed, hipStream_t s)
+{
+    unsigned char* ws = p->ws;
+    int32_t* changed = reinterpret_cast<int32_t*>(ws + p->off_pch);
+    hipError_t e = launch_prep_c(reinterpret_cast<const float*>(ws + p->off_cp), p->k, p->d, p->D, p->kpad, p->DP,
+                                 reinterpret_cast<const XStats*>(ws + p->off_xs), reinterpret_cast<__bf16*>(ws + p->off_ab),
+                                 reinterpret_cast<float*>(ws + p->off_bias), reinterpret_cast<CStats*>(ws + p->off_cs),
+                                 reinterpret_cast<int32_t*>(ws + p->off_rqc), ctrl, iter, s);
+    if (e != hipSuccess) return e;
+    MixArgs m{};
+    m.X = X; m.n = p->n; m.d = p->d; m.k = p->k; m.kpad = p->kpad;
+    m.Ab = reinterpret_cast<const __bf16*>(ws + p->off_ab);
+    m.bias = reinterpret_cast<const float*>(ws + p->off_bias);
+    m.cs = reinterpret_cast<const CStats*>(ws + p->off_cs);
+    m.u = 0.00390625f;                       // BF16: 8 significant bits, u = 2^-8
+    m.IB = p->IB;
+    m.gamma_terms = 2 * p->DP + 8;
+    m.D8 = p->D8;
+    m.labels = labels;
+    m.rq = reinterpret_cast<int32_t*>(ws + p->off_rq);
+    m.rq_count = reinterpret_cast<int32_t*>(ws + p->off_rqc);
+    m.changed_part = changed;
+    m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
+    const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
+    if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
+    if ((e = launch_mfma_assign(p->D16, m, p->grid_mfma, s)) != hipSuccess) return e;
+    if (timed) {
+        if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
+        ++p->ev_used;
+    }
+    RecheckArgs r{};
+    r.X = X; r.Cp = reinterpret_cast<const float*>(ws + p->off_cp); r.n = p->n; r.d = p->d; r.k = p->k;
+    r.rq = m.rq; r.rq_count = m.rq_count; r.labels = labels; r.changed_part = changed + p->grid_mfma;
+    r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
+    return launch_recheck(p->D8, r, p->grid_rc, s);
+}
+
+hipError_t enqueue_prep_x(km_plan* p, const float* X, hipStream_t s)
+{
+    return launch_prep_x(X, p->n, p->d, reinterpret_cast<float*>(p->ws + p->off_pxm),
+                         reinterpret_cast<double*>(p->ws + p->off_pxs), reinterpret_cast<XStats*>(p->ws + p->off_xs), s);
 }
 
 Ctrl* ctrl_of(const km_plan* p) { return reinterpret_cast<Ctrl*>(p->ws + p->off_ctrl); }
@@ -127,12 +215,10 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     if (k < 1 || (int64_t)k > n) return fail(KM_EINVAL, "k = %d outside [1, n]", k);
     if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3)
         return fail(KM_EINVAL, "unknown precision %d", (int)prec);
-    if (prec != KM_FP32) return fail(KM_ENOTSUP, "precision %d is not available in this build", (int)prec);
-    if (d > 8 * kMaxD8Plain) return fail(KM_ENOTSUP, "FP32 path supports d <= %d (got %d)", 8 * kMaxD8Plain, d);
-    const size_t lds = plain_lds_bytes(k, d, MODE_FUSED);
-    if (lds > 160 * 1024 - 1024)
-        return fail(KM_ENOTSUP, "k*d = %lld needs %zu bytes of LDS per block; the FP32 path holds at most 159 KiB",
-                    (long long)k * d, lds);
+    if (prec == KM_FP8_E4M3) return fail(KM_ENOTSUP, "FP8 distances are not available in this build");
+    if (d > 8 * kMaxD8Plain) return fail(KM_ENOTSUP, "this build supports d <= %d (got %d)", 8 * kMaxD8Plain, d);
+    if (prec == KM_BF16 && ((int64_t)k + kMixCK - 1) / kMixCK * kMixCK > 16384)
+        return fail(KM_ENOTSUP, "BF16 distances support k <= 16384 (got %d)", k);
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -146,25 +232,66 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->n = n; p->d = d; p->k = k; p->prec = prec; p->device = dev; p->num_cu = ncu;
     p->D8 = (d + 7) / 8;
     p->D = 8 * p->D8;
-    p->lds_fused = lds;
-    // One resident wave of blocks (the pass walks its tiles persistently): the
-    // smaller residency of the fused and assign-only variants, capped at 4.
-    int per_cu = std::min(plain_blocks_per_cu(p->D8, MODE_FUSED, lds), plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0));
-    if (per_cu < 1) { delete p; return fail(KM_EHIP, "occupancy query for the per-sample pass failed"); }
-    per_cu = std::min(per_cu, 4);
     const int64_t ntiles = (n + plain_tile(p->D8) - 1) / plain_tile(p->D8);
+
+    // The per-label record (k x d FP64 + counts) lives in LDS.  Up to 80 KiB
+    // (two blocks per CU) it is whole and the assign and reduce run fused;
+    // beyond that the reduce runs as a separate pass over label chunks of at
+    // most 64 KiB, a 2-D grid of (point range, label chunk) blocks.
+    p->lds_fused = plain_lds_bytes(k, d, MODE_FUSED);
+    p->split = p->lds_fused > 80 * 1024;
+    p->kc = p->split ? std::max(1, (64 * 1024) / (8 * d)) : k;
+    p->nch = (k + p->kc - 1) / p->kc;
+    p->lds_upd = plain_lds_bytes(p->kc, d, MODE_UPDATE);
+
+    // One resident wave of blocks for the persistent passes, at most 4 per CU.
+    int per_cu = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
+    if (!p->split) per_cu = std::min(per_cu, plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused));
+    int per_cu_upd = plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
+    if (per_cu < 1 || per_cu_upd < 1) { delete p; return fail(KM_EHIP, "occupancy query for the per-sample pass failed"); }
+    per_cu = std::min(per_cu, 4);
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
+    if (p->split) {
+        const int64_t resident = (int64_t)ncu * std::min(per_cu_upd, 4);
+        p->grid_upd = (int)std::max<int64_t>(1, std::min<int64_t>(resident / p->nch, ntiles));
+    } else {
+        p->grid_upd = p->grid;
+    }
+    if (prec == KM_BF16) {
+        p->mixed = true;
+        p->D16 = (d + 15) / 16;
+        p->DP = 16 * p->D16;
+        p->kpad = (k + kMixCK - 1) / kMixCK * kMixCK;
+        p->IB = 1;
+        while ((1 << p->IB) < p->kpad) ++p->IB;
+        const int occ = mfma_blocks_per_cu(p->D16);
+        if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
+        const int64_t mt = (n + kMixTile - 1) / kMixTile;
+        p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
+        p->grid_rc = ncu * 2;
+    }
 
     size_t off = 0;
     p->off_ctrl = off; off = align256(off + sizeof(Ctrl));
     p->off_cp = off;   off = align256(off + (size_t)k * p->D * sizeof(float));
-    p->off_pS = off;   off = align256(off + (size_t)p->grid * k * d * sizeof(double));
-    p->off_pcnt = off; off = align256(off + (size_t)p->grid * k * sizeof(int32_t));
+    p->off_pS = off;   off = align256(off + (size_t)p->GS() * k * d * sizeof(double));
+    p->off_pcnt = off; off = align256(off + (size_t)p->GS() * k * sizeof(int32_t));
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
-    p->off_pch = off;  off = align256(off + (size_t)p->grid * sizeof(int32_t));
-    p->off_pbad = off; off = align256(off + (size_t)p->grid * sizeof(int32_t));
+    p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, p->grid_mfma + p->grid_rc) * sizeof(int32_t));
+    p->off_pbad = off; off = align256(off + (size_t)std::max(p->grid, p->GS()) * sizeof(int32_t));
     p->off_stS = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(double));
     p->off_stC = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(int32_t));
+    p->off_jt = off;   off = align256(off + (size_t)finalize_blocks(k, d) * sizeof(double));
+    if (p->mixed) {
+        p->off_xs = off;   off = align256(off + sizeof(XStats));
+        p->off_pxm = off;  off = align256(off + kXStatBlocks * sizeof(float));
+        p->off_pxs = off;  off = align256(off + kXStatBlocks * sizeof(double));
+        p->off_ab = off;   off = align256(off + (size_t)p->kpad * p->DP * sizeof(__bf16));
+        p->off_bias = off; off = align256(off + (size_t)p->kpad * sizeof(float));
+        p->off_cs = off;   off = align256(off + sizeof(CStats));
+        p->off_rqc = off;  off = align256(off + sizeof(int32_t));
+        p->off_rq = off;   off = align256(off + (size_t)n * kRqInts * sizeof(int32_t));
+    }
     p->total = off;
     *out = p;
     return KM_OK;
@@ -197,13 +324,19 @@ km_status kmeans_assign(km_plan* plan, const float* X, const float* C, int32_t* 
     if (!aligned16(X) || !aligned16(C)) return fail(KM_EINVAL, "X and C must be 16-byte aligned");
     if ((st = set_device(plan)) != KM_OK) return st;
 
+    if (plan->mixed && (mindist || objective))
+        return fail(KM_ENOTSUP, "BF16 plans return labels only from kmeans_assign (mindist and objective must be NULL)");
     hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, cp_of(plan), nullptr, stream);
     if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
-    PassArgs a{};
-    a.X = X; a.Cp = cp_of(plan); a.labels = labels; a.mindist = mindist;
-    a.part = partials_of(plan); a.ctrl = nullptr;
-    a.n = plan->n; a.d = plan->d; a.k = plan->k; a.iter = 0;
-    e = timed_pass(plan, MODE_ASSIGN, a, 0, stream);
+    if (plan->mixed) {
+        if ((e = enqueue_prep_x(plan, X, stream)) != hipSuccess) return hip_fail(e, "prep_x launch");
+        if ((e = enqueue_mixed_assign(plan, X, labels, nullptr, 0, 0, stream)) != hipSuccess)
+            return hip_fail(e, "mixed assign launch");
+        return KM_OK;
+    }
+    PassArgs a = pass_args(plan, X, cp_of(plan), labels);
+    a.mindist = mindist;
+    e = timed_pass(plan, MODE_ASSIGN, a, dim3(plan->grid), 0, stream);
     if (e != hipSuccess) return hip_fail(e, "assign pass launch");
     if (objective) {
         e = launch_reduce_objective(a.part.J, plan->grid, objective, stream);
@@ -222,18 +355,12 @@ km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, co
     if (!aligned16(X)) return fail(KM_EINVAL, "X must be 16-byte aligned");
     if ((st = set_device(plan)) != KM_OK) return st;
 
-    PassArgs a{};
-    a.X = X; a.Cp = nullptr; a.labels = const_cast<int32_t*>(labels); a.mindist = nullptr;
-    a.part = partials_of(plan); a.ctrl = nullptr;
-    a.n = plan->n; a.d = plan->d; a.k = plan->k; a.iter = 0;
-    hipError_t e = timed_pass(plan, MODE_UPDATE, a, plan->lds_fused, stream);
+    PassArgs a = pass_args(plan, X, nullptr, const_cast<int32_t*>(labels));
+    hipError_t e = enqueue_update(plan, a, stream);
     if (e != hipSuccess) return hip_fail(e, "update pass launch");
-    FinArgs f{};
-    f.stageS = reinterpret_cast<double*>(plan->ws + plan->off_stS);
-    f.stageC = reinterpret_cast<int32_t*>(plan->ws + plan->off_stC);
-    f.part = a.part; f.G = plan->grid; f.k = plan->k; f.d = plan->d; f.D = plan->D;
+    FinArgs f = fin_args(plan);
     f.C_old = C_old; f.ld_old = plan->d; f.C_new = C_new; f.ld_new = plan->d; f.Cp_out = nullptr;
-    f.counts = counts; f.ctrl = nullptr; f.obj_hist = nullptr; f.iter = 0; f.tol = -1.0; f.want_J = 0;
+    f.counts = counts; f.want_J = 0;
     e = launch_finalize(f, stream);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     return KM_OK;
@@ -256,21 +383,30 @@ km_status kmeans_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels,
     hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, Cp, ctrl, stream);
     if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
 
-    PassArgs a{};
-    a.X = X; a.Cp = Cp; a.labels = labels; a.mindist = nullptr;
-    a.part = partials_of(plan); a.ctrl = (tol >= 0.0) ? ctrl : nullptr;
-    a.n = plan->n; a.d = plan->d; a.k = plan->k;
-    FinArgs f{};
-    f.stageS = reinterpret_cast<double*>(plan->ws + plan->off_stS);
-    f.stageC = reinterpret_cast<int32_t*>(plan->ws + plan->off_stC);
-    f.part = a.part; f.G = plan->grid; f.k = plan->k; f.d = plan->d; f.D = plan->D;
+    PassArgs a = pass_args(plan, X, Cp, labels);
+    a.ctrl = (tol >= 0.0) ? ctrl : nullptr;
+    a.count_changed = 1;
+    FinArgs f = fin_args(plan);
     f.C_old = Cp; f.ld_old = plan->D; f.C_new = C; f.ld_new = plan->d; f.Cp_out = Cp;
     f.counts = counts; f.ctrl = ctrl; f.obj_hist = obj_hist; f.tol = tol; f.want_J = 1;
+    if (plan->mixed && (e = enqueue_prep_x(plan, X, stream)) != hipSuccess) return hip_fail(e, "prep_x launch");
     for (int32_t t = 0; t < max_iter; ++t) {
         a.iter = t;
         f.iter = t;
-        e = timed_pass(plan, MODE_FUSED, a, plan->lds_fused, stream);
-        if (e != hipSuccess) return hip_fail(e, "fused pass launch");
+        if (plan->mixed) {
+            e = enqueue_mixed_assign(plan, X, labels, a.ctrl, t, 1, stream);
+            if (e != hipSuccess) return hip_fail(e, "mixed assign launch");
+            e = enqueue_update(plan, a, stream);
+            if (e != hipSuccess) return hip_fail(e, "update pass launch");
+        } else if (!plan->split) {
+            e = timed_pass(plan, MODE_FUSED, a, dim3(plan->grid), plan->lds_fused, stream);
+            if (e != hipSuccess) return hip_fail(e, "fused pass launch");
+        } else {
+            e = timed_pass(plan, MODE_ASSIGN, a, dim3(plan->grid), 0, stream);
+            if (e != hipSuccess) return hip_fail(e, "assign pass launch");
+            e = enqueue_update(plan, a, stream);
+            if (e != hipSuccess) return hip_fail(e, "update pass launch");
+        }
         e = launch_finalize(f, stream);
         if (e != hipSuccess) return hip_fail(e, "finalize launch");
     }

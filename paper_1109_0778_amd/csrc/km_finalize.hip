@@ -54,57 +54,73 @@ __global__ __launch_bounds__(256) void finalize_partial_kernel(FinArgs a)
 }
 
 // Stage 2: the kFinSplit stage sums of each element in split order, then the
-// mean with the empty-cluster rule.  Block 0's second wave reduces the
-// objective and the changed count and drives the control block.
-__global__ __launch_bounds__(128) void finalize_combine_kernel(FinArgs a)
+// mean with the empty-cluster rule.  With jmode 1 each block also writes its
+// share of sum_j (cnt_j |c_j|^2 - 2 c_j . S_j) (xor tree over its 64 elements).
+__global__ __launch_bounds__(64) void finalize_combine_kernel(FinArgs a)
 {
     if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
 
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     const int64_t kd = (int64_t)a.k * a.d;
-    if (wave == 0) {
-        const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-        if (e < kd) {
-            const int j = (int)(e / a.d);
-            const int f = (int)(e - (int64_t)j * a.d);
-            double S = a.stageS[e];
-            int64_t c = a.stageC[e];
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    double term = 0.0;
+    if (e < kd) {
+        const int j = (int)(e / a.d);
+        const int f = (int)(e - (int64_t)j * a.d);
+        double S = a.stageS[e];
+        int64_t c = a.stageC[e];
 #pragma unroll
-            for (int s = 1; s < kFinSplit; ++s) {
-                S += a.stageS[(size_t)s * kd + e];
-                c += a.stageC[(size_t)s * kd + e];
-            }
-            float v;
-            if (c > 0) v = (float)(S / (double)c);
-            else v = a.C_old[(size_t)j * a.ld_old + f];
-            a.C_new[(size_t)j * a.ld_new + f] = v;
-            if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
-            if (a.counts && f == 0) a.counts[j] = c;
+        for (int s = 1; s < kFinSplit; ++s) {
+            S += a.stageS[(size_t)s * kd + e];
+            c += a.stageC[(size_t)s * kd + e];
         }
-    } else if (blockIdx.x == 0 && a.want_J) {
-        // objective and changed count: lane-strided slots, then xor tree
-        double J = 0.0;
-        int64_t ch = 0;
-        for (int b = lane; b < a.G; b += 64) { J += a.part.J[b]; ch += a.part.changed[b]; }
+        const float old = a.C_old[(size_t)j * a.ld_old + f];
+        const float v = (c > 0) ? (float)(S / (double)c) : old;
+        a.C_new[(size_t)j * a.ld_new + f] = v;
+        if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
+        if (a.counts && f == 0) a.counts[j] = c;
+        const double co = (double)old;
+        term = (double)c * co * co - 2.0 * co * S;
+    }
+    if (a.jmode == 1) {
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            J += __shfl_xor(J, off);
-            ch += __shfl_xor(ch, off);
-        }
-        if (lane == 0) {
-            const int t = a.iter;
-            if (a.obj_hist) a.obj_hist[t] = J;
-            if (a.ctrl) {
-                Ctrl* c = a.ctrl;
-                if (a.tol >= 0.0 && t >= 1) {
-                    const double Jp = c->J_prev;
-                    if ((Jp - J) <= a.tol * Jp || ch == 0) c->stop_iter = t;
-                }
-                c->J_prev = J;
-                c->changed_last = ch;
-                c->iters_done = t + 1;
+        for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
+        if (lane == 0) a.Jterm[blockIdx.x] = term;
+    }
+}
+
+// Objective, changed count and the tolerance decision (one wave).
+__global__ __launch_bounds__(64) void finalize_objective_kernel(FinArgs a)
+{
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
+    const int lane = threadIdx.x;
+    double J = 0.0;
+    int64_t ch = 0;
+    if (a.jmode == 0) {
+        for (int b = lane; b < a.GJ; b += 64) J += a.part.J[b];
+    } else {
+        const int nb = finalize_blocks(a.k, a.d);
+        for (int b = lane; b < nb; b += 64) J += a.Jterm[b];
+    }
+    for (int b = lane; b < a.GC; b += 64) ch += a.part.changed[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        J += __shfl_xor(J, off);
+        ch += __shfl_xor(ch, off);
+    }
+    if (lane == 0) {
+        if (a.jmode == 1) J = *a.sum_xn2 + J;
+        const int t = a.iter;
+        if (a.obj_hist) a.obj_hist[t] = J;
+        if (a.ctrl) {
+            Ctrl* c = a.ctrl;
+            if (a.tol >= 0.0 && t >= 1) {
+                const double Jp = c->J_prev;
+                if ((Jp - J) <= a.tol * Jp || ch == 0) c->stop_iter = t;
             }
+            c->J_prev = J;
+            c->changed_last = ch;
+            c->iters_done = t + 1;
         }
     }
 }
@@ -148,13 +164,17 @@ __global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __rest
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s)
 {
-    const int64_t kd = (int64_t)a.k * a.d;
-    const int grid = (int)((kd + 63) / 64);
+    const int grid = finalize_blocks(a.k, a.d);
     hipLaunchKernelGGL(finalize_partial_kernel, dim3(grid, kFinSplit), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_combine_kernel, dim3(grid), dim3(128), 0, s, a);
-    return hipGetLastError();
+    hipLaunchKernelGGL(finalize_combine_kernel, dim3(grid), dim3(64), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.want_J) {
+        hipLaunchKernelGGL(finalize_objective_kernel, dim3(1), dim3(64), 0, s, a);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_pad_centroids(const float* C, int32_t k, int32_t d, int32_t D, float* Cp, Ctrl* ctrl,

@@ -45,18 +45,21 @@ struct PassArgs {
     int32_t* labels;      // [n]
     float* mindist;       // [n] or nullptr
     Partials part;
-    const Ctrl* ctrl;     // nullptr outside kmeans_lloyd
+    const Ctrl* ctrl;     // early-exit control (tolerance mode), or nullptr
     int64_t n;
     int32_t d;
     int32_t k;
     int32_t iter;         // Lloyd iteration index (0 outside kmeans_lloyd)
+    int32_t count_changed;// assign passes: count labels that differ from the stored ones
+    int32_t kc;           // update passes: labels per chunk; block y owns labels [y*kc, y*kc+kc)
 };
 
 struct FinArgs {
     Partials part;
     double* stageS;       // [kFinSplit][k*d] first-stage sums
     int32_t* stageC;      // [kFinSplit][k*d] first-stage counts (per element)
-    int32_t G;            // number of partial slots
+    int32_t G;            // number of per-label partial slots (sums, counts)
+    int32_t GJ;           // number of objective / changed partial slots
     int32_t k, d, D;
     const float* C_old; int32_t ld_old;   // centroids kept for empty clusters
     float* C_new;       int32_t ld_new;   // output centroids
@@ -67,14 +70,23 @@ struct FinArgs {
     int32_t iter;
     double tol;                           // < 0: fixed iteration count
     int32_t want_J;                       // reduce J / changed / control
+    // objective: jmode 0 sums the per-sample partials part.J[0..GJ);
+    // jmode 1 uses J = sum_i |x_i|^2 + sum_j (cnt_j |c_j|^2 - 2 c_j . S_j)
+    // (exact algebra on the reduce's own FP64 sums), with *sum_xn2 the first
+    // term and Jterm[] the per-block second term.
+    int32_t jmode;
+    double* Jterm;                        // [ceil(k*d/64)] (jmode 1)
+    const double* sum_xn2;                // (jmode 1)
+    int32_t GC;                           // changed partial slots in part.changed
 };
 
 // Launchers (return the launch status).
 hipError_t launch_pad_centroids(const float* C, int32_t k, int32_t d, int32_t D, float* Cp,
                                 Ctrl* ctrl_reset, hipStream_t s);
-hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, int grid, size_t lds_bytes,
+hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, dim3 grid, size_t lds_bytes,
                              hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+__host__ __device__ inline int finalize_blocks(int k, int d) { return (int)(((int64_t)k * d + 63) / 64); }
 // Resident blocks per CU of the plain pass (HIP occupancy query), -1 on error.
 int plain_blocks_per_cu(int D8, Mode mode, size_t lds_bytes);
 hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s);
@@ -98,5 +110,69 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
     }
     return b;
 }
+
+// ---------------------------------------------------------------- mixed path
+// BF16 MFMA distances with a proven error band and an exact FP32 recheck.
+constexpr int kMixWaves = 4;                    // waves per block
+constexpr int kMixNB = 2;                       // 32-sample column blocks per wave
+constexpr int kMixTile = kMixWaves * kMixNB * 32;
+constexpr int kMixCK = 64;                      // centroids per LDS chunk
+constexpr int kCandCap = 7;                     // candidate slots per lane (half a sample's rows)
+constexpr int kRqInts = 16;                     // ints per recheck entry: sample, count, 14 ids
+constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
+constexpr int kXStatBlocks = 256;
+
+struct XStats {                 // once per run, over all samples
+    float max_xn2;              // max_i |x_i|^2 (FP32)
+    float K;                    // distance offset 2 max_i |x_i|^2 + 1 (keeps keys positive)
+    double sum_xn2;             // sum_i |x_i|^2 (FP64)
+};
+struct CStats {                 // per iteration, over the centroids
+    float K, cmax, cn2max, pad;
+};
+
+struct MixArgs {
+    const float* X;
+    int64_t n;
+    int32_t d, k, kpad;
+    const __bf16* Ab;           // [kpad][16*D16] bf16(-2 c), zero padded
+    const float* bias;          // [kpad] K + |c_j|^2, padded rows huge
+    const CStats* cs;
+    float u;                    // unit roundoff of the quantised format
+    int32_t IB;                 // index bits in a key
+    int32_t gamma_terms;        // m of the gamma_m accumulation bound
+    int32_t D8;                 // chunks of the canonical FP32 distance
+    int32_t* labels;
+    int32_t* rq;                // [n][kRqInts] recheck entries
+    int32_t* rq_count;
+    int32_t* changed_part;      // [grid]
+    const Ctrl* ctrl;
+    int32_t iter;
+    int32_t count_changed;
+};
+
+struct RecheckArgs {
+    const float* X;
+    const float* Cp;            // [k][8*D8] FP32 centroids (zero padded)
+    int64_t n;
+    int32_t d, k;
+    const int32_t* rq;
+    const int32_t* rq_count;
+    int32_t* labels;
+    int32_t* changed_part;      // [grid]
+    const Ctrl* ctrl;
+    int32_t iter;
+    int32_t count_changed;
+};
+
+hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, double* part_sum,
+                         XStats* xs, hipStream_t s);
+hipError_t launch_prep_c(const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
+                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, int32_t* rq_count,
+                         const Ctrl* ctrl, int32_t iter, hipStream_t s);
+hipError_t launch_mfma_assign(int D16, const MixArgs& a, int grid, hipStream_t s);
+size_t mfma_lds_bytes(int D16);
+int mfma_blocks_per_cu(int D16);
+hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
 
 }  // namespace km

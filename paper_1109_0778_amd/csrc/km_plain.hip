@@ -13,7 +13,7 @@
 //   * each lane holds its sample row in VGPRs (zero-padded to D = 8 * D8);
 //     centroid rows are wave-uniform, so they are read with scalar loads and
 //     enter the VALU as SGPR operands: no LDS traffic and no VGPRs for C;
-//   * distances are the canonical direct form (see dist_canonical below);
+//   * distances are the canonical direct form (dist_rows in km_dist.h);
 //   * the block's activation record -- FP64 per-label sums S[k][d] and counts
 //     -- is private to the block in LDS ("alloc" zeroes it, "process" adds a
 //     sample, and it is merged once per block into a fixed partial slot);
@@ -21,62 +21,11 @@
 //     samples in tile order with LDS atomics that it alone issues, so the
 //     order of every FP64 sum is fixed and results are bit-reproducible.
 #include "km_internal.h"
+#include "km_dist.h"
 
 #include <climits>
 
 namespace km {
-
-// Canonical FP32 squared distance: diff = fl(x - c); features in chunks of 8
-// accumulated with fused multiply-add starting from 0; chunk partials summed
-// by the pairwise tree (p += p + s for s = 1, 2, 4, ...).  Zero padding adds
-// exact zeros and does not change the value.  Error <= (2 + 8 + ceil(log2 P))
-// units of 2^-24 of the exact distance (P = number of chunks).
-// Centroids are read through the constant address space: every lane of a
-// wave reads the same row, so the loads become scalar (SMEM) loads and the
-// values enter the VALU as SGPR operands.
-typedef __attribute__((address_space(4))) const float cfloat;
-
-template <int D8>
-__device__ __forceinline__ float dist_canonical(const float (&x)[8 * D8], cfloat* __restrict__ c)
-{
-    float part[D8];
-#pragma unroll
-    for (int p = 0; p < D8; ++p) {
-        float a = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float df = x[8 * p + q] - c[8 * p + q];
-            a = __builtin_fmaf(df, df, a);
-        }
-        part[p] = a;
-    }
-#pragma unroll
-    for (int s = 1; s < D8; s *= 2) {
-#pragma unroll
-        for (int p = 0; p + s < D8; p += 2 * s) part[p] = part[p] + part[p + s];
-    }
-    return part[0];
-}
-
-template <int D8>
-__device__ __forceinline__ void load_row(const float* __restrict__ row, int d, bool valid, float (&x)[8 * D8])
-{
-    constexpr int D = 8 * D8;
-    if (valid && (d & 3) == 0) {
-#pragma unroll
-        for (int q = 0; q < D / 4; ++q) {
-            if (4 * q < d) {
-                const float4 v = *reinterpret_cast<const float4*>(row + 4 * q);
-                x[4 * q + 0] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
-            } else {
-                x[4 * q + 0] = 0.f; x[4 * q + 1] = 0.f; x[4 * q + 2] = 0.f; x[4 * q + 3] = 0.f;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int f = 0; f < D; ++f) x[f] = (valid && f < d) ? row[f] : 0.0f;
-    }
-}
 
 __device__ __forceinline__ void lds_add_f64(double* p, double v)
 {
@@ -130,37 +79,6 @@ __device__ __forceinline__ void accumulate_group(const float* __restrict__ Xg, i
     }
 }
 
-// R distances against one centroid row; the row's values are shared by the R
-// samples a lane holds.
-template <int D8, int R, typename CP>
-__device__ __forceinline__ void dist_rows(const float (&x)[R][8 * D8], CP c, float (&out)[R])
-{
-    float part[R][D8];
-#pragma unroll
-    for (int p = 0; p < D8; ++p) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) part[r][p] = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float cv = c[8 * p + q];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const float df = x[r][8 * p + q] - cv;
-                part[r][p] = __builtin_fmaf(df, df, part[r][p]);
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-        for (int s = 1; s < D8; s *= 2) {
-#pragma unroll
-            for (int p = 0; p + s < D8; p += 2 * s) part[r][p] = part[r][p] + part[r][p + s];
-        }
-        out[r] = part[r][0];
-    }
-}
-
 // Nearest centroid of each of the R rows a lane holds, over all k centroids,
 // with the canonical distance.  Ties keep the lower index.
 template <int D8, int R, typename CP>
@@ -195,15 +113,18 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
     const int wave = tid >> 6;
     const int k = a.k, d = a.d;
     const int64_t n = a.n;
+    // Label chunk of this block (update / fused passes): labels [j0, j0 + kc).
+    const int j0 = (MODE == MODE_UPDATE) ? (int)blockIdx.y * a.kc : 0;
+    const int kc = (MODE == MODE_UPDATE) ? min(a.kc, k - j0) : k;
 
     double* S = reinterpret_cast<double*>(smem);
-    int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)k * d);
-    int32_t* lbl = cnt + (((size_t)k + 3) & ~(size_t)3);
+    int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
+    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);
 
     // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
-        for (int e = tid; e < k * d; e += kBlock) S[e] = 0.0;
-        for (int j = tid; j < k; j += kBlock) cnt[j] = 0;
+        for (int e = tid; e < kc * d; e += kBlock) S[e] = 0.0;
+        for (int j = tid; j < kc; j += kBlock) cnt[j] = 0;
     }
     __syncthreads();
 
@@ -220,8 +141,9 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
                 const int64_t gp = t * TILE + r * kBlock + tid;
                 lab[r] = -1;
                 if (gp < n) {
-                    lab[r] = a.labels[gp];
-                    if (lab[r] < 0 || lab[r] >= k) { ++bad; lab[r] = -1; }
+                    const int L = a.labels[gp];
+                    if (L < 0 || L >= k) ++bad;
+                    else if (L >= j0 && L < j0 + kc) lab[r] = L - j0;   // chunk-local label
                 }
             }
         } else {
@@ -240,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
                 const int64_t gp = t * TILE + r * kBlock + tid;
                 lab[r] = -1;
                 if (gp < n) {
-                    if (MODE == MODE_FUSED) changed += (a.iter == 0) ? 1 : (a.labels[gp] != bj[r]);
+                    if (a.count_changed) changed += (a.iter == 0) ? 1 : (a.labels[gp] != bj[r]);
                     a.labels[gp] = bj[r];
                     if (a.mindist) a.mindist[gp] = best[r];
                     Jl += (double)best[r];
@@ -265,14 +187,15 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
         }
     }
 
-    // Merge once per block: the activation record goes to this block's slot.
+    // Merge once per block: the activation record goes to slot blockIdx.x,
+    // labels [j0, j0 + kc) of it.
     __syncthreads();
     const int b = blockIdx.x;
     if (MODE != MODE_ASSIGN) {
-        double* dst = a.part.S + (size_t)b * k * d;
-        for (int e = tid; e < k * d; e += kBlock) dst[e] = S[e];
-        int32_t* dc = a.part.cnt + (size_t)b * k;
-        for (int j = tid; j < k; j += kBlock) dc[j] = cnt[j];
+        double* dst = a.part.S + (size_t)b * k * d + (size_t)j0 * d;
+        for (int e = tid; e < kc * d; e += kBlock) dst[e] = S[e];
+        int32_t* dc = a.part.cnt + (size_t)b * k + j0;
+        for (int j = tid; j < kc; j += kBlock) dc[j] = cnt[j];
     }
     // Fixed-order reductions of the scalar partials: xor tree inside the
     // wave (lane 0's value), then waves in index order.
@@ -288,9 +211,11 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
         double J = redJ[0];
         int32_t c = redC[0], bb = redB[0];
         for (int w = 1; w < kWaves; ++w) { J += redJ[w]; c += redC[w]; bb += redB[w]; }
-        a.part.J[b] = J;
-        a.part.changed[b] = c;
-        a.part.bad[b] = bb;
+        if (MODE != MODE_UPDATE) {
+            a.part.J[b] = J;
+            a.part.changed[b] = c;
+        }
+        if (blockIdx.y == 0) a.part.bad[b] = bb;
     }
 }
 
@@ -304,7 +229,7 @@ static hipError_t allow_lds(size_t lds)
 }
 
 template <int D8>
-static hipError_t launch_d8(Mode mode, const PassArgs& a, int grid, size_t lds, hipStream_t s)
+static hipError_t launch_d8(Mode mode, const PassArgs& a, dim3 grid, size_t lds, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     switch (mode) {
@@ -314,9 +239,9 @@ static hipError_t launch_d8(Mode mode, const PassArgs& a, int grid, size_t lds, 
     }
     if (e != hipSuccess) return e;
     switch (mode) {
-    case MODE_ASSIGN: hipLaunchKernelGGL((plain_pass<D8, MODE_ASSIGN>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case MODE_UPDATE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE>), dim3(grid), dim3(kBlock), lds, s, a); break;
-    case MODE_FUSED:  hipLaunchKernelGGL((plain_pass<D8, MODE_FUSED>), dim3(grid), dim3(kBlock), lds, s, a); break;
+    case MODE_ASSIGN: hipLaunchKernelGGL((plain_pass<D8, MODE_ASSIGN>), grid, dim3(kBlock), lds, s, a); break;
+    case MODE_UPDATE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE>), grid, dim3(kBlock), lds, s, a); break;
+    case MODE_FUSED:  hipLaunchKernelGGL((plain_pass<D8, MODE_FUSED>), grid, dim3(kBlock), lds, s, a); break;
     }
     return hipGetLastError();
 }
@@ -345,7 +270,7 @@ int plain_blocks_per_cu(int D8, Mode mode, size_t lds)
     }
 }
 
-hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, int grid, size_t lds, hipStream_t s)
+hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, dim3 grid, size_t lds, hipStream_t s)
 {
     switch (D8) {
     case 1: return launch_d8<1>(mode, a, grid, lds, s);

@@ -70,6 +70,13 @@ def test_plan_create_rejects_unknown_precision(L):
     assert st == binding.KM_EINVAL and not h.value
 
 
+@pytest.mark.parametrize("n,d,k,prec", [(100, 200, 3, 0), (100, 129, 3, 1), (100, 4, 3, 2)])
+def test_plan_create_reports_unsupported(L, n, d, k, prec):
+    st, h = _create(L, n, d, k, prec)
+    assert st == binding.KM_ENOTSUP and not h.value
+    assert L.km_last_error().decode()
+
+
 def test_null_handles(L):
     assert L.km_plan_workspace_bytes(None) == 0
     L.km_plan_destroy(None)

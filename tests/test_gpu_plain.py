@@ -113,6 +113,8 @@ def run_lloyd(torch, B, X, C0, iters, tol=-1.0, plan=None):
 SHAPES = [  # (n, d, k): several tiles, ragged tails, odd d, d not a multiple of 8
     (3000, 8, 8), (5000, 3, 5), (4099, 17, 13), (2500, 64, 64), (1200, 128, 9),
     (257, 33, 40), (700, 1, 4), (20000, 24, 100), (999, 96, 3), (64, 5, 64),
+    # per-label record beyond one block's LDS: assign + label-chunked update
+    (20000, 128, 200), (9001, 96, 150), (5000, 24, 600),
 ]
 
 
@@ -165,7 +167,8 @@ def test_small_workload_end_to_end():
     np.testing.assert_allclose(g["J"], o["J"], rtol=REL_TOL)
 
 
-@pytest.mark.parametrize("n,d,k,iters", [(20000, 16, 20, 6), (6001, 64, 64, 4), (3001, 7, 11, 5)])
+@pytest.mark.parametrize("n,d,k,iters", [(20000, 16, 20, 6), (6001, 64, 64, 4), (3001, 7, 11, 5),
+                                          (12000, 128, 180, 3)])
 def test_lloyd_stepwise(n, d, k, iters):
     """Each iteration of the GPU run checked against the oracle fed with the
     GPU's own iterate; the fused pass equals assign-then-update bit for bit."""
