@@ -11,11 +11,18 @@ centroids sampled without replacement, 20 iterations, FP32 distances.
 
 Prints ONE JSON line on stdout (diagnostics go to stderr).  Besides the timed
 throughput it carries:
-  roofline      the per-sample pass (dominant kernel): algorithmic VALU work
-                per launch / its mean duration from HIP events recorded on the
-                launch stream during the timed region;
-  cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample
-                of the same workload.
+  roofline       the per-sample pass (dominant kernel): algorithmic VALU work
+                 per launch / its mean duration from HIP events recorded on the
+                 launch stream during the timed region;
+  mixed_bf16     the same workload through the BF16-MFMA path (labels and
+                 centroids compared bit for bit with the FP32 run), with its
+                 MFMA pass on the MFMA or HBM roofline;
+  bf16_workload  FP32 and BF16 on n = 2^22, d = 128, k = 1024 (1024 blobs,
+                 sigma 2, seed 2, 20 iterations);
+  batched_workload  512 independent instances advanced together (autotuned
+                 schedule, one graph launch), next to per-instance calls;
+  cpu_baseline   the FP64 oracle timed on this host's cores on a bounded sample
+                 of the headline workload.
 """
 from __future__ import annotations
 
@@ -59,6 +66,144 @@ def measured_traffic(n_launch_units):
     return t.get("bytes_per_launch")
 
 
+def timed_lloyd(B, torch, X, C0, precision, steps, warmup):
+    """One timed kmeans_lloyd call of `steps` iterations from C0 (inputs
+    resident), after `warmup` untimed iterations; HIP-event durations of the
+    dominant kernel over the timed call."""
+    import numpy as np
+    n, d = X.shape
+    k = C0.shape[0]
+    dev = torch.device("cuda", 0)
+    Xg = torch.from_numpy(X).to(dev)
+    C0g = torch.from_numpy(C0).to(dev)
+    plan = B.Plan(n, d, k, precision)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    counts = torch.empty(k, dtype=torch.int64, device=dev)
+    hist = torch.empty(max(steps, warmup, 1), dtype=torch.float64, device=dev)
+    if warmup > 0:
+        Cw = C0g.clone()
+        B.kmeans_lloyd(plan, Xg, Cw, labels, counts, hist, warmup, -1.0)
+        torch.cuda.synchronize()
+    C = C0g.clone()
+    plan.enable_timing(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = plan.kernel_times(steps)
+    plan.enable_timing(0)
+    res = {"el": el, "kt": kt, "C": C.cpu().numpy(), "labels": labels.cpu().numpy(),
+           "J": hist[:steps].cpu().numpy()}
+    if precision != "fp32":
+        res["recheck"], res["full_scans"] = plan.recheck_count()
+    del plan, Xg
+    torch.cuda.empty_cache()
+    return res
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mixed_report(B, torch, w, X, C0, steps, warmup, fp):
+    """BF16-MFMA path on the same input: throughput, equality of its labels
+    and centroids with the FP32 run, recheck fraction, and the MFMA pass on
+    its roofline (MFMA or HBM, whichever the shape is bound by)."""
+    import numpy as np
+    mx = timed_lloyd(B, torch, X, C0, "bf16", steps, warmup)
+    kmean_ms = float(np.mean(mx["kt"]))
+    flops = 2.0 * w.n * w.k * w.d
+    nbytes = w.n * w.d * 4 + 2 * w.n * 4
+    tflops = flops / (kmean_ms * 1e-3) / 1e12
+    gbps = nbytes / (kmean_ms * 1e-3) / 1e9
+    ai = flops / nbytes
+    bound = "mfma" if ai > MFMA_BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBPS * 1e9) else "hbm"
+    if bound == "mfma":
+        roof = {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / MFMA_BF16_PEAK_TFLOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": gbps / HBM_PEAK_GBPS}
+    roof.update({"kernel": "mfma_assign_bf16 (BF16 MFMA distances, key min, candidate band)",
+                 "traffic": None, "flops_per_launch": flops, "bytes_per_launch": nbytes,
+                 "mean_launch_ms": kmean_ms, "launches": len(mx["kt"]),
+                 "mfma_tflops": tflops, "hbm_gbps": gbps})
+    same_labels = bool(np.array_equal(mx["labels"], fp["labels"]))
+    same_c = bool(np.array_equal(mx["C"], fp["C"]))
+    log(f"bf16 on {w.name}: {steps} iterations in {mx['el'] * 1e3:.2f} ms (fp32 {fp['el'] * 1e3:.2f} ms); "
+        f"MFMA pass {kmean_ms * 1e3:.1f} us; labels equal {same_labels}, centroids equal {same_c}; "
+        f"recheck {mx['recheck']} of {w.n} ({mx['full_scans']} full scans)")
+    return {"value": steps / mx["el"], "unit": "Lloyd iters/s", "ms_per_step": mx["el"] * 1e3 / steps,
+            "fp32_value": steps / fp["el"], "speedup_vs_fp32": fp["el"] / mx["el"],
+            "dist_evals_per_s": w.n * w.k * steps / mx["el"],
+            "labels_equal_fp32": same_labels, "centroids_equal_fp32": same_c,
+            "objective_rel_diff_vs_fp32": float(np.max(np.abs(mx["J"] - fp["J"]) / fp["J"])),
+            "recheck_fraction_last_iter": mx["recheck"] / w.n,
+            "full_scan_fraction_last_iter": mx["full_scans"] / w.n, "roofline": roof}
+
+
+def batched_report(B, torch, iters, per_instance_sample=32):
+    """The 512-instance workload: autotuned schedule, one graph launch for all
+    iterations of all instances, timed; next to it the same instances through
+    single-instance kmeans_lloyd calls (a sample, extrapolated)."""
+    import numpy as np
+    from paper_1109_0778_amd import autotune, datagen
+    dev = torch.device("cuda", 0)
+    inst, shapes = [], []
+    for s_ in range(datagen.BATCH_COUNT):
+        shp, X, C = datagen.batch_instance(s_)
+        shapes.append(shp)
+        inst.append({"X": torch.from_numpy(X).to(dev), "C": torch.from_numpy(C).to(dev),
+                     "labels": torch.empty(shp.n, dtype=torch.int32, device=dev),
+                     "counts": torch.empty(shp.k, dtype=torch.int64, device=dev),
+                     "obj_hist": torch.zeros(iters, dtype=torch.float64, device=dev)})
+    C0 = [t["C"].clone() for t in inst]
+    batch = B.Batch(inst)
+    choice, tune_ms = autotune.tune_batch(batch, use_cache=False)
+    batch.use_graphs(True)
+    B.kmeans_lloyd_batched(batch, iters)            # capture + warm-up
+    torch.cuda.synchronize()
+    for t, c in zip(inst, C0):
+        t["C"].copy_(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.kmeans_lloyd_batched(batch, iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = sum(s_.n for s_ in shapes)
+    evals = sum(s_.n * s_.k for s_ in shapes)
+    nbytes = sum(s_.n * s_.d * 4 + 8 * s_.n for s_ in shapes)
+    # per-instance launches on a sample of instances (same iterations)
+    idx = np.random.default_rng(0).choice(len(inst), per_instance_sample, replace=False)
+    el_single = 0.0
+    for i in idx:
+        t = inst[i]
+        n, d = t["X"].shape
+        k = t["C"].shape[0]
+        plan = B.Plan(n, d, k)
+        C = C0[i].clone()
+        B.kmeans_lloyd(plan, t["X"], C, t["labels"], None, None, 1)
+        torch.cuda.synchronize()
+        C = C0[i].clone()
+        t1 = time.perf_counter()
+        B.kmeans_lloyd(plan, t["X"], C, t["labels"], None, None, iters)
+        torch.cuda.synchronize()
+        el_single += time.perf_counter() - t1
+    el_single *= len(inst) / per_instance_sample
+    log(f"batched: {len(inst)} instances x {iters} iterations in {el * 1e3:.1f} ms "
+        f"(per-instance launches, extrapolated: {el_single * 1e3:.1f} ms); schedule {choice}")
+    return {"workload": f"batched: {len(inst)} instances, n log-uniform [1e3, 2e5] (total {pts}), d in {{16,32,64}}, "
+                        f"k uniform [4,128], blobs = k, sigma 1, seeds 0..{len(inst) - 1}, {iters} iterations",
+            "value": len(inst) * iters / el, "unit": "instance-iterations/s",
+            "ms_per_round": el * 1e3 / iters,
+            "dist_evals_per_s": evals * iters / el,
+            "hbm_gbps_algorithmic": nbytes * iters / el / 1e9,
+            "per_instance_launches_value": len(inst) * iters / el_single,
+            "speedup_vs_per_instance_launches": el_single / el,
+            "schedule": {"tiles_per_block": choice[0], "order": choice[1], "candidates_ms": tune_ms},
+            "precision": "fp32", "graph": True}
+
+
 def cpu_baseline(X, C0, iters, budget_s):
     import numpy as np
     import oracle
@@ -97,8 +242,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed Lloyd iterations (default: workload's 20)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain", choices=["plain", "small"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "small", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-MFMA comparison")
+    ap.add_argument("--no-bf16-workload", action="store_true",
+                    help="skip the n=2^22, d=128, k=1024 mixed-precision workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (PMC calibration)")
@@ -125,36 +274,14 @@ def main():
     steps = args.steps if args.steps is not None else w.iters
     log(f"workload {w.name}: n={w.n} d={w.d} k={w.k}, {steps} timed iterations, {args.warmup} warmup")
     X, C0 = datagen.workload(w.name)
-    dev = torch.device("cuda", 0)
-    Xg = torch.from_numpy(X).to(dev)
-    C0g = torch.from_numpy(C0).to(dev)
-    plan = B.Plan(w.n, w.d, w.k, "fp32")
-    labels = torch.empty(w.n, dtype=torch.int32, device=dev)
-    counts = torch.empty(w.k, dtype=torch.int64, device=dev)
-    hist = torch.empty(max(steps, args.warmup, 1), dtype=torch.float64, device=dev)
-
-    if args.warmup > 0:
-        Cw = C0g.clone()
-        B.kmeans_lloyd(plan, Xg, Cw, labels, counts, hist, args.warmup, -1.0)
-        torch.cuda.synchronize()
-
-    C = C0g.clone()
-    plan.enable_timing(steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kt = plan.kernel_times(steps)
-    plan.enable_timing(0)
-
-    J = hist[:steps].cpu().numpy()
+    fp = timed_lloyd(B, torch, X, C0, "fp32", steps, args.warmup)
+    el, kt, J = fp["el"], fp["kt"], fp["J"]
     kmean_ms = float(np.mean(kt)) if kt else float("nan")
     ops = 2.0 * w.n * w.k * w.d                # one subtract + one FMA per (sample, centroid, feature)
     achieved = ops / (kmean_ms * 1e-3) / 1e12
     algo_bytes = w.n * w.d * 4 + 2 * w.n * 4   # X once, labels read + written
     traffic = measured_traffic(f"{w.name}:{w.n}x{w.d}x{w.k}")
-    log(f"timed {steps} iterations in {el * 1e3:.2f} ms; per-sample pass mean {kmean_ms * 1e3:.1f} us "
+    log(f"fp32: {steps} iterations in {el * 1e3:.2f} ms; per-sample pass mean {kmean_ms * 1e3:.1f} us "
         f"over {len(kt)} launches; J[0]={J[0]:.6e} J[-1]={J[-1]:.6e}")
 
     out = {
@@ -191,6 +318,21 @@ def main():
         },
         "objective_first_last": [float(J[0]), float(J[-1])],
     }
+    if not args.no_mixed:
+        out["mixed_bf16"] = mixed_report(B, torch, w, X, C0, steps, args.warmup, fp)
+        if args.workload == "plain" and not args.no_bf16_workload:
+            wb = datagen.WORKLOADS["bf16"]
+            log(f"bf16 workload: n={wb.n} d={wb.d} k={wb.k}")
+            Xb, Cb = datagen.workload("bf16")
+            fpb = timed_lloyd(B, torch, Xb, Cb, "fp32", wb.iters, 1)
+            rep = mixed_report(B, torch, wb, Xb, Cb, wb.iters, 1, fpb)
+            rep["workload"] = (f"bf16: n={wb.n}, d={wb.d}, k={wb.k}, {wb.blobs} blobs sigma={wb.sigma}, "
+                               f"seed {wb.seed}, {wb.iters} iterations")
+            out["bf16_workload"] = rep
+            del Xb, Cb
+    if not args.no_batched and args.workload == "plain":
+        from paper_1109_0778_amd import datagen as dg
+        out["batched_workload"] = batched_report(B, torch, dg.BATCH_ITERS)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(X, C0, w.iters, args.cpu_seconds)

@@ -143,6 +143,61 @@ km_status kmeans_lloyd(km_plan *plan, const float *X, float *C, int32_t *labels,
                        double tol, int32_t *iters_done, hipStream_t stream);
 
 /*
+ * Batched Lloyd: many independent k-means problems of different n, d and k
+ * advanced together, every iteration of all of them in one launch of the
+ * per-sample pass per shape class plus one finalize launch (and, with graphs
+ * enabled, one graph launch for the whole call).  Each instance is the same
+ * computation as kmeans_lloyd with a fixed iteration count.
+ */
+typedef struct {
+    const float *X;     /* [n x d] FP32 samples (device, 16-byte aligned)       */
+    float *C;           /* [k x d] FP32 in: C_0, out: C_T (device, aligned)     */
+    int32_t *labels;    /* [n] int32 out: L_{T-1} (device)                      */
+    int64_t *counts;    /* [k] int64 out: counts of L_{T-1}, or NULL            */
+    double *obj_hist;   /* [iterations] FP64 out: J_t, or NULL                  */
+    int64_t n;
+    int32_t d, k;
+} km_instance;
+
+typedef struct km_batch km_batch;
+
+/*
+ * Create a batch over `count` instances (host array, copied).  Validates every
+ * instance like km_plan_create (KM_EINVAL), needs d <= 128 and a per-label
+ * record k * d * 8 bytes of at most 80 KiB (KM_ENOTSUP otherwise), FP32
+ * distances only (KM_ENOTSUP for other precisions).  Queries the device.
+ */
+km_status km_batch_create(const km_instance *inst, int32_t count, km_precision prec,
+                          km_batch **out);
+size_t km_batch_workspace_bytes(const km_batch *batch);
+/* Bind device workspace (256-byte aligned, at least km_batch_workspace_bytes);
+ * uploads the batch's descriptor tables (synchronous). */
+km_status km_batch_set_workspace(km_batch *batch, void *ws, size_t bytes);
+/*
+ * Schedule: each instance's tiles of 256 samples are split into blocks of
+ * `tiles_per_block` tiles (>= 1); order 0 launches blocks in instance order,
+ * order 1 by decreasing work per block.  Changes the workspace size (bind a
+ * workspace again afterwards).  The autotuner in the Python package picks these.
+ */
+km_status km_batch_set_schedule(km_batch *batch, int32_t tiles_per_block, int32_t order);
+/* As km_plan_use_graphs, for kmeans_lloyd_batched (graph keyed by iterations). */
+km_status km_batch_use_graphs(km_batch *batch, int32_t enable);
+void km_batch_destroy(km_batch *batch);
+/* `iterations` >= 1 Lloyd iterations of every instance (fixed count). */
+km_status kmeans_lloyd_batched(km_batch *batch, int32_t iterations, hipStream_t stream);
+
+/*
+ * Launch mode of kmeans_lloyd.  With enable != 0 the plan captures the whole
+ * call (every iteration's kernels) into a HIP graph the first time it sees a
+ * given (X, C, labels, counts, obj_hist, max_iter, tol), and afterwards
+ * replays that graph on the call's stream while those arguments stay the same
+ * (a replay reads C afresh, so it continues from the current centroids).
+ * Capture runs on a stream the plan owns, so the caller's stream may be the
+ * null stream.  enable = 0 returns to direct launches and drops any graph.
+ */
+km_status km_plan_use_graphs(km_plan *plan, int32_t enable);
+
+/*
  * Diagnostics: per-launch duration of the per-sample pass (the kernel that
  * computes the distances, labels and per-label partial sums; it dominates
  * every call).  km_plan_enable_timing(plan, cap) makes the plan record a pair
@@ -156,6 +211,17 @@ km_status kmeans_lloyd(km_plan *plan, const float *X, float *C, int32_t *labels,
 km_status km_plan_enable_timing(km_plan *plan, int32_t cap);
 km_status km_plan_kernel_times(km_plan *plan, float *ms, int32_t cap,
                                int32_t *count);
+
+/*
+ * Diagnostics of a BF16 plan: number of samples the last MFMA assign queued
+ * for the exact FP32 recheck (their candidate set under the proven band had
+ * more than one member), and how many of those were re-checked against all k
+ * centroids because their candidate list overflowed.  Waits on `stream`;
+ * writes the HOST int64 *count and *full_scans (may be NULL).  KM_EINVAL for
+ * an FP32 plan.
+ */
+km_status km_plan_recheck_count(km_plan *plan, int64_t *count,
+                                int64_t *full_scans, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,16 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 # Entry points the header declares (checked by the ABI tests).
 EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_plan_destroy", "km_last_error", "kmeans_assign", "kmeans_update",
-           "kmeans_lloyd", "km_plan_enable_timing", "km_plan_kernel_times"]
+           "kmeans_lloyd", "km_plan_enable_timing", "km_plan_kernel_times", "km_plan_recheck_count",
+           "km_plan_use_graphs", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
+           "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched"]
+
+
+class KmInstance(ctypes.Structure):
+    """km_instance of the C header."""
+    _fields_ = [("X", ctypes.c_void_p), ("C", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("counts", ctypes.c_void_p), ("obj_hist", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("d", ctypes.c_int32), ("k", ctypes.c_int32)]
 
 
 class KMeansError(RuntimeError):
@@ -61,6 +70,24 @@ def lib():
         L.km_plan_enable_timing.argtypes = [P, I32]
         L.km_plan_kernel_times.restype = I32
         L.km_plan_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(I32)]
+        L.km_batch_create.restype = I32
+        L.km_batch_create.argtypes = [ctypes.POINTER(KmInstance), I32, I32, ctypes.POINTER(P)]
+        L.km_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.km_batch_workspace_bytes.argtypes = [P]
+        L.km_batch_set_workspace.restype = I32
+        L.km_batch_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+        L.km_batch_set_schedule.restype = I32
+        L.km_batch_set_schedule.argtypes = [P, I32, I32]
+        L.km_batch_use_graphs.restype = I32
+        L.km_batch_use_graphs.argtypes = [P, I32]
+        L.km_batch_destroy.restype = None
+        L.km_batch_destroy.argtypes = [P]
+        L.kmeans_lloyd_batched.restype = I32
+        L.kmeans_lloyd_batched.argtypes = [P, I32, P]
+        L.km_plan_use_graphs.restype = I32
+        L.km_plan_use_graphs.argtypes = [P, I32]
+        L.km_plan_recheck_count.restype = I32
+        L.km_plan_recheck_count.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
         _lib = L
     return _lib
 
@@ -122,6 +149,10 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(lib().km_plan_workspace_bytes(self._h))
 
+    def use_graphs(self, enable: bool = True):
+        """km_plan_use_graphs: capture kmeans_lloyd calls into HIP graphs."""
+        _check(lib().km_plan_use_graphs(self._h, int(bool(enable))))
+
     def enable_timing(self, cap: int):
         """km_plan_enable_timing: time up to ``cap`` launches of the per-sample pass."""
         _check(lib().km_plan_enable_timing(self._h, int(cap)))
@@ -132,6 +163,14 @@ class Plan:
         cnt = ctypes.c_int32(0)
         _check(lib().km_plan_kernel_times(self._h, buf, cap, ctypes.byref(cnt)))
         return [float(buf[i]) for i in range(min(cap, cnt.value))]
+
+    def recheck_count(self, stream=None):
+        """km_plan_recheck_count: (samples the last BF16 assign queued for the
+        exact recheck, how many of them were full scans)."""
+        v = ctypes.c_int64(0)
+        f = ctypes.c_int64(0)
+        _check(lib().km_plan_recheck_count(self._h, ctypes.byref(v), ctypes.byref(f), _stream(stream)))
+        return int(v.value), int(f.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -177,3 +216,68 @@ def kmeans_lloyd(plan: Plan, X, C, labels, counts=None, obj_hist=None, max_iter:
         _ptr(obj_hist, torch.float64, "obj_hist"), int(max_iter), float(tol), ctypes.byref(it),
         _stream(stream)))
     return int(it.value)
+
+
+class Batch:
+    """km_batch over a list of instances, each a dict of tensors X (n x d,
+    FP32), C (k x d, FP32, updated in place), labels (n, int32) and optional
+    counts (k, int64) and obj_hist (>= iterations, FP64); plus a workspace
+    tensor the batch owns."""
+
+    def __init__(self, instances, precision: str = "fp32", device=None):
+        import torch
+        self.instances = instances
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        arr = (KmInstance * len(instances))()
+        for i, t in enumerate(instances):
+            X, C = t["X"], t["C"]
+            n, d = X.shape
+            k = C.shape[0]
+            arr[i] = KmInstance(_ptr(X, torch.float32, "X"), _ptr(C, torch.float32, "C", k * d),
+                                _ptr(t["labels"], torch.int32, "labels", n),
+                                _ptr(t.get("counts"), torch.int64, "counts", k),
+                                _ptr(t.get("obj_hist"), torch.float64, "obj_hist"), n, d, k)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().km_batch_create(arr, len(instances), PRECISIONS[precision], ctypes.byref(h)))
+        self._h = h
+        self._bind()
+
+    def _bind(self):
+        import torch
+        nbytes = int(lib().km_batch_workspace_bytes(self._h))
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off:off + nbytes]
+        _check(lib().km_batch_set_workspace(self._h, self.workspace.data_ptr(), nbytes))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_schedule(self, tiles_per_block: int, order: int):
+        """km_batch_set_schedule, then a workspace of the new size is bound."""
+        _check(lib().km_batch_set_schedule(self._h, int(tiles_per_block), int(order)))
+        self._bind()
+
+    def use_graphs(self, enable: bool = True):
+        _check(lib().km_batch_use_graphs(self._h, int(bool(enable))))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().km_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kmeans_lloyd_batched(batch: Batch, iterations: int, stream=None):
+    for t in batch.instances:
+        h = t.get("obj_hist")
+        if h is not None and h.numel() < iterations:
+            raise ValueError("obj_hist needs one entry per iteration")
+    _check(lib().kmeans_lloyd_batched(batch.handle, int(iterations), _stream(stream)))

@@ -40,6 +40,13 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// Shared with km_batch.cpp: record an error text for km_last_error().
+km_status km_set_error(km_status st, const char* msg)
+{
+    g_err = msg;
+    return st;
+}
+
 struct km_plan {
     int64_t n;
     int32_t d, k;
@@ -58,6 +65,7 @@ struct km_plan {
     bool mixed = false;
     int D16 = 0, DP = 0, kpad = 0, IB = 0;
     int grid_mfma = 0, grid_rc = 0;
+    int64_t rq_per_block = 0;
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
     // workspace
@@ -67,8 +75,28 @@ struct km_plan {
     // optional per-launch timing of the per-sample pass
     std::vector<hipEvent_t> ev;   // 2 per launch
     int32_t ev_used = 0;
+    // optional graph of a whole kmeans_lloyd call, keyed by its arguments
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const float* X; float* C; int32_t* labels; int64_t* counts; double* obj_hist;
+        int32_t max_iter; double tol; int32_t ev_used;
+        bool operator==(const GraphKey& o) const
+        {
+            return X == o.X && C == o.C && labels == o.labels && counts == o.counts && obj_hist == o.obj_hist &&
+                   max_iter == o.max_iter && tol == o.tol && ev_used == o.ev_used;
+        }
+    } gkey{};
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+    }
     ~km_plan()
     {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
 };
@@ -138,8 +166,9 @@ FinArgs fin_args(const km_plan* p)
 // label chunks.
 hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
 {
-    if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_fused, s);
-    return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
+    // without a split, the update walks exactly the fused pass's tiles and blocks
+    if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_upd, s);
+    return launch_plain_pass(p->D8, MODE_UPDATE_WIDE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
 }
 
 // Mixed path: the MFMA pass (timed) and the exact recheck of its queue.
@@ -151,7 +180,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     hipError_t e = launch_prep_c(reinterpret_cast<const float*>(ws + p->off_cp), p->k, p->d, p->D, p->kpad, p->DP,
                                  reinterpret_cast<const XStats*>(ws + p->off_xs), reinterpret_cast<__bf16*>(ws + p->off_ab),
                                  reinterpret_cast<float*>(ws + p->off_bias), reinterpret_cast<CStats*>(ws + p->off_cs),
-                                 reinterpret_cast<int32_t*>(ws + p->off_rqc), ctrl, iter, s);
+                                 ctrl, iter, s);
     if (e != hipSuccess) return e;
     MixArgs m{};
     m.X = X; m.n = p->n; m.d = p->d; m.k = p->k; m.kpad = p->kpad;
@@ -165,6 +194,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.labels = labels;
     m.rq = reinterpret_cast<int32_t*>(ws + p->off_rq);
     m.rq_count = reinterpret_cast<int32_t*>(ws + p->off_rqc);
+    m.rq_per_block = p->rq_per_block;
     m.changed_part = changed;
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
@@ -176,9 +206,10 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     }
     RecheckArgs r{};
     r.X = X; r.Cp = reinterpret_cast<const float*>(ws + p->off_cp); r.n = p->n; r.d = p->d; r.k = p->k;
-    r.rq = m.rq; r.rq_count = m.rq_count; r.labels = labels; r.changed_part = changed + p->grid_mfma;
+    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block;
+    r.labels = labels; r.changed_part = changed + p->grid_mfma;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
-    return launch_recheck(p->D8, r, p->grid_rc, s);
+    return launch_recheck(p->D8, r, p->grid_mfma, s);
 }
 
 hipError_t enqueue_prep_x(km_plan* p, const float* X, hipStream_t s)
@@ -186,6 +217,9 @@ hipError_t enqueue_prep_x(km_plan* p, const float* X, hipStream_t s)
     return launch_prep_x(X, p->n, p->d, reinterpret_cast<float*>(p->ws + p->off_pxm),
                          reinterpret_cast<double*>(p->ws + p->off_pxs), reinterpret_cast<XStats*>(p->ws + p->off_xs), s);
 }
+
+km_status enqueue_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
+                        double* obj_hist, int32_t max_iter, double tol, hipStream_t stream);
 
 Ctrl* ctrl_of(const km_plan* p) { return reinterpret_cast<Ctrl*>(p->ws + p->off_ctrl); }
 float* cp_of(const km_plan* p) { return reinterpret_cast<float*>(p->ws + p->off_cp); }
@@ -237,17 +271,17 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     // The per-label record (k x d FP64 + counts) lives in LDS.  Up to 80 KiB
     // (two blocks per CU) it is whole and the assign and reduce run fused;
     // beyond that the reduce runs as a separate pass over label chunks of at
-    // most 64 KiB, a 2-D grid of (point range, label chunk) blocks.
+    // most 48 KiB, a 2-D grid of (point range, label chunk) blocks.
     p->lds_fused = plain_lds_bytes(k, d, MODE_FUSED);
     p->split = p->lds_fused > 80 * 1024;
-    p->kc = p->split ? std::max(1, (64 * 1024) / (8 * d)) : k;
+    p->kc = p->split ? std::max(1, (48 * 1024) / (8 * d)) : k;
     p->nch = (k + p->kc - 1) / p->kc;
-    p->lds_upd = plain_lds_bytes(p->kc, d, MODE_UPDATE);
+    p->lds_upd = p->split ? plain_lds_bytes(p->kc, d, MODE_UPDATE_WIDE) : p->lds_fused;
 
     // One resident wave of blocks for the persistent passes, at most 4 per CU.
     int per_cu = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
     if (!p->split) per_cu = std::min(per_cu, plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused));
-    int per_cu_upd = plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
+    int per_cu_upd = plain_blocks_per_cu(p->D8, p->split ? MODE_UPDATE_WIDE : MODE_UPDATE, p->lds_upd);
     if (per_cu < 1 || per_cu_upd < 1) { delete p; return fail(KM_EHIP, "occupancy query for the per-sample pass failed"); }
     per_cu = std::min(per_cu, 4);
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
@@ -268,7 +302,8 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
-        p->grid_rc = ncu * 2;
+        p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
+        p->rq_per_block = ((mt + p->grid_mfma - 1) / p->grid_mfma) * kMixTile;
     }
 
     size_t off = 0;
@@ -289,8 +324,8 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_ab = off;   off = align256(off + (size_t)p->kpad * p->DP * sizeof(__bf16));
         p->off_bias = off; off = align256(off + (size_t)p->kpad * sizeof(float));
         p->off_cs = off;   off = align256(off + sizeof(CStats));
-        p->off_rqc = off;  off = align256(off + sizeof(int32_t));
-        p->off_rq = off;   off = align256(off + (size_t)n * kRqInts * sizeof(int32_t));
+        p->off_rqc = off;  off = align256(off + 2 * (size_t)p->grid_mfma * sizeof(int32_t));
+        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * kRqInts * sizeof(int32_t));
     }
     p->total = off;
     *out = p;
@@ -379,6 +414,68 @@ km_status kmeans_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels,
     if ((st = set_device(plan)) != KM_OK) return st;
 
     Ctrl* ctrl = ctrl_of(plan);
+    hipError_t e;
+    if (plan->use_graph) {
+        // Replay the captured call when the arguments are unchanged; otherwise
+        // capture it on the plan's own stream (the caller's may be the null
+        // stream, which cannot be captured) and replay on the caller's.
+        const km_plan::GraphKey key{X, C, labels, counts, obj_hist, max_iter, tol, plan->ev_used};
+        if (!plan->gexec || !(plan->gkey == key)) {
+            plan->drop_graph();
+            if (!plan->cap_stream && (e = hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreateWithFlags");
+            if ((e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(e, "hipStreamBeginCapture");
+            const int32_t ev_before = plan->ev_used;
+            km_status cs = enqueue_lloyd(plan, X, C, labels, counts, obj_hist, max_iter, tol, plan->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(plan->cap_stream, &g);
+            if (cs != KM_OK) { if (g) (void)hipGraphDestroy(g); plan->ev_used = ev_before; return cs; }
+            if (ee != hipSuccess) { plan->ev_used = ev_before; return hip_fail(ee, "hipStreamEndCapture"); }
+            ee = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ee != hipSuccess) { plan->gexec = nullptr; plan->ev_used = ev_before; return hip_fail(ee, "hipGraphInstantiate"); }
+            plan->gkey = key;
+            plan->gkey.ev_used = plan->ev_used;
+        }
+        if ((e = hipGraphLaunch(plan->gexec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        km_status es = enqueue_lloyd(plan, X, C, labels, counts, obj_hist, max_iter, tol, stream);
+        if (es != KM_OK) return es;
+    }
+    if (iters_done) {
+        if (tol < 0.0) {
+            *iters_done = max_iter;
+        } else {
+            int32_t v = 0;
+            e = hipMemcpyAsync(&v, &ctrl->iters_done, sizeof v, hipMemcpyDeviceToHost, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(iters_done)");
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            *iters_done = v;
+        }
+    }
+    return KM_OK;
+}
+
+km_status km_plan_use_graphs(km_plan* plan, int32_t enable)
+{
+    g_err.clear();
+    if (!plan) return fail(KM_EINVAL, "plan is NULL");
+    plan->use_graph = enable != 0;
+    plan->drop_graph();
+    return KM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The launches of one kmeans_lloyd call, in stream order.
+km_status enqueue_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
+                        double* obj_hist, int32_t max_iter, double tol, hipStream_t stream)
+{
+    Ctrl* ctrl = ctrl_of(plan);
     float* Cp = cp_of(plan);
     hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, Cp, ctrl, stream);
     if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
@@ -410,26 +507,19 @@ km_status kmeans_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels,
         e = launch_finalize(f, stream);
         if (e != hipSuccess) return hip_fail(e, "finalize launch");
     }
-    if (iters_done) {
-        if (tol < 0.0) {
-            *iters_done = max_iter;
-        } else {
-            int32_t v = 0;
-            e = hipMemcpyAsync(&v, &ctrl->iters_done, sizeof v, hipMemcpyDeviceToHost, stream);
-            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(iters_done)");
-            e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            *iters_done = v;
-        }
-    }
     return KM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 km_status km_plan_enable_timing(km_plan* plan, int32_t cap)
 {
     g_err.clear();
     if (!plan) return fail(KM_EINVAL, "plan is NULL");
     if (cap < 0) return fail(KM_EINVAL, "cap = %d must be >= 0", cap);
+    plan->drop_graph();   // a captured graph records into the old events
     for (hipEvent_t e : plan->ev) (void)hipEventDestroy(e);
     plan->ev.clear();
     plan->ev_used = 0;
@@ -439,6 +529,25 @@ km_status km_plan_enable_timing(km_plan* plan, int32_t cap)
         if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
         plan->ev.push_back(e);
     }
+    return KM_OK;
+}
+
+km_status km_plan_recheck_count(km_plan* plan, int64_t* count, int64_t* full_scans, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    if (!plan->mixed) return fail(KM_EINVAL, "the plan has no recheck queue (FP32 plan)");
+    if (!count) return fail(KM_EINVAL, "count is NULL");
+    std::vector<int32_t> v(2 * (size_t)plan->grid_mfma);
+    hipError_t e = hipMemcpyAsync(v.data(), plan->ws + plan->off_rqc, v.size() * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(recheck counts)");
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int64_t total = 0, full = 0;
+    for (int b = 0; b < plan->grid_mfma; ++b) { total += v[b]; full += v[plan->grid_mfma + b]; }
+    *count = total;
+    if (full_scans) *full_scans = full;
     return KM_OK;
 }
 

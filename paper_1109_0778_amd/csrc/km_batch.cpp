@@ -1,0 +1,326 @@
+// Host side of the batched C ABI: many independent Lloyd problems advanced
+// together.  Every iteration is one launch of the per-sample pass per shape
+// class (instances grouped by padded dimension and by the LDS their record
+// needs) over a table of (instance, tile range, partial slot) blocks, plus one
+// finalize launch over (instance, 64-element chunk) blocks.
+#include "kmeans_mi355x.h"
+#include "km_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace km;
+
+// Defined in km_api.cpp: sets km_last_error() text and returns the status.
+km_status km_set_error(km_status st, const char* msg);
+
+namespace {
+
+km_status berr(km_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return km_set_error(st, buf);
+}
+
+km_status bhip(hipError_t e, const char* what)
+{
+    return berr(KM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Group {
+    int D8;
+    size_t lds;
+    int first, count;     // range in the work table
+};
+
+}  // namespace
+
+struct km_batch {
+    std::vector<km_instance> inst;
+    int device = 0;
+    int tpb = 16;          // tiles per block
+    int order = 1;         // 0: instance order, 1: decreasing work per block
+    // derived layout
+    std::vector<int> nslots;
+    std::vector<size_t> off_cp, off_S, off_cnt, off_J, off_ch, off_bad;
+    std::vector<BatchWork> work;
+    std::vector<BatchFinWork> fwork;
+    std::vector<Group> groups;
+    size_t off_pa = 0, off_fa = 0, off_work = 0, off_fwork = 0, total = 0;
+    unsigned char* ws = nullptr;
+    // graph
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int32_t g_iters = 0;
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+    }
+    ~km_batch()
+    {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+namespace {
+
+int d8_of(int d) { return (d + 7) / 8; }
+
+size_t lds_bucket(size_t lds)
+{
+    static const size_t b[] = {24 * 1024, 48 * 1024, 64 * 1024, 80 * 1024};
+    for (size_t x : b)
+        if (lds <= x) return x;
+    return lds;
+}
+
+// Work tables and workspace layout for the current schedule.
+void layout(km_batch* B)
+{
+    const int m = (int)B->inst.size();
+    B->nslots.assign(m, 0);
+    B->off_cp.assign(m, 0); B->off_S.assign(m, 0); B->off_cnt.assign(m, 0);
+    B->off_J.assign(m, 0); B->off_ch.assign(m, 0); B->off_bad.assign(m, 0);
+    std::map<std::pair<int, size_t>, std::vector<BatchWork>> by_group;
+    std::vector<double> cost_of;   // parallel to by_group vectors (work per block)
+    std::map<std::pair<int, size_t>, std::vector<double>> costs;
+    B->fwork.clear();
+    size_t off = 0;
+    for (int i = 0; i < m; ++i) {
+        const km_instance& x = B->inst[i];
+        const int D8 = d8_of(x.d);
+        const int64_t tiles = (x.n + kBlock - 1) / kBlock;
+        const int nb = (int)((tiles + B->tpb - 1) / B->tpb);
+        B->nslots[i] = nb;
+        const size_t lds = lds_bucket(plain_lds_bytes(x.k, x.d, MODE_FUSED));
+        auto key = std::make_pair(D8, lds);
+        for (int b = 0; b < nb; ++b) {
+            BatchWork w;
+            w.inst = i;
+            w.slot = b;
+            w.t0 = (int64_t)b * B->tpb;
+            w.t1 = std::min<int64_t>(tiles, w.t0 + B->tpb);
+            by_group[key].push_back(w);
+            costs[key].push_back((double)(w.t1 - w.t0) * x.k * x.d);
+        }
+        const int chunks = finalize_blocks(x.k, x.d);
+        for (int c = 0; c < chunks; ++c) B->fwork.push_back(BatchFinWork{i, c});
+        B->off_cp[i] = off;  off = al256(off + (size_t)x.k * 8 * D8 * sizeof(float));
+        B->off_S[i] = off;   off = al256(off + (size_t)nb * x.k * x.d * sizeof(double));
+        B->off_cnt[i] = off; off = al256(off + (size_t)nb * x.k * sizeof(int32_t));
+        B->off_J[i] = off;   off = al256(off + (size_t)nb * sizeof(double));
+        B->off_ch[i] = off;  off = al256(off + (size_t)nb * sizeof(int32_t));
+        B->off_bad[i] = off; off = al256(off + (size_t)nb * sizeof(int32_t));
+    }
+    B->work.clear();
+    B->groups.clear();
+    for (auto& kv : by_group) {
+        std::vector<BatchWork>& v = kv.second;
+        if (B->order == 1) {
+            std::vector<double>& c = costs[kv.first];
+            std::vector<int> idx(v.size());
+            for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int)q;
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c[a] > c[b]; });
+            std::vector<BatchWork> s(v.size());
+            for (size_t q = 0; q < idx.size(); ++q) s[q] = v[idx[q]];
+            v.swap(s);
+        }
+        Group g;
+        g.D8 = kv.first.first;
+        g.lds = kv.first.second;
+        g.first = (int)B->work.size();
+        g.count = (int)v.size();
+        B->groups.push_back(g);
+        B->work.insert(B->work.end(), v.begin(), v.end());
+    }
+    B->off_pa = off;    off = al256(off + (size_t)m * sizeof(PassArgs));
+    B->off_fa = off;    off = al256(off + (size_t)m * sizeof(FinArgs));
+    B->off_work = off;  off = al256(off + B->work.size() * sizeof(BatchWork));
+    B->off_fwork = off; off = al256(off + B->fwork.size() * sizeof(BatchFinWork));
+    B->total = off;
+}
+
+// Device tables: per-instance PassArgs / FinArgs pointing into the workspace.
+km_status upload(km_batch* B)
+{
+    const int m = (int)B->inst.size();
+    std::vector<PassArgs> pa(m);
+    std::vector<FinArgs> fa(m);
+    unsigned char* ws = B->ws;
+    for (int i = 0; i < m; ++i) {
+        const km_instance& x = B->inst[i];
+        const int D8 = d8_of(x.d);
+        Partials pt;
+        pt.S = reinterpret_cast<double*>(ws + B->off_S[i]);
+        pt.cnt = reinterpret_cast<int32_t*>(ws + B->off_cnt[i]);
+        pt.J = reinterpret_cast<double*>(ws + B->off_J[i]);
+        pt.changed = reinterpret_cast<int32_t*>(ws + B->off_ch[i]);
+        pt.bad = reinterpret_cast<int32_t*>(ws + B->off_bad[i]);
+        float* Cp = reinterpret_cast<float*>(ws + B->off_cp[i]);
+        PassArgs& a = pa[i];
+        std::memset(&a, 0, sizeof a);
+        a.X = x.X; a.Cp = Cp; a.labels = x.labels; a.mindist = nullptr; a.part = pt; a.ctrl = nullptr;
+        a.n = x.n; a.d = x.d; a.k = x.k; a.iter = 0; a.count_changed = 1; a.kc = x.k;
+        FinArgs& f = fa[i];
+        std::memset(&f, 0, sizeof f);
+        f.part = pt; f.G = B->nslots[i]; f.GJ = B->nslots[i]; f.GC = B->nslots[i];
+        f.k = x.k; f.d = x.d; f.D = 8 * D8;
+        f.C_old = Cp; f.ld_old = 8 * D8; f.C_new = x.C; f.ld_new = x.d; f.Cp_out = Cp;
+        f.counts = x.counts; f.ctrl = nullptr; f.obj_hist = x.obj_hist; f.tol = -1.0; f.want_J = 1; f.jmode = 0;
+    }
+    hipError_t e;
+    if ((e = hipMemcpy(ws + B->off_pa, pa.data(), pa.size() * sizeof(PassArgs), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(ws + B->off_fa, fa.data(), fa.size() * sizeof(FinArgs), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(ws + B->off_work, B->work.data(), B->work.size() * sizeof(BatchWork),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(ws + B->off_fwork, B->fwork.data(), B->fwork.size() * sizeof(BatchFinWork),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return bhip(e, "hipMemcpy(batch tables)");
+    return KM_OK;
+}
+
+km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
+{
+    const unsigned char* ws = B->ws;
+    const FinArgs* fa = reinterpret_cast<const FinArgs*>(ws + B->off_fa);
+    const PassArgs* pa = reinterpret_cast<const PassArgs*>(ws + B->off_pa);
+    const BatchWork* work = reinterpret_cast<const BatchWork*>(ws + B->off_work);
+    const BatchFinWork* fwork = reinterpret_cast<const BatchFinWork*>(ws + B->off_fwork);
+    hipError_t e = launch_batch_pad(fa, nullptr, (int)B->inst.size(), s);
+    if (e != hipSuccess) return bhip(e, "batch pad launch");
+    for (int32_t t = 0; t < iters; ++t) {
+        for (const Group& g : B->groups) {
+            if ((e = launch_batch_pass(g.D8, work + g.first, g.count, pa, t, g.lds, s)) != hipSuccess)
+                return bhip(e, "batch pass launch");
+        }
+        if ((e = launch_batch_finalize(fwork, (int)B->fwork.size(), fa, t, s)) != hipSuccess)
+            return bhip(e, "batch finalize launch");
+    }
+    return KM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+km_status km_batch_create(const km_instance* inst, int32_t count, km_precision prec, km_batch** out)
+{
+    km_set_error(KM_OK, "");
+    if (!out) return berr(KM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!inst || count < 1) return berr(KM_EINVAL, "need at least one instance");
+    if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3) return berr(KM_EINVAL, "unknown precision %d", (int)prec);
+    if (prec != KM_FP32) return berr(KM_ENOTSUP, "batched Lloyd supports FP32 distances only");
+    for (int32_t i = 0; i < count; ++i) {
+        const km_instance& x = inst[i];
+        if (x.n < 1 || x.n >= ((int64_t)1 << 31)) return berr(KM_EINVAL, "instance %d: n outside [1, 2^31)", i);
+        if (x.d < 1 || x.d > 1024) return berr(KM_EINVAL, "instance %d: d outside [1, 1024]", i);
+        if (x.k < 1 || (int64_t)x.k > x.n) return berr(KM_EINVAL, "instance %d: k outside [1, n]", i);
+        if (!x.X || !x.C || !x.labels) return berr(KM_EINVAL, "instance %d: X, C and labels must be non-NULL", i);
+        if ((reinterpret_cast<uintptr_t>(x.X) | reinterpret_cast<uintptr_t>(x.C)) & 15u)
+            return berr(KM_EINVAL, "instance %d: X and C must be 16-byte aligned", i);
+        if (x.d > 8 * kMaxD8Plain) return berr(KM_ENOTSUP, "instance %d: batched Lloyd supports d <= 128", i);
+        if (plain_lds_bytes(x.k, x.d, MODE_FUSED) > 80 * 1024)
+            return berr(KM_ENOTSUP, "instance %d: k*d too large for a batched per-label record", i);
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return bhip(e, "hipGetDevice");
+    km_batch* B = new (std::nothrow) km_batch();
+    if (!B) return berr(KM_EINVAL, "out of host memory");
+    B->inst.assign(inst, inst + count);
+    B->device = dev;
+    layout(B);
+    *out = B;
+    return KM_OK;
+}
+
+size_t km_batch_workspace_bytes(const km_batch* batch) { return batch ? batch->total : 0; }
+
+km_status km_batch_set_workspace(km_batch* batch, void* ws, size_t bytes)
+{
+    km_set_error(KM_OK, "");
+    if (!batch) return berr(KM_EINVAL, "batch is NULL");
+    if (!ws) return berr(KM_EWORKSPACE, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return berr(KM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < batch->total)
+        return berr(KM_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu the batch needs", bytes, batch->total);
+    batch->ws = static_cast<unsigned char*>(ws);
+    batch->drop_graph();
+    return upload(batch);
+}
+
+km_status km_batch_set_schedule(km_batch* batch, int32_t tiles_per_block, int32_t order)
+{
+    km_set_error(KM_OK, "");
+    if (!batch) return berr(KM_EINVAL, "batch is NULL");
+    if (tiles_per_block < 1 || (order != 0 && order != 1)) return berr(KM_EINVAL, "bad schedule");
+    batch->tpb = tiles_per_block;
+    batch->order = order;
+    batch->drop_graph();
+    batch->ws = nullptr;   // layout changes: a workspace must be bound again
+    layout(batch);
+    return KM_OK;
+}
+
+km_status km_batch_use_graphs(km_batch* batch, int32_t enable)
+{
+    km_set_error(KM_OK, "");
+    if (!batch) return berr(KM_EINVAL, "batch is NULL");
+    batch->use_graph = enable != 0;
+    batch->drop_graph();
+    return KM_OK;
+}
+
+void km_batch_destroy(km_batch* batch) { delete batch; }
+
+km_status kmeans_lloyd_batched(km_batch* B, int32_t iters, hipStream_t stream)
+{
+    km_set_error(KM_OK, "");
+    if (!B) return berr(KM_EINVAL, "batch is NULL");
+    if (!B->ws) return berr(KM_EWORKSPACE, "no workspace bound to the batch (km_batch_set_workspace)");
+    if (iters < 1) return berr(KM_EINVAL, "iterations = %d must be >= 1", iters);
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return bhip(e, "hipGetDevice");
+    if (cur != B->device) return berr(KM_EINVAL, "batch was created on device %d but device %d is current", B->device, cur);
+    if (!B->use_graph) return enqueue_batch(B, iters, stream);
+    if (!B->gexec || B->g_iters != iters) {
+        B->drop_graph();
+        if (!B->cap_stream && (e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return bhip(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return bhip(e, "hipStreamBeginCapture");
+        km_status cs = enqueue_batch(B, iters, B->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(B->cap_stream, &g);
+        if (cs != KM_OK) { if (g) (void)hipGraphDestroy(g); return cs; }
+        if (ee != hipSuccess) return bhip(ee, "hipStreamEndCapture");
+        ee = hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ee != hipSuccess) { B->gexec = nullptr; return bhip(ee, "hipGraphInstantiate"); }
+        B->g_iters = iters;
+    }
+    if ((e = hipGraphLaunch(B->gexec, stream)) != hipSuccess) return bhip(e, "hipGraphLaunch");
+    return KM_OK;
+}
+
+}  // extern "C"

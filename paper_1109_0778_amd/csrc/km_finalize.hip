@@ -125,6 +125,70 @@ __global__ __launch_bounds__(64) void finalize_objective_kernel(FinArgs a)
     }
 }
 
+// Batched finalize: block (instance, 64 elements) of 128 threads.  Wave 0
+// sums the instance's partial slots for its elements in slot order, divides
+// in FP64, rounds once to FP32 and applies the empty-cluster rule; wave 1 of
+// the instance's first block reduces its objective partials (lane-strided,
+// then xor tree) into obj_hist[iter].
+__global__ __launch_bounds__(128) void batch_finalize_kernel(const BatchFinWork* __restrict__ work,
+                                                             const FinArgs* __restrict__ fa, int32_t iter)
+{
+    const BatchFinWork w = work[blockIdx.x];
+    const FinArgs a = fa[w.inst];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t kd = (int64_t)a.k * a.d;
+    if (wave == 0) {
+        const int64_t e = (int64_t)w.chunk * 64 + lane;
+        if (e < kd) {
+            const int j = (int)(e / a.d);
+            const int f = (int)(e - (int64_t)j * a.d);
+            double S = 0.0;
+            int64_t c = 0;
+            for (int b = 0; b < a.G; ++b) {
+                S += a.part.S[(size_t)b * kd + e];
+                c += a.part.cnt[(size_t)b * a.k + j];
+            }
+            const float old = a.C_old[(size_t)j * a.ld_old + f];
+            const float v = (c > 0) ? (float)(S / (double)c) : old;
+            a.C_new[(size_t)j * a.ld_new + f] = v;
+            if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
+            if (a.counts && f == 0) a.counts[j] = c;
+        }
+    } else if (w.chunk == 0) {
+        double J = 0.0;
+        for (int b = lane; b < a.GJ; b += 64) J += a.part.J[b];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) J += __shfl_xor(J, off);
+        if (lane == 0 && a.obj_hist) a.obj_hist[iter] = J;
+    }
+}
+
+// Batched: each instance's C (in FinArgs.C_new, row stride d) padded into its
+// Cp (FinArgs.Cp_out, row stride D); one block per instance.
+__global__ __launch_bounds__(256) void batch_pad_kernel(const FinArgs* __restrict__ fa)
+{
+    const FinArgs a = fa[blockIdx.x];
+    const int64_t total = (int64_t)a.k * a.D;
+    for (int64_t e = threadIdx.x; e < total; e += 256) {
+        const int j = (int)(e / a.D);
+        const int f = (int)(e - (int64_t)j * a.D);
+        a.Cp_out[e] = (f < a.d) ? a.C_new[(size_t)j * a.d + f] : 0.0f;
+    }
+}
+
+hipError_t launch_batch_finalize(const BatchFinWork* work, int nwork, const FinArgs* fa, int iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(nwork), dim3(128), 0, s, work, fa, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pad(const FinArgs* fa, const float* const*, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_pad_kernel, dim3(ninst), dim3(256), 0, s, fa);
+    return hipGetLastError();
+}
+
 // Pads C (k x d) into Cp (k x D, zero columns d..D-1); optionally resets the
 // control block.
 __global__ void pad_centroids_kernel(const float* __restrict__ C, int32_t k, int32_t d, int32_t D,

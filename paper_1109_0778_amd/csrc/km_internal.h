@@ -16,7 +16,10 @@ constexpr int kMaxD8Plain = 16;       // plain path: d <= 128 (eight-feature chu
 // kFinSplit ways in a first stage, whose sums a second stage adds in order.
 constexpr int kFinSplit = 16;
 
-enum Mode : int { MODE_ASSIGN = 0, MODE_UPDATE = 1, MODE_FUSED = 2 };
+// Per-sample pass variants: assign only; update from stored labels with the
+// fused pass's tiles (so the two give bit-identical sums); fused assign +
+// update; update over label chunks with wider tiles (records beyond LDS).
+enum Mode : int { MODE_ASSIGN = 0, MODE_UPDATE = 1, MODE_FUSED = 2, MODE_UPDATE_WIDE = 3 };
 
 // Device control block of one plan (lives at the head of the workspace).
 struct Ctrl {
@@ -54,6 +57,13 @@ struct PassArgs {
     int32_t kc;           // update passes: labels per chunk; block y owns labels [y*kc, y*kc+kc)
 };
 
+// One block of a batched per-sample pass.
+struct BatchWork {
+    int32_t inst;         // instance index
+    int32_t slot;         // partial slot of the instance
+    int64_t t0, t1;       // tiles [t0, t1) of the instance
+};
+
 struct FinArgs {
     Partials part;
     double* stageS;       // [kFinSplit][k*d] first-stage sums
@@ -87,6 +97,13 @@ hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, dim3 grid, si
                              hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 __host__ __device__ inline int finalize_blocks(int k, int d) { return (int)(((int64_t)k * d + 63) / 64); }
+hipError_t launch_batch_pass(int D8, const BatchWork* work, int nwork, const PassArgs* insts, int iter,
+                             size_t lds_bytes, hipStream_t s);
+// Batched finalize: one block per (instance, 64 elements); also pads the
+// instances' centroids at the start of a call (pad = true).
+struct BatchFinWork { int32_t inst; int32_t chunk; };
+hipError_t launch_batch_finalize(const BatchFinWork* work, int nwork, const FinArgs* fa, int iter, hipStream_t s);
+hipError_t launch_batch_pad(const FinArgs* fa, const float* const* C_in, int ninst, hipStream_t s);
 // Resident blocks per CU of the plain pass (HIP occupancy query), -1 on error.
 int plain_blocks_per_cu(int D8, Mode mode, size_t lds_bytes);
 hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s);
@@ -98,6 +115,9 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStrea
 // operands 13% slower than SGPR operands.
 constexpr int plain_rows_per_lane(int) { return 1; }
 inline int plain_tile(int D8) { return kBlock * plain_rows_per_lane(D8); }
+// Update-only passes read labels, not distances: 4 labels per lane per tile,
+// so each wave's list of owned samples is long enough to keep 16 rows in flight.
+constexpr int kUpdateRows = 4;
 
 // LDS bytes the plain pass needs for given k, d (activation record + label buffers).
 inline size_t plain_lds_bytes(int k, int d, Mode mode)
@@ -106,7 +126,9 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
     if (mode != MODE_ASSIGN) {
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
-        b += 2 * (size_t)kBlock * 2 * sizeof(int32_t);
+        const size_t tile = (size_t)kBlock * (mode == MODE_UPDATE_WIDE ? kUpdateRows : 1);
+        b += (2 + 2 * kWaves) * tile * sizeof(int32_t);     // tile labels, per-wave lists, sorted lists
+        b += (size_t)k * sizeof(int32_t);                    // per-label cursors
     }
     return b;
 }
@@ -117,10 +139,12 @@ constexpr int kMixWaves = 4;                    // waves per block
 constexpr int kMixNB = 2;                       // 32-sample column blocks per wave
 constexpr int kMixTile = kMixWaves * kMixNB * 32;
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
-constexpr int kCandCap = 7;                     // candidate slots per lane (half a sample's rows)
+constexpr int kCandCap = 7;                     // candidates kept per lane (half a sample's rows)
+constexpr int kCandSlots = kCandCap + 8;        // LDS slots per lane: room for 8 appends before compaction
 constexpr int kRqInts = 16;                     // ints per recheck entry: sample, count, 14 ids
 constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
 constexpr int kXStatBlocks = 256;
+constexpr int kRecheckSplit = 8;                // recheck blocks per MFMA block's queue region
 
 struct XStats {                 // once per run, over all samples
     float max_xn2;              // max_i |x_i|^2 (FP32)
@@ -143,8 +167,9 @@ struct MixArgs {
     int32_t gamma_terms;        // m of the gamma_m accumulation bound
     int32_t D8;                 // chunks of the canonical FP32 distance
     int32_t* labels;
-    int32_t* rq;                // [n][kRqInts] recheck entries
-    int32_t* rq_count;
+    int32_t* rq;                // [grid][rq_per_block][kRqInts] recheck entries, one region per block
+    int32_t* rq_count;          // [2][grid] entries queued by each block, then full scans among them
+    int64_t rq_per_block;       // region capacity (tiles per block x samples per tile)
     int32_t* changed_part;      // [grid]
     const Ctrl* ctrl;
     int32_t iter;
@@ -157,7 +182,8 @@ struct RecheckArgs {
     int64_t n;
     int32_t d, k;
     const int32_t* rq;
-    const int32_t* rq_count;
+    const int32_t* rq_count;    // [grid]; recheck block b takes region b
+    int64_t rq_per_block;
     int32_t* labels;
     int32_t* changed_part;      // [grid]
     const Ctrl* ctrl;
@@ -168,8 +194,8 @@ struct RecheckArgs {
 hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, double* part_sum,
                          XStats* xs, hipStream_t s);
 hipError_t launch_prep_c(const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
-                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, int32_t* rq_count,
-                         const Ctrl* ctrl, int32_t iter, hipStream_t s);
+                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter,
+                         hipStream_t s);
 hipError_t launch_mfma_assign(int D16, const MixArgs& a, int grid, hipStream_t s);
 size_t mfma_lds_bytes(int D16);
 int mfma_blocks_per_cu(int D16);

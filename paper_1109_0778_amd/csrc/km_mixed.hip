@@ -32,9 +32,8 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 // ------------------------------------------------------------ run-level prep
-// Per block: max |x|^2 (FP32) and sum |x|^2 (FP64, rows in a fixed order);
-// the last block to finish is not special: a second one-wave kernel combines
-// the block partials in index order.
+// Per block: max |x|^2 (FP32) and sum |x|^2 (FP64, rows in a fixed order); a
+// second one-wave kernel combines the block partials in a fixed order.
 __global__ __launch_bounds__(256) void prep_x_kernel(const float* __restrict__ X, int64_t n, int32_t d,
                                                      float* part_max, double* part_sum)
 {
@@ -92,14 +91,12 @@ __global__ void prep_x_combine_kernel(const float* part_max, const double* part_
 
 // ------------------------------------------------------ per-iteration prep
 // One block: BF16 operand rows bf16(-2 c_j) (zero padded to DP features and
-// kpad rows), biases K + |c_j|^2 (huge for padded rows), the band constants,
-// and the recheck-queue reset.  The centroid loop invariants are hoisted here,
-// out of the per-sample pass.
+// kpad rows), biases K + |c_j|^2 (huge for padded rows) and the band constants.
+// The centroid loop invariants are hoisted here, out of the per-sample pass.
 __global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ Cp, int32_t k, int32_t d,
                                                      int32_t D, int32_t kpad, int32_t DP,
                                                      const XStats* __restrict__ xs, __bf16* Ab,
-                                                     float* bias, CStats* cs, int32_t* rq_count,
-                                                     const Ctrl* ctrl, int32_t iter)
+                                                     float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter)
 {
     __shared__ float smax[256];
     if (ctrl != nullptr && ctrl->stop_iter < iter) return;
@@ -137,7 +134,6 @@ __global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ C
         cs->cn2max = m;
         cs->cmax = sqrtf(m) * (1.0f + 1e-6f);
         cs->pad = 0.0f;
-        *rq_count = 0;
     }
 }
 
@@ -160,11 +156,16 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
     constexpr int DP = 16 * D16;
     constexpr int ROWB = DP * 2 + 16;      // padded LDS row: conflict-free 16-byte reads
     constexpr int NB = kMixNB;
+    constexpr int CHB = kMixCK * ROWB;     // bytes of one chunk buffer
+    constexpr int V = DP * 2 / 16;         // uint4 per centroid row
+    constexpr int PF = (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned char* Abuf = smem;                                                   // [CK][ROWB]
-    float* bbuf = reinterpret_cast<float*>(smem + kMixCK * ROWB);                 // [CK]
-    uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + kMixCK);                  // [waves][NB][CAP][64]
+    unsigned char* Abuf = smem;                                                   // [2][CK][ROWB]
+    float* bbuf = reinterpret_cast<float*>(smem + 2 * CHB);                       // [2][CK]
+    uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + 2 * kMixCK);              // [waves][NB][SLOTS][64]
     __shared__ int32_t sred[kMixWaves];
+    __shared__ int32_t blk_count;           // recheck entries queued by this block
+    __shared__ int32_t blk_full;            // ... of which full scans (candidate list overflowed)
 
     if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
 
@@ -172,6 +173,8 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int h = lane >> 5;
+    if (tid == 0) { blk_count = 0; blk_full = 0; }
+    int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * kRqInts;
     const int col = lane & 31;
     const int d = a.d;
     const int64_t n = a.n;
@@ -185,8 +188,38 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
     const float gcan = (10.0f + (a.D8 > 1 ? ceilf(log2f(P)) : 0.0f)) * 5.9604645e-8f;
     const int nchunks = a.kpad / kMixCK;
     const int64_t ntiles = (n + kMixTile - 1) / kMixTile;
-    uint32_t* mycand = cand + (size_t)wave * NB * kCandCap * 64;
+    uint32_t* mycand = cand + (size_t)wave * NB * kCandSlots * 64;
     int32_t changed = 0;
+
+    // Chunk c of the centroid operands: registers <- global, LDS buffer <- registers.
+#define KM_LOAD_CHUNK(c_)                                                                 \
+    {                                                                                     \
+        const uint4* src_ = reinterpret_cast<const uint4*>(a.Ab + (size_t)(c_) * kMixCK * DP); \
+        _Pragma("unroll") for (int i_ = 0; i_ < PF; ++i_) {                               \
+            const int e_ = tid + i_ * 64 * kMixWaves;                                     \
+            pr[i_] = (e_ < kMixCK * V) ? src_[e_] : make_uint4(0, 0, 0, 0);               \
+        }                                                                                 \
+        pb = (tid < kMixCK) ? a.bias[(size_t)(c_) * kMixCK + tid] : 0.0f;                 \
+    }
+#define KM_STORE_CHUNK(buf_)                                                              \
+    {                                                                                     \
+        _Pragma("unroll") for (int i_ = 0; i_ < PF; ++i_) {                               \
+            const int e_ = tid + i_ * 64 * kMixWaves;                                     \
+            if (e_ < kMixCK * V) {                                                        \
+                const int row_ = e_ / V, q_ = e_ - row_ * V;                              \
+                *reinterpret_cast<uint4*>(Abuf + (buf_) * CHB + row_ * ROWB + q_ * 16) = pr[i_]; \
+            }                                                                             \
+        }                                                                                 \
+        if (tid < kMixCK) bbuf[(buf_) * kMixCK + tid] = pb;                              \
+    }
+    uint4 pr[PF];
+    float pb = 0.0f;
+    int cur = 0;
+    if (blockIdx.x < ntiles) {
+        KM_LOAD_CHUNK(0)
+        KM_STORE_CHUNK(0)
+    }
+    __syncthreads();
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         // --- B fragments (BF16) and |x| of this wave's 2 x 32 samples
@@ -229,39 +262,33 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
         }
 
         uint32_t m[NB], thr[NB];
-        int cnt[NB];
+        int cnt[NB], ovf[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) { m[nb] = 0xffffffffu; thr[nb] = 0xffffffffu; cnt[nb] = 0; }
+        for (int nb = 0; nb < NB; ++nb) { m[nb] = 0xffffffffu; thr[nb] = 0xffffffffu; cnt[nb] = 0; ovf[nb] = 0; }
 
-        // --- sweep over the centroids
+        // --- sweep over the centroids; the next chunk (possibly chunk 0 of the
+        // next tile) is fetched into registers while this one is computed
         for (int c = 0; c < nchunks; ++c) {
-            __syncthreads();   // the previous chunk is no longer read
-            {
-                const uint4* src = reinterpret_cast<const uint4*>(a.Ab + (size_t)c * kMixCK * DP);
-                constexpr int V = DP * 2 / 16;   // uint4 per row
-                for (int e = tid; e < kMixCK * V; e += 64 * kMixWaves) {
-                    const int r = e / V, q = e - r * V;
-                    *reinterpret_cast<uint4*>(Abuf + r * ROWB + q * 16) = src[e];
-                }
-                for (int e = tid; e < kMixCK; e += 64 * kMixWaves) bbuf[e] = a.bias[(size_t)c * kMixCK + e];
-            }
-            __syncthreads();
+            const bool pref = nchunks > 1 && (c + 1 < nchunks || t + gridDim.x < ntiles);
+            if (pref) KM_LOAD_CHUNK(c + 1 < nchunks ? c + 1 : 0)
+            const unsigned char* Ab_c = Abuf + cur * CHB;
+            const float* bb_c = bbuf + cur * kMixCK;
 #pragma unroll
             for (int tt = 0; tt < kMixCK / 32; ++tt) {
                 f32x16 acc[NB];
                 {
-                    float bv[16];
+                    float bvv[16];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        const float4 b4 = *reinterpret_cast<const float4*>(bbuf + tt * 32 + 8 * g + 4 * h);
-                        bv[4 * g + 0] = b4.x; bv[4 * g + 1] = b4.y; bv[4 * g + 2] = b4.z; bv[4 * g + 3] = b4.w;
+                        const float4 b4 = *reinterpret_cast<const float4*>(bb_c + tt * 32 + 8 * g + 4 * h);
+                        bvv[4 * g + 0] = b4.x; bvv[4 * g + 1] = b4.y; bvv[4 * g + 2] = b4.z; bvv[4 * g + 3] = b4.w;
                     }
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) acc[nb][i] = bv[i];
+                        for (int i = 0; i < 16; ++i) acc[nb][i] = bvv[i];
                 }
-                const unsigned char* arow = Abuf + (tt * 32 + col) * ROWB + 16 * h;
+                const unsigned char* arow = Ab_c + (tt * 32 + col) * ROWB + 16 * h;
 #pragma unroll
                 for (int s = 0; s < D16; ++s) {
                     const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * s);
@@ -281,15 +308,32 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
                         mm = min(mm, key[i]);
                     }
                     m[nb] = mm;
-                    thr[nb] = thr_key(mm, W[nb], ibm);
+                    const uint32_t th = thr_key(mm, W[nb], ibm);
+                    thr[nb] = th;
+                    uint32_t* lst = mycand + nb * kCandSlots * 64 + lane;
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        if (key[i] <= thr[nb]) {
-                            if (cnt[nb] < kCandCap) mycand[(nb * kCandCap + cnt[nb]) * 64 + lane] = key[i];
-                            ++cnt[nb];
+                    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+                        for (int i = 8 * half; i < 8 * half + 8; ++i) {
+                            if (key[i] <= th) { lst[cnt[nb] * 64] = key[i]; ++cnt[nb]; }
+                        }
+                        if (cnt[nb] > kCandCap) {
+                            // drop entries the (only decreasing) threshold has passed
+                            int w = 0;
+                            for (int q = 0; q < cnt[nb]; ++q) {
+                                const uint32_t v = lst[q * 64];
+                                if (v <= th) { lst[w * 64] = v; ++w; }
+                            }
+                            if (w > kCandCap) { ovf[nb] = 1; w = kCandCap; }
+                            cnt[nb] = w;
                         }
                     }
                 }
+            }
+            if (pref) {
+                KM_STORE_CHUNK(cur ^ 1)
+                __syncthreads();     // next buffer complete; this one no longer read
+                cur ^= 1;
             }
         }
 
@@ -299,11 +343,10 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
             const uint32_t mp = min(m[nb], (uint32_t)__shfl_xor((int)m[nb], 32));
             const uint32_t tf = thr_key(mp, W[nb], ibm);
             int vc = 0;
-            const int stored = min(cnt[nb], kCandCap);
-            for (int q = 0; q < stored; ++q) vc += (mycand[(nb * kCandCap + q) * 64 + lane] <= tf);
-            const int ovf = cnt[nb] > kCandCap;
+            const int stored = cnt[nb];
+            for (int q = 0; q < stored; ++q) vc += (mycand[(nb * kCandSlots + q) * 64 + lane] <= tf);
             const int vc_other = __shfl_xor(vc, 32);
-            const int ovf_any = ovf | __shfl_xor(ovf, 32);
+            const int ovf_any = ovf[nb] | __shfl_xor(ovf[nb], 32);
             const int64_t p = pidx[nb];
             const bool valid = p < n;
             // a winner index outside [0, k) can only come from non-finite keys: rescan
@@ -313,20 +356,29 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
                 if (a.count_changed) changed += (a.iter == 0) ? 1 : (a.labels[p] != lab);
                 a.labels[p] = lab;
             }
+            // queue slots in this block's region: one LDS atomic per wave; lanes
+            // l and l+32 share sample l's slot
+            const uint64_t need = __ballot(valid && !unique && h == 0);
             int slot = 0;
-            if (valid && !unique && h == 0) slot = atomicAdd(a.rq_count, 1);
-            slot = __shfl(slot, col);           // lane l+32 takes lane l's slot
+            if (need) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&blk_count, (int)__popcll(need));
+                base = __shfl(base, 0);
+                slot = base + (int)__popcll(need & ((1ull << col) - 1ull));
+            }
             const int base0 = __shfl(vc, col);  // candidates of the lower half come first
             if (valid && !unique) {
-                int32_t* ent = a.rq + (size_t)slot * kRqInts;
+                int32_t* ent = rq_blk + (size_t)slot * kRqInts;
                 if (h == 0) {
+                    const bool full = ovf_any || (int)(mp & ibm) >= a.k;
                     ent[0] = (int32_t)p;
-                    ent[1] = (ovf_any || (int)(mp & ibm) >= a.k) ? -1 : (vc + vc_other);
+                    ent[1] = full ? -1 : (vc + vc_other);
+                    if (full) atomicAdd(&blk_full, 1);
                 }
                 if (!ovf_any && (int)(mp & ibm) < a.k) {
                     int w = 2 + (h ? base0 : 0);
                     for (int q = 0; q < stored; ++q) {
-                        const uint32_t kq = mycand[(nb * kCandCap + q) * 64 + lane];
+                        const uint32_t kq = mycand[(nb * kCandSlots + q) * 64 + lane];
                         if (kq <= tf) ent[w++] = (int32_t)(kq & ibm);
                     }
                 }
@@ -334,6 +386,8 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
         }
     }
 
+#undef KM_LOAD_CHUNK
+#undef KM_STORE_CHUNK
     // changed-label partial of this block (fixed order)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) changed += __shfl_xor(changed, off);
@@ -343,54 +397,99 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
         int32_t c = 0;
         for (int w = 0; w < kMixWaves; ++w) c += sred[w];
         a.changed_part[blockIdx.x] = c;
+        a.rq_count[blockIdx.x] = blk_count;
+        a.rq_count[gridDim.x + blockIdx.x] = blk_full;
     }
 }
 
 // ------------------------------------------------------------ exact recheck
-// One queue entry per lane: the canonical FP32 distance (the same code as the
-// plain pass) over the entry's candidates, lexicographic (distance, index)
-// minimum; entries flagged -1 scan all k centroids in index order.
+// A group of GS lanes (GS = the chunk count rounded up to a power of two)
+// evaluates one queued sample: lane q of the group owns features 8q..8q+7, so
+// sample and centroid rows are read as contiguous 32-byte pieces.  Lane q
+// accumulates chunk q exactly as the FP32 path does (fused multiply-add from
+// 0 over its 8 features) and the chunk partials are added by the same
+// pairwise tree (chunk p += chunk p+s) through lane shuffles, so every
+// distance is bit-identical to the FP32 path's.  The winner is the
+// lexicographic (distance, index) minimum over the candidates; entries
+// flagged -1 scan all k centroids in index order.
 template <int D8>
 __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
 {
     constexpr int D = 8 * D8;
+    constexpr int GS = D8 <= 1 ? 1 : D8 <= 2 ? 2 : D8 <= 4 ? 4 : D8 <= 8 ? 8 : 16;
+    constexpr int GPW = 64 / GS;
     __shared__ int32_t sred[4];
     if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
     const int tid = threadIdx.x;
-    const int count = *a.rq_count;
+    const int lane = tid & 63;
+    const int q = lane % GS;
+    const int grp = lane / GS;
+    const int leader = lane - q;
+    // blocks (b, 0..gridDim.y-1) re-check the entries queued by block b of
+    // the MFMA pass
+    const int count = a.rq_count[blockIdx.x];
+    const int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * kRqInts;
+    const int wave_id = blockIdx.y * 4 + (tid >> 6);
+    const int nwaves = gridDim.y * 4;
     int32_t changed = 0;
-    for (int e = blockIdx.x * 256 + tid; e < count; e += gridDim.x * 256) {
-        const int32_t* ent = a.rq + (size_t)e * kRqInts;
+    for (int e0 = wave_id * GPW; e0 < count; e0 += nwaves * GPW) {
+        const int e = e0 + grp;
+        const bool valid = e < count;
+        const int32_t* ent = rq_blk + (size_t)(valid ? e : 0) * kRqInts;
         const int64_t p = ent[0];
-        const int nc = ent[1];
-        float x[1][D];
-        load_row<D8>(a.X + p * a.d, a.d, true, x[0]);
+        const int nc = valid ? ent[1] : 0;
+        // this lane's 8 features of the sample
+        float x[8];
+        const float* xr = a.X + p * a.d + 8 * q;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = (valid && q < D8 && 8 * q + i < a.d) ? xr[i] : 0.0f;
+        // trip count: the longest candidate list of the wave
+        int trips = nc < 0 ? a.k : nc;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) trips = max(trips, __shfl_xor(trips, off));
         float best = __builtin_huge_valf();
         int bj = 0;
-        if (nc < 0) {
-            for (int j = 0; j < a.k; ++j) {
-                float dist[1];
-                dist_rows<D8, 1>(x, a.Cp + (size_t)j * D, dist);
-                if (dist[0] < best) { best = dist[0]; bj = j; }
+        constexpr int TB = 4;                // candidates in flight per group
+        for (int t0 = 0; t0 < trips; t0 += TB) {
+            float cv[TB][8];
+            int jj[TB];
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                const int t = t0 + u;
+                const int j = (nc < 0) ? (t < a.k ? t : -1) : (t < nc ? ent[2 + t] : -1);
+                jj[u] = (valid && j >= 0 && j < a.k) ? j : -1;
+                const float* cr = a.Cp + (size_t)(jj[u] >= 0 ? jj[u] : 0) * D + 8 * q;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) cv[u][i] = (q < D8) ? cr[i] : 0.0f;
             }
-        } else {
-            bj = 0;
-            for (int q = 0; q < nc; ++q) {
-                const int j = ent[2 + q];
-                if (j < 0 || j >= a.k) continue;
-                float dist[1];
-                dist_rows<D8, 1>(x, a.Cp + (size_t)j * D, dist);
-                if (dist[0] < best || (dist[0] == best && j < bj)) { best = dist[0]; bj = j; }
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                float part = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float df = x[i] - cv[u][i];
+                    part = __builtin_fmaf(df, df, part);
+                }
+#pragma unroll
+                for (int s = 1; s < D8; s *= 2) {
+                    const float other = __shfl(part, lane + s < 64 ? lane + s : lane);
+                    if ((q % (2 * s)) == 0 && q + s < D8) part = part + other;
+                }
+                const float dist = __shfl(part, leader);
+                const int j = jj[u];
+                if (j >= 0 && (dist < best || (dist == best && j < bj))) { best = dist; bj = j; }
             }
         }
-        if (a.count_changed) changed += (a.iter == 0) ? 1 : (a.labels[p] != bj);
-        a.labels[p] = bj;
+        if (valid && q == 0) {
+            if (a.count_changed) changed += (a.iter == 0) ? 1 : (a.labels[p] != bj);
+            a.labels[p] = bj;
+        }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) changed += __shfl_xor(changed, off);
     if ((tid & 63) == 0) sred[tid >> 6] = changed;
     __syncthreads();
-    if (tid == 0) a.changed_part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+    if (tid == 0) a.changed_part[blockIdx.y * gridDim.x + blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -405,18 +504,18 @@ hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, 
 }
 
 hipError_t launch_prep_c(const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
-                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, int32_t* rq_count,
-                         const Ctrl* ctrl, int32_t iter, hipStream_t s)
+                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(prep_c_kernel, dim3(1), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs, Ab, bias, cs, rq_count,
-                       ctrl, iter);
+    hipLaunchKernelGGL(prep_c_kernel, dim3(1), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs, Ab, bias, cs, ctrl, iter);
     return hipGetLastError();
 }
 
 size_t mfma_lds_bytes(int D16)
 {
     const size_t rowb = (size_t)D16 * 16 * 2 + 16;
-    return kMixCK * rowb + kMixCK * sizeof(float) + (size_t)kMixWaves * kMixNB * kCandCap * 64 * sizeof(uint32_t);
+    return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
+           (size_t)kMixWaves * kMixNB * kCandSlots * 64 * sizeof(uint32_t);
 }
 
 template <int D16>
@@ -475,7 +574,7 @@ int mfma_blocks_per_cu(int D16)
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s)
 {
     switch (D8) {
-#define KM_RC(N) case N: hipLaunchKernelGGL((recheck_kernel<N>), dim3(grid), dim3(256), 0, s, a); break;
+#define KM_RC(N) case N: hipLaunchKernelGGL((recheck_kernel<N>), dim3(grid, kRecheckSplit), dim3(256), 0, s, a); break;
     KM_RC(1) KM_RC(2) KM_RC(3) KM_RC(4) KM_RC(5) KM_RC(6) KM_RC(7) KM_RC(8)
     KM_RC(9) KM_RC(10) KM_RC(11) KM_RC(12) KM_RC(13) KM_RC(14) KM_RC(15) KM_RC(16)
 #undef KM_RC

@@ -27,53 +27,109 @@
 
 namespace km {
 
-__device__ __forceinline__ void lds_add_f64(double* p, double v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
-// Add the samples of one 64-sample group that wave `wave` owns to the block's
-// activation record, in increasing sample order, eight rows in flight.
-template <int D8>
-__device__ __forceinline__ void accumulate_group(const float* __restrict__ Xg, int d, int lab_lane,
-                                                 uint64_t mask, double* S, int32_t* cnt, int lane)
+// "process": add the tile's samples that this wave owns (label L with
+// L % 4 == wave) to the block's activation record.
+//  1. list the owned samples in increasing sample order (entry = (L << 12) |
+//     offset in the tile) and count them per label (integer LDS adds);
+//  2. turn the counts into run starts (prefix over the wave's labels) and
+//     stable-scatter the list into label order: for each 64-entry chunk, the
+//     distinct labels are taken one by one and their entries placed in lane
+//     order after the run's cursor;
+//  3. walk the sorted list 16 rows at a time (lane f loads feature f of each
+//     row, coalesced): a register accumulates the current label's run and is
+//     added into the LDS record once per run.
+// Only this wave touches these labels; every sum has a fixed order (the
+// block's tiles in order, the tile's samples in order within a run).
+template <int D8, int TILE>
+__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, int kc, const int32_t* lb,
+                                                int32_t* wl, int32_t* ws, int32_t* cur, double* S, int32_t* cnt,
+                                                int lane, int wave)
 {
     constexpr int FPL = (8 * D8 + 63) / 64;  // features per lane
-    constexpr int B = 8;
-    while (mask) {
-        int p[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            if (mask) {
-                p[u] = __builtin_ctzll(mask);
-                mask &= mask - 1;
-            } else {
-                p[u] = -1;
-            }
+    constexpr int B = 16;
+    const int nlab = (kc - wave + kWaves - 1) / kWaves;   // labels this wave owns: L = 4 ll + wave
+    for (int ll = lane; ll < nlab; ll += 64) cur[ll * kWaves + wave] = 0;
+    int nown = 0;
+#pragma unroll 4
+    for (int g = 0; g < TILE / 64; ++g) {
+        const int L = lb[g * 64 + lane];
+        const bool own = L >= 0 && (L & (kWaves - 1)) == wave;
+        const uint64_t mask = __ballot(own);
+        if (own) {
+            wl[nown + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0))] =
+                (L << 12) | (g * 64 + lane);
+            __hip_atomic_fetch_add(cur + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        nown += __popcll(mask);
+    }
+    if (nown == 0) return;
+    // counts -> record counts, then exclusive prefix (run starts) in label order
+    int carry = 0;
+    for (int c0 = 0; c0 < nlab; c0 += 64) {
+        const int ll = c0 + lane;
+        const int L = ll * kWaves + wave;
+        const int c = ll < nlab ? cur[L] : 0;
+        if (ll < nlab && c) cnt[L] += c;
+        int incl = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (ll < nlab) cur[L] = carry + incl - c;
+        carry += __shfl(incl, 63);
+    }
+    // stable scatter into label order
+    for (int c0 = 0; c0 < nown; c0 += 64) {
+        const int ent = (c0 + lane < nown) ? wl[c0 + lane] : -1;
+        const int L = ent >= 0 ? (ent >> 12) : -1;
+        uint64_t rem = __ballot(L >= 0);
+        const uint64_t lt = (1ull << lane) - 1ull;
+        while (rem) {
+            const int Lx = __builtin_amdgcn_readlane(L, (int)__builtin_ctzll(rem));
+            const uint64_t m = __ballot(L == Lx);
+            const int base = cur[Lx];
+            if (L == Lx) ws[base + (int)__popcll(m & lt)] = ent;
+            if (lane == (int)__builtin_ctzll(m)) cur[Lx] = base + (int)__popcll(m);
+            rem &= ~m;
+        }
+    }
+    // runs
+    double acc[FPL];
+#pragma unroll
+    for (int mm = 0; mm < FPL; ++mm) acc[mm] = 0.0;
+    for (int i0 = 0; i0 < nown; i0 += B) {
+        const int mine = (lane < B && i0 + lane < nown) ? ws[i0 + lane] : -1;
+        const int nxt_first = (i0 + B < nown) ? ws[i0 + B] : -1;   // uniform: first entry of the next batch
         float v[B][FPL];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            if (p[u] >= 0) {
-                const float* row = Xg + (int64_t)p[u] * d;
+            const int ent = __builtin_amdgcn_readlane(mine, u);
+            const float* row = Xt + (int64_t)(ent >= 0 ? (ent & 4095) : 0) * d;
 #pragma unroll
-                for (int m = 0; m < FPL; ++m) {
-                    const int f = lane + 64 * m;
-                    v[u][m] = (f < d) ? row[f] : 0.0f;
-                }
+            for (int mm = 0; mm < FPL; ++mm) {
+                const int f = lane + 64 * mm;
+                v[u][mm] = (f < d) ? row[f] : 0.0f;
             }
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            if (p[u] >= 0) {
-                const int L = __builtin_amdgcn_readlane(lab_lane, p[u]);
-                double* s = S + (size_t)L * d;
+            const int ent = __builtin_amdgcn_readlane(mine, u);
+            if (ent >= 0) {
 #pragma unroll
-                for (int m = 0; m < FPL; ++m) {
-                    const int f = lane + 64 * m;
-                    if (f < d) lds_add_f64(s + f, (double)v[u][m]);
+                for (int mm = 0; mm < FPL; ++mm) acc[mm] += (double)v[u][mm];
+                const int nx = (u + 1 < B) ? __builtin_amdgcn_readlane(mine, u + 1) : nxt_first;
+                const int L = ent >> 12;
+                if (nx < 0 || (nx >> 12) != L) {      // end of this label's run: into the record
+                    double* srow = S + (size_t)L * d;
+#pragma unroll
+                    for (int mm = 0; mm < FPL; ++mm) {
+                        const int f = lane + 64 * mm;
+                        if (f < d) srow[f] = srow[f] + acc[mm];
+                        acc[mm] = 0.0;
+                    }
                 }
-                if (lane == 0) __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
     }
@@ -95,13 +151,17 @@ __device__ __forceinline__ void nearest(const float (&x)[R][8 * D8], CP C, int k
     }
 }
 
+// The per-sample pass of one block: tiles t_first, t_first + t_step, ... below
+// t_end, its activation record written to partial slot `slot`; `chunk` is the
+// label chunk of update passes over chunked records.
 template <int D8, int MODE>
-__global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
+__device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
+                                          int slot, int chunk, unsigned char* smem)
 {
     constexpr int D = 8 * D8;
-    constexpr int R = plain_rows_per_lane(D8);
+    constexpr int R = (MODE == MODE_UPDATE_WIDE) ? kUpdateRows : plain_rows_per_lane(D8);
+    constexpr bool UPD = (MODE == MODE_UPDATE || MODE == MODE_UPDATE_WIDE);
     constexpr int TILE = kBlock * R;
-    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double redJ[kWaves];
     __shared__ int32_t redC[kWaves];
     __shared__ int32_t redB[kWaves];
@@ -114,12 +174,15 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
     const int k = a.k, d = a.d;
     const int64_t n = a.n;
     // Label chunk of this block (update / fused passes): labels [j0, j0 + kc).
-    const int j0 = (MODE == MODE_UPDATE) ? (int)blockIdx.y * a.kc : 0;
-    const int kc = (MODE == MODE_UPDATE) ? min(a.kc, k - j0) : k;
+    const int j0 = UPD ? chunk * a.kc : 0;
+    const int kc = UPD ? min(a.kc, k - j0) : k;
 
     double* S = reinterpret_cast<double*>(smem);
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
-    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);
+    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [2][TILE] labels of a tile
+    int32_t* wlist = lbl + 2 * TILE;                           // [kWaves][TILE] per-wave lists
+    int32_t* wsort = wlist + kWaves * TILE;                    // [kWaves][TILE] the lists in label order
+    int32_t* cursor = wsort + kWaves * TILE;                   // [kc] per-label counts / run cursors
 
     // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
@@ -131,11 +194,12 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
     double Jl = 0.0;
     int32_t changed = 0, bad = 0;
     const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     int buf = 0;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = t_first; t < t_last; t += t_step) {
         // lane holds samples t*TILE + r*256 + tid, r < R
         int lab[R];
-        if (MODE == MODE_UPDATE) {
+        if (UPD) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t gp = t * TILE + r * kBlock + tid;
@@ -176,21 +240,16 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) lb[r * kBlock + tid] = lab[r];
             __syncthreads();
-            const float* Xt = a.X + t * TILE * (int64_t)d;
-#pragma unroll 1
-            for (int g = 0; g < TILE / 64; ++g) {
-                const int L = lb[g * 64 + lane];
-                const uint64_t mask = __ballot(L >= 0 && (L & (kWaves - 1)) == wave);
-                accumulate_group<D8>(Xt + (int64_t)g * 64 * d, d, L, mask, S, cnt, lane);
-            }
+            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, kc, lb, wlist + wave * TILE,
+                                      wsort + wave * TILE, cursor, S, cnt, lane, wave);
             buf ^= 1;
         }
     }
 
-    // Merge once per block: the activation record goes to slot blockIdx.x,
+    // Merge once per block: the activation record goes to slot `slot`,
     // labels [j0, j0 + kc) of it.
     __syncthreads();
-    const int b = blockIdx.x;
+    const int b = slot;
     if (MODE != MODE_ASSIGN) {
         double* dst = a.part.S + (size_t)b * k * d + (size_t)j0 * d;
         for (int e = tid; e < kc * d; e += kBlock) dst[e] = S[e];
@@ -211,12 +270,32 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
         double J = redJ[0];
         int32_t c = redC[0], bb = redB[0];
         for (int w = 1; w < kWaves; ++w) { J += redJ[w]; c += redC[w]; bb += redB[w]; }
-        if (MODE != MODE_UPDATE) {
+        if (!UPD) {
             a.part.J[b] = J;
             a.part.changed[b] = c;
         }
-        if (blockIdx.y == 0) a.part.bad[b] = bb;
+        if (chunk == 0) a.part.bad[b] = bb;
     }
+}
+
+template <int D8, int MODE>
+__global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass_body<D8, MODE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, blockIdx.y, smem);
+}
+
+// Batched instances: block b runs tiles [t0, t1) of instance work[b].inst into
+// that instance's partial slot work[b].slot.
+template <int D8>
+__global__ __launch_bounds__(kBlock) void batch_pass(const BatchWork* __restrict__ work,
+                                                     const PassArgs* __restrict__ insts, int32_t iter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchWork w = work[blockIdx.x];
+    PassArgs a = insts[w.inst];
+    a.iter = iter;
+    pass_body<D8, MODE_FUSED>(a, w.t0, w.t1, 1, w.slot, 0, smem);
 }
 
 template <int D8, int MODE>
@@ -235,12 +314,14 @@ static hipError_t launch_d8(Mode mode, const PassArgs& a, dim3 grid, size_t lds,
     switch (mode) {
     case MODE_ASSIGN: e = allow_lds<D8, MODE_ASSIGN>(lds); break;
     case MODE_UPDATE: e = allow_lds<D8, MODE_UPDATE>(lds); break;
+    case MODE_UPDATE_WIDE: e = allow_lds<D8, MODE_UPDATE_WIDE>(lds); break;
     case MODE_FUSED:  e = allow_lds<D8, MODE_FUSED>(lds); break;
     }
     if (e != hipSuccess) return e;
     switch (mode) {
     case MODE_ASSIGN: hipLaunchKernelGGL((plain_pass<D8, MODE_ASSIGN>), grid, dim3(kBlock), lds, s, a); break;
     case MODE_UPDATE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE>), grid, dim3(kBlock), lds, s, a); break;
+    case MODE_UPDATE_WIDE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE_WIDE>), grid, dim3(kBlock), lds, s, a); break;
     case MODE_FUSED:  hipLaunchKernelGGL((plain_pass<D8, MODE_FUSED>), grid, dim3(kBlock), lds, s, a); break;
     }
     return hipGetLastError();
@@ -254,6 +335,7 @@ static int occupancy_d8(Mode mode, size_t lds)
     switch (mode) {
     case MODE_ASSIGN: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_ASSIGN>, kBlock, lds); break;
     case MODE_UPDATE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_UPDATE>, kBlock, lds); break;
+    case MODE_UPDATE_WIDE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_UPDATE_WIDE>, kBlock, lds); break;
     case MODE_FUSED:  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_FUSED>, kBlock, lds); break;
     }
     return e == hipSuccess ? nb : -1;
@@ -267,6 +349,31 @@ int plain_blocks_per_cu(int D8, Mode mode, size_t lds)
     KM_OCC(9) KM_OCC(10) KM_OCC(11) KM_OCC(12) KM_OCC(13) KM_OCC(14) KM_OCC(15) KM_OCC(16)
 #undef KM_OCC
     default: return -1;
+    }
+}
+
+template <int D8>
+static hipError_t launch_batch_d8(const BatchWork* work, int nwork, const PassArgs* insts, int iter, size_t lds,
+                                  hipStream_t s)
+{
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_pass<D8>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((batch_pass<D8>), dim3(nwork), dim3(kBlock), lds, s, work, insts, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(int D8, const BatchWork* work, int nwork, const PassArgs* insts, int iter, size_t lds,
+                             hipStream_t s)
+{
+    switch (D8) {
+#define KM_BP(N) case N: return launch_batch_d8<N>(work, nwork, insts, iter, lds, s);
+    KM_BP(1) KM_BP(2) KM_BP(3) KM_BP(4) KM_BP(5) KM_BP(6) KM_BP(7) KM_BP(8)
+    KM_BP(9) KM_BP(10) KM_BP(11) KM_BP(12) KM_BP(13) KM_BP(14) KM_BP(15) KM_BP(16)
+#undef KM_BP
+    default: return hipErrorInvalidValue;
     }
 }
 

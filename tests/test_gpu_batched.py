@@ -1,0 +1,144 @@
+"""Batched Lloyd: many instances of different n, d, k in the same launches
+(needs an MI355X).  Each instance is checked stepwise against the FP64 oracle
+(labels under the near-tie rule, centroids from the oracle's update of the
+GPU's labels, counts exact, objective within 1e-5), and graph replays against
+direct launches."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1109_0778_amd import datagen
+from test_gpu_plain import REL_TOL, _bind, _torch, check_centroids, check_labels, say
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(torch, B, shapes, seed0=0, iters=4):
+    dev = torch.device("cuda")
+    inst, host = [], []
+    for i, (n, d, k) in enumerate(shapes):
+        X, C = datagen.blobs(n, d, k, k, 1.0, seed=seed0 + i)
+        host.append((X, C))
+        inst.append({"X": torch.from_numpy(X).to(dev), "C": torch.from_numpy(C).to(dev),
+                     "labels": torch.full((n,), -1, dtype=torch.int32, device=dev),
+                     "counts": torch.empty(k, dtype=torch.int64, device=dev),
+                     "obj_hist": torch.zeros(iters, dtype=torch.float64, device=dev)})
+    return inst, host
+
+
+SHAPES = [(1000, 16, 4), (257, 32, 7), (5000, 64, 128), (12345, 16, 60), (3000, 33, 17), (700, 8, 9),
+          (40000, 64, 100), (2048, 128, 20), (1, 5, 1), (999, 1, 3), (65536, 32, 64), (300, 64, 128)]
+
+
+def test_batched_stepwise_against_oracle():
+    torch, B = _torch(), _bind()
+    inst, host = make_batch(torch, B, SHAPES)
+    batch = B.Batch(inst)
+    Cs = [C.copy() for _, C in host]
+    for t in range(3):
+        B.kmeans_lloyd_batched(batch, 1)
+        torch.cuda.synchronize()
+        for i, ((X, _), ti) in enumerate(zip(host, inst)):
+            say(f"t={t} instance {i} shape {X.shape} k={Cs[i].shape[0]}")
+            lab = ti["labels"].cpu().numpy()
+            _, _, J, _, _ = check_labels(lab, Cs[i], X, f"instance {i} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(ti["counts"].cpu().numpy(), cnto)
+            Cg = ti["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"instance {i} t={t}")
+            assert abs(ti["obj_hist"][0].item() - J) <= REL_TOL * J + 1e-30
+            Cs[i] = Cg
+
+
+@pytest.mark.parametrize("tpb,order", [(1, 0), (3, 1), (64, 1)])
+def test_batched_schedules_and_graphs(tpb, order):
+    """Any schedule gives oracle-valid results; with a fixed schedule the graph
+    replays equal direct launches bit for bit, replay after replay."""
+    torch, B = _torch(), _bind()
+    inst, host = make_batch(torch, B, SHAPES[:8], seed0=50, iters=3)
+    inst2, _ = make_batch(torch, B, SHAPES[:8], seed0=50, iters=3)
+    b1 = B.Batch(inst)
+    b2 = B.Batch(inst2)
+    b1.set_schedule(tpb, order)
+    b2.set_schedule(tpb, order)
+    b2.use_graphs(True)
+    for rep in range(3):
+        B.kmeans_lloyd_batched(b1, 3)
+        torch.cuda.synchronize()
+        B.kmeans_lloyd_batched(b2, 3)
+        torch.cuda.synchronize()
+        for a, b in zip(inst, inst2):
+            assert torch.equal(a["C"], b["C"]) and torch.equal(a["labels"], b["labels"]), f"replay {rep}"
+            assert torch.equal(a["counts"], b["counts"]) and torch.equal(a["obj_hist"], b["obj_hist"])
+
+
+def test_batched_equals_single_instance_path_statistically():
+    """The same instance alone (kmeans_lloyd) and inside a batch: identical
+    labels and centroids within one FP32 ulp after the same iterations (the
+    two differ only in how samples are grouped into FP64 partial sums)."""
+    torch, B = _torch(), _bind()
+    inst, host = make_batch(torch, B, SHAPES[:6], seed0=80, iters=2)
+    batch = B.Batch(inst)
+    B.kmeans_lloyd_batched(batch, 2)
+    torch.cuda.synchronize()
+    for (X, C0), ti in zip(host, inst):
+        n, d = X.shape
+        k = C0.shape[0]
+        plan = B.Plan(n, d, k)
+        Cg = torch.from_numpy(C0).cuda()
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        B.kmeans_lloyd(plan, torch.from_numpy(X).cuda(), Cg, lab, None, None, 2)
+        torch.cuda.synchronize()
+        a, b = Cg.cpu().numpy(), ti["C"].cpu().numpy()
+        ulp = np.spacing(np.abs(a)).astype(np.float32)
+        assert np.all(np.abs(a - b) <= ulp)
+
+
+def test_batched_rejects_bad_instances():
+    torch, B = _torch(), _bind()
+    dev = torch.device("cuda")
+    good = {"X": torch.zeros(100, 4, device=dev), "C": torch.zeros(3, 4, device=dev),
+            "labels": torch.zeros(100, dtype=torch.int32, device=dev)}
+    bad = {"X": torch.zeros(10, 4, device=dev), "C": torch.zeros(11, 4, device=dev),
+           "labels": torch.zeros(10, dtype=torch.int32, device=dev)}
+    with pytest.raises(B.KMeansError) as e:
+        B.Batch([good, bad])
+    assert e.value.status == B.KM_EINVAL
+    with pytest.raises(B.KMeansError) as e:
+        B.Batch([good], precision="fp8")
+    assert e.value.status == B.KM_ENOTSUP
+
+
+@pytest.mark.slow
+def test_batched_workload_sampled():
+    """The 512-instance workload (n log-uniform in [1e3, 2e5], d in {16, 32,
+    64}, k uniform in [4, 128], seeds 0..511), autotuned and graph-launched as
+    the benchmark runs it: 24 iterations, then iteration 25 checked against the
+    oracle on a fixed sample of 24 instances."""
+    torch, B = _torch(), _bind()
+    from paper_1109_0778_amd import autotune
+    dev = torch.device("cuda")
+    inst, host = [], []
+    for s in range(datagen.BATCH_COUNT):
+        shp, X, C = datagen.batch_instance(s)
+        host.append((X, C))
+        inst.append({"X": torch.from_numpy(X).to(dev), "C": torch.from_numpy(C).to(dev),
+                     "labels": torch.empty(shp.n, dtype=torch.int32, device=dev),
+                     "counts": torch.empty(shp.k, dtype=torch.int64, device=dev),
+                     "obj_hist": torch.zeros(datagen.BATCH_ITERS, dtype=torch.float64, device=dev)})
+    batch = B.Batch(inst)
+    choice, _ = autotune.tune_batch(batch, use_cache=False)
+    say(f"autotuned schedule {choice}")
+    batch.use_graphs(True)
+    B.kmeans_lloyd_batched(batch, datagen.BATCH_ITERS - 1)
+    torch.cuda.synchronize()
+    C24 = [t["C"].cpu().numpy() for t in inst]
+    B.kmeans_lloyd_batched(batch, 1)
+    torch.cuda.synchronize()
+    for i in np.random.default_rng(0).choice(len(inst), 24, replace=False):
+        X = host[i][0]
+        lab = inst[i]["labels"].cpu().numpy()
+        check_labels(lab, C24[i], X, f"instance {i}")
+        Co, cnto = oracle.update(X, lab, C24[i].astype(np.float64))
+        assert np.array_equal(inst[i]["counts"].cpu().numpy(), cnto)
+        check_centroids(inst[i]["C"].cpu().numpy(), Co, X, f"instance {i}")

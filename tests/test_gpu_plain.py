@@ -304,3 +304,40 @@ def test_plain_workload_full_size_sampled():
     _, _, _, J = oracle.assign(X, a["C"].astype(np.float64))
     assert abs(g["J"][0] - J) <= REL_TOL * J
     assert np.all(np.diff(full["J"]) <= 1e-6 * full["J"][:-1])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_graph_replays_match_direct_launches(precision):
+    """kmeans_lloyd captured into a HIP graph: several replays, with direct
+    work and synchronisations in between, each equal to a direct call."""
+    torch, B = _torch(), _bind()
+    dev = torch.device("cuda")
+    X, C0 = datagen.blobs(20000, 24, 30, 30, 1.5, seed=21)
+    n, d = X.shape
+    k = C0.shape[0]
+    Xg = torch.from_numpy(X).to(dev)
+    ref = B.Plan(n, d, k, precision)
+    gp = B.Plan(n, d, k, precision)
+    gp.use_graphs(True)
+    C_ref = torch.from_numpy(C0).to(dev)
+    C_g = torch.from_numpy(C0).to(dev)
+    lab_r = torch.empty(n, dtype=torch.int32, device=dev)
+    lab_g = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt_r = torch.empty(k, dtype=torch.int64, device=dev)
+    cnt_g = torch.empty(k, dtype=torch.int64, device=dev)
+    h_r = torch.empty(3, dtype=torch.float64, device=dev)
+    h_g = torch.empty(3, dtype=torch.float64, device=dev)
+    for rep in range(4):
+        B.kmeans_lloyd(ref, Xg, C_ref, lab_r, cnt_r, h_r, 3, -1.0)
+        torch.cuda.synchronize()
+        B.kmeans_lloyd(gp, Xg, C_g, lab_g, cnt_g, h_g, 3, -1.0)   # capture on rep 0, replay after
+        torch.cuda.synchronize()
+        _ = (Xg[:100] * 2).sum().item()                           # unrelated direct work in between
+        assert torch.equal(C_g, C_ref) and torch.equal(lab_g, lab_r), f"replay {rep}"
+        assert torch.equal(cnt_g, cnt_r) and torch.equal(h_g, h_r), f"replay {rep}"
+    # tolerance mode through the graph: iterations done come back each replay
+    C_a = torch.from_numpy(C0).to(dev)
+    C_b = torch.from_numpy(C0).to(dev)
+    it_a = B.kmeans_lloyd(ref, Xg, C_a, lab_r, None, None, 50, 0.0)
+    it_b = B.kmeans_lloyd(gp, Xg, C_b, lab_g, None, None, 50, 0.0)
+    assert it_a == it_b and torch.equal(C_a, C_b)
