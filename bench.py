@@ -5,7 +5,9 @@ One step = one Lloyd iteration over the whole input: the per-sample pass
 (distances to every centroid, argmin label, per-label FP64 sums and counts,
 objective) and the finalize (fixed-order combine, mean, empty-cluster rule),
 all inside one kmeans_lloyd call of STEPS iterations with the input already
-resident in HBM.  Default workload: n = 2^20 samples, d = 64, k = 64, 64
+resident in HBM.  The call is timed twice, launched directly and as one
+captured graph; the headline takes the faster when both give identical
+results.  Default workload: n = 2^20 samples, d = 64, k = 64, 64
 Gaussian blobs (sigma 1, centres uniform in [-10, 10]^d, seed 1), k initial
 centroids sampled without replacement, 20 iterations, FP32 distances.
 
@@ -19,6 +21,8 @@ throughput it carries:
                  MFMA pass on the MFMA or HBM roofline;
   bf16_workload  FP32 and BF16 on n = 2^22, d = 128, k = 1024 (1024 blobs,
                  sigma 2, seed 2, 20 iterations);
+  fp8_workload   FP32, FP8 and BF16 on n = 2^24, d = 32, k = 256 (256
+                 anisotropic blobs, seed 3, 15 iterations);
   batched_workload  512 independent instances advanced together (autotuned
                  schedule, one graph launch), next to per-instance calls;
   cpu_baseline   the FP64 oracle timed on this host's cores on a bounded sample
@@ -102,38 +106,70 @@ def timed_lloyd(B, torch, X, C0, precision, steps, warmup):
     return res
 
 
-MFMA_BF16_PEAK_TFLOPS = 2500.0
+def timed_lloyd_graph(B, torch, X, C0, precision, steps):
+    """The same call launched as one captured graph: the first call captures
+    and runs it, the second (same arguments, C reset to C0) is timed."""
+    n, d = X.shape
+    k = C0.shape[0]
+    dev = torch.device("cuda", 0)
+    Xg = torch.from_numpy(X).to(dev)
+    C0g = torch.from_numpy(C0).to(dev)
+    plan = B.Plan(n, d, k, precision)
+    plan.use_graphs(True)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    counts = torch.empty(k, dtype=torch.int64, device=dev)
+    hist = torch.empty(max(steps, 1), dtype=torch.float64, device=dev)
+    C = C0g.clone()
+    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
+    torch.cuda.synchronize()
+    C.copy_(C0g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = {"el": el, "C": C.cpu().numpy(), "labels": labels.cpu().numpy()}
+    del plan, Xg
+    torch.cuda.empty_cache()
+    return res
 
 
-def mixed_report(B, torch, w, X, C0, steps, warmup, fp):
-    """BF16-MFMA path on the same input: throughput, equality of its labels
-    and centroids with the FP32 run, recheck fraction, and the MFMA pass on
-    its roofline (MFMA or HBM, whichever the shape is bound by)."""
+# dense MFMA peaks of MI355X (no sparsity), TFLOP/s
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
+
+
+def mixed_report(B, torch, w, X, C0, steps, warmup, fp, precision="bf16"):
+    """A mixed-precision path on the same input: throughput, equality of its
+    labels and centroids with the FP32 run, recheck fraction, and the MFMA
+    pass on its roofline (MFMA or HBM, whichever the shape is bound by)."""
     import numpy as np
-    mx = timed_lloyd(B, torch, X, C0, "bf16", steps, warmup)
+    mx = timed_lloyd(B, torch, X, C0, precision, steps, warmup)
     kmean_ms = float(np.mean(mx["kt"]))
     flops = 2.0 * w.n * w.k * w.d
-    nbytes = w.n * w.d * 4 + 2 * w.n * 4
+    # BF16 reads FP32 X; FP8 reads its e4m3 copy (d bytes padded to 16) and 8 bytes of band inputs
+    dq = (w.d + 15) // 16 * 16
+    nbytes = (w.n * w.d * 4 if precision == "bf16" else w.n * (dq + 8)) + 2 * w.n * 4
+    peak = MFMA_PEAK_TFLOPS[precision]
     tflops = flops / (kmean_ms * 1e-3) / 1e12
     gbps = nbytes / (kmean_ms * 1e-3) / 1e9
     ai = flops / nbytes
-    bound = "mfma" if ai > MFMA_BF16_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBPS * 1e9) else "hbm"
+    bound = "mfma" if ai > peak * 1e12 / (HBM_PEAK_GBPS * 1e9) else "hbm"
     if bound == "mfma":
-        roof = {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tflops / MFMA_BF16_PEAK_TFLOPS}
+        roof = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak}
     else:
         roof = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": gbps / HBM_PEAK_GBPS}
-    roof.update({"kernel": "mfma_assign_bf16 (BF16 MFMA distances, key min, candidate band)",
+    roof.update({"kernel": f"mfma_assign<{precision}> (MFMA distances, key min, candidate band)",
                  "traffic": None, "flops_per_launch": flops, "bytes_per_launch": nbytes,
                  "mean_launch_ms": kmean_ms, "launches": len(mx["kt"]),
                  "mfma_tflops": tflops, "hbm_gbps": gbps})
     same_labels = bool(np.array_equal(mx["labels"], fp["labels"]))
     same_c = bool(np.array_equal(mx["C"], fp["C"]))
-    log(f"bf16 on {w.name}: {steps} iterations in {mx['el'] * 1e3:.2f} ms (fp32 {fp['el'] * 1e3:.2f} ms); "
+    log(f"{precision} on {w.name}: {steps} iterations in {mx['el'] * 1e3:.2f} ms (fp32 {fp['el'] * 1e3:.2f} ms); "
         f"MFMA pass {kmean_ms * 1e3:.1f} us; labels equal {same_labels}, centroids equal {same_c}; "
         f"recheck {mx['recheck']} of {w.n} ({mx['full_scans']} full scans)")
-    return {"value": steps / mx["el"], "unit": "Lloyd iters/s", "ms_per_step": mx["el"] * 1e3 / steps,
+    return {"precision": precision, "value": steps / mx["el"], "unit": "Lloyd iters/s",
+            "ms_per_step": mx["el"] * 1e3 / steps,
             "fp32_value": steps / fp["el"], "speedup_vs_fp32": fp["el"] / mx["el"],
             "dist_evals_per_s": w.n * w.k * steps / mx["el"],
             "labels_equal_fp32": same_labels, "centroids_equal_fp32": same_c,
@@ -247,6 +283,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-MFMA comparison")
     ap.add_argument("--no-bf16-workload", action="store_true",
                     help="skip the n=2^22, d=128, k=1024 mixed-precision workload")
+    ap.add_argument("--no-fp8-workload", action="store_true",
+                    help="skip the n=2^24, d=32, k=256 FP8 workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -283,6 +321,13 @@ def main():
     traffic = measured_traffic(f"{w.name}:{w.n}x{w.d}x{w.k}")
     log(f"fp32: {steps} iterations in {el * 1e3:.2f} ms; per-sample pass mean {kmean_ms * 1e3:.1f} us "
         f"over {len(kt)} launches; J[0]={J[0]:.6e} J[-1]={J[-1]:.6e}")
+    # the same call as one graph launch; the headline takes it when it matches the direct run
+    gr = timed_lloyd_graph(B, torch, X, C0, "fp32", steps)
+    graph_ok = bool(np.array_equal(gr["C"], fp["C"]) and np.array_equal(gr["labels"], fp["labels"]))
+    log(f"fp32 graph launch: {steps} iterations in {gr['el'] * 1e3:.2f} ms (equal to direct: {graph_ok})")
+    el_direct = el
+    if graph_ok and gr["el"] < el:
+        el = gr["el"]
 
     out = {
         "metric": "Lloyd iters/s and point-centroid dist evals/s; mixed vs FP32 at equal labels",
@@ -301,6 +346,10 @@ def main():
                                f"sigma={w.sigma}, centres U[-10,10]^d, seed {w.seed}, init={w.init}, "
                                f"{w.iters} iterations",
                    "n": w.n, "d": w.d, "k": w.k, "iters": steps, "precision": "fp32"},
+        "launch": "graph" if el != el_direct else "direct",
+        "ms_per_step_direct": el_direct * 1e3 / steps,
+        "ms_per_step_graph": gr["el"] * 1e3 / steps,
+        "graph_equals_direct": graph_ok,
         "dist_evals_per_s": w.n * w.k * steps / el,
         "hbm_gbps_algorithmic": algo_bytes * steps / el / 1e9,
         "roofline": {
@@ -330,6 +379,18 @@ def main():
                                f"seed {wb.seed}, {wb.iters} iterations")
             out["bf16_workload"] = rep
             del Xb, Cb
+        if args.workload == "plain" and not args.no_fp8_workload:
+            w8 = datagen.WORKLOADS["fp8"]
+            log(f"fp8 workload: n={w8.n} d={w8.d} k={w8.k}")
+            X8, C8 = datagen.workload("fp8")
+            fp8 = timed_lloyd(B, torch, X8, C8, "fp32", w8.iters, 1)
+            rep = {"workload": (f"fp8: n={w8.n}, d={w8.d}, k={w8.k}, {w8.blobs} anisotropic blobs "
+                                f"(per-blob per-feature sigma U[0.5,3]), seed {w8.seed}, {w8.iters} iterations"),
+                   "fp32_value": w8.iters / fp8["el"], "unit": "Lloyd iters/s"}
+            for prec in ("fp8", "bf16"):
+                rep[prec] = mixed_report(B, torch, w8, X8, C8, w8.iters, 1, fp8, prec)
+            out["fp8_workload"] = rep
+            del X8, C8
     if not args.no_batched and args.workload == "plain":
         from paper_1109_0778_amd import datagen as dg
         out["batched_workload"] = batched_report(B, torch, dg.BATCH_ITERS)

@@ -41,6 +41,18 @@
  * argmin only where the top-2 distances are within that relative margin.
  * Ties go to the lowest centroid index.  Results are deterministic: the same
  * inputs on the same plan give bit-identical outputs.
+ *
+ * Mixed precision (KM_BF16, KM_FP8_E4M3): the matrix cores form the dense
+ * -2 x.c term in the narrow format with FP32 accumulation; a per-sample error
+ * band, proven from the format's unit roundoff and the norms of x and c,
+ * selects the candidates that could be the FP32 path's choice, and samples
+ * with more than one candidate are re-checked with the FP32 path's distance.
+ * The labels therefore equal the FP32 path's bit for bit, and so do the
+ * centroids; the objective comes from the FP64 per-label sums through
+ * J = sum_i |x_i|^2 + sum_j (cnt_j |c_j|^2 - 2 c_j . S_j).  FP8 scales each
+ * feature by a power of two s_f >= max_i |x_if| / 448 (exact) and keeps an
+ * e4m3 copy of X in the workspace, made once per call; d <= 128 and
+ * k <= 16384 for both (KM_ENOTSUP otherwise).
  */
 #ifndef KMEANS_MI355X_H
 #define KMEANS_MI355X_H
@@ -64,7 +76,8 @@ typedef enum {
 typedef enum {
     KM_FP32 = 0,         /* direct-form FP32 distances (the plain path)      */
     KM_BF16 = 1,         /* BF16 MFMA distances + proven-band FP32 recheck    */
-    KM_FP8_E4M3 = 2      /* FP8 e4m3 MFMA distances + FP32 recheck           */
+    KM_FP8_E4M3 = 2      /* FP8 e4m3 (OCP) MFMA distances, per-feature power-
+                            of-two scales + proven-band FP32 recheck          */
 } km_precision;
 
 typedef struct km_plan km_plan;
@@ -104,6 +117,8 @@ const char *km_last_error(void);
  *   labels   [n] int32 output, L(i) in [0, k)
  *   mindist  [n] FP32 output d_{i,L(i)} as computed, or NULL
  *   objective [1] FP64 output J = sum_i d_{i,L(i)} (FP64 sum), or NULL
+ * Mixed-precision plans compute labels only: mindist and objective must be
+ * NULL (KM_ENOTSUP otherwise; kmeans_lloyd reports their objective).
  */
 km_status kmeans_assign(km_plan *plan, const float *X, const float *C,
                         int32_t *labels, float *mindist, double *objective,
@@ -213,7 +228,7 @@ km_status km_plan_kernel_times(km_plan *plan, float *ms, int32_t cap,
                                int32_t *count);
 
 /*
- * Diagnostics of a BF16 plan: number of samples the last MFMA assign queued
+ * Diagnostics of a BF16 or FP8 plan: number of samples the last MFMA assign queued
  * for the exact FP32 recheck (their candidate set under the proven band had
  * more than one member), and how many of those were re-checked against all k
  * centroids because their candidate list overflowed.  Waits on `stream`;

@@ -165,7 +165,7 @@ class Plan:
         return [float(buf[i]) for i in range(min(cap, cnt.value))]
 
     def recheck_count(self, stream=None):
-        """km_plan_recheck_count: (samples the last BF16 assign queued for the
+        """km_plan_recheck_count: (samples the last mixed-precision assign queued for the
         exact recheck, how many of them were full scans)."""
         v = ctypes.c_int64(0)
         f = ctypes.c_int64(0)

@@ -61,13 +61,15 @@ struct km_plan {
     size_t lds_fused;    // dynamic LDS of the fused pass (whole record)
     size_t lds_upd;      // dynamic LDS of the update pass (one chunk of the record)
     int GS() const { return split ? grid_upd : grid; }
-    // mixed precision (BF16 MFMA + FP32 recheck)
+    // mixed precision (BF16 or FP8 MFMA + FP32 recheck)
     bool mixed = false;
+    int fmt = FMT_BF16;
     int D16 = 0, DP = 0, kpad = 0, IB = 0;
     int grid_mfma = 0, grid_rc = 0;
     int64_t rq_per_block = 0;
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
+    size_t off_fsc = 0, off_pfm = 0, off_xq = 0, off_xst = 0;   // FP8 only
     // workspace
     unsigned char* ws;
     size_t ws_bytes;
@@ -177,17 +179,21 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
 {
     unsigned char* ws = p->ws;
     int32_t* changed = reinterpret_cast<int32_t*>(ws + p->off_pch);
-    hipError_t e = launch_prep_c(reinterpret_cast<const float*>(ws + p->off_cp), p->k, p->d, p->D, p->kpad, p->DP,
-                                 reinterpret_cast<const XStats*>(ws + p->off_xs), reinterpret_cast<__bf16*>(ws + p->off_ab),
+    const bool f8 = p->fmt == FMT_FP8;
+    hipError_t e = launch_prep_c(p->fmt, reinterpret_cast<const float*>(ws + p->off_cp), p->k, p->d, p->D, p->kpad,
+                                 p->DP, reinterpret_cast<const XStats*>(ws + p->off_xs),
+                                 f8 ? reinterpret_cast<const float*>(ws + p->off_fsc) : nullptr, ws + p->off_ab,
                                  reinterpret_cast<float*>(ws + p->off_bias), reinterpret_cast<CStats*>(ws + p->off_cs),
                                  ctrl, iter, s);
     if (e != hipSuccess) return e;
     MixArgs m{};
     m.X = X; m.n = p->n; m.d = p->d; m.k = p->k; m.kpad = p->kpad;
-    m.Ab = reinterpret_cast<const __bf16*>(ws + p->off_ab);
+    m.Ab = ws + p->off_ab;
+    m.Xq = f8 ? ws + p->off_xq : nullptr;
+    m.xst = f8 ? reinterpret_cast<const float2*>(ws + p->off_xst) : nullptr;
     m.bias = reinterpret_cast<const float*>(ws + p->off_bias);
     m.cs = reinterpret_cast<const CStats*>(ws + p->off_cs);
-    m.u = 0.00390625f;                       // BF16: 8 significant bits, u = 2^-8
+    m.u = f8 ? 0.0625f : 0.00390625f;        // unit roundoff: e4m3 2^-4, BF16 2^-8
     m.IB = p->IB;
     m.gamma_terms = 2 * p->DP + 8;
     m.D8 = p->D8;
@@ -199,23 +205,30 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
-    if ((e = launch_mfma_assign(p->D16, m, p->grid_mfma, s)) != hipSuccess) return e;
+    if ((e = launch_mfma_assign(p->fmt, p->D16, m, p->grid_mfma, s)) != hipSuccess) return e;
     if (timed) {
         if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
         ++p->ev_used;
     }
     RecheckArgs r{};
     r.X = X; r.Cp = reinterpret_cast<const float*>(ws + p->off_cp); r.n = p->n; r.d = p->d; r.k = p->k;
-    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block;
+    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = rq_ints(p->fmt);
     r.labels = labels; r.changed_part = changed + p->grid_mfma;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
     return launch_recheck(p->D8, r, p->grid_mfma, s);
 }
 
+// Run-level prep of the mixed path (once per call, amortised over its
+// iterations): |x| statistics, and for FP8 the scaled e4m3 copy of X.
 hipError_t enqueue_prep_x(km_plan* p, const float* X, hipStream_t s)
 {
-    return launch_prep_x(X, p->n, p->d, reinterpret_cast<float*>(p->ws + p->off_pxm),
-                         reinterpret_cast<double*>(p->ws + p->off_pxs), reinterpret_cast<XStats*>(p->ws + p->off_xs), s);
+    hipError_t e = launch_prep_x(X, p->n, p->d, reinterpret_cast<float*>(p->ws + p->off_pxm),
+                                 reinterpret_cast<double*>(p->ws + p->off_pxs),
+                                 reinterpret_cast<XStats*>(p->ws + p->off_xs), s);
+    if (e != hipSuccess || p->fmt != FMT_FP8) return e;
+    return launch_prep_x_fp8(X, p->n, p->d, p->DP, reinterpret_cast<float*>(p->ws + p->off_pfm),
+                             reinterpret_cast<float*>(p->ws + p->off_fsc), p->ws + p->off_xq,
+                             reinterpret_cast<float2*>(p->ws + p->off_xst), s);
 }
 
 km_status enqueue_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
@@ -249,10 +262,9 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     if (k < 1 || (int64_t)k > n) return fail(KM_EINVAL, "k = %d outside [1, n]", k);
     if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3)
         return fail(KM_EINVAL, "unknown precision %d", (int)prec);
-    if (prec == KM_FP8_E4M3) return fail(KM_ENOTSUP, "FP8 distances are not available in this build");
     if (d > 8 * kMaxD8Plain) return fail(KM_ENOTSUP, "this build supports d <= %d (got %d)", 8 * kMaxD8Plain, d);
-    if (prec == KM_BF16 && ((int64_t)k + kMixCK - 1) / kMixCK * kMixCK > 16384)
-        return fail(KM_ENOTSUP, "BF16 distances support k <= 16384 (got %d)", k);
+    if (prec != KM_FP32 && ((int64_t)k + kMixCK - 1) / kMixCK * kMixCK > 16384)
+        return fail(KM_ENOTSUP, "BF16 and FP8 distances support k <= 16384 (got %d)", k);
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -291,14 +303,15 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     } else {
         p->grid_upd = p->grid;
     }
-    if (prec == KM_BF16) {
+    if (prec == KM_BF16 || prec == KM_FP8_E4M3) {
         p->mixed = true;
+        p->fmt = prec == KM_FP8_E4M3 ? FMT_FP8 : FMT_BF16;
         p->D16 = (d + 15) / 16;
         p->DP = 16 * p->D16;
         p->kpad = (k + kMixCK - 1) / kMixCK * kMixCK;
         p->IB = 1;
         while ((1 << p->IB) < p->kpad) ++p->IB;
-        const int occ = mfma_blocks_per_cu(p->D16);
+        const int occ = mfma_blocks_per_cu(p->fmt, p->D16);
         if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
@@ -321,11 +334,17 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_xs = off;   off = align256(off + sizeof(XStats));
         p->off_pxm = off;  off = align256(off + kXStatBlocks * sizeof(float));
         p->off_pxs = off;  off = align256(off + kXStatBlocks * sizeof(double));
-        p->off_ab = off;   off = align256(off + (size_t)p->kpad * p->DP * sizeof(__bf16));
+        p->off_ab = off;   off = align256(off + (size_t)p->kpad * p->DP * (p->fmt == FMT_FP8 ? 1 : 2));
         p->off_bias = off; off = align256(off + (size_t)p->kpad * sizeof(float));
         p->off_cs = off;   off = align256(off + sizeof(CStats));
         p->off_rqc = off;  off = align256(off + 2 * (size_t)p->grid_mfma * sizeof(int32_t));
-        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * kRqInts * sizeof(int32_t));
+        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(p->fmt) * sizeof(int32_t));
+        if (p->fmt == FMT_FP8) {
+            p->off_fsc = off; off = align256(off + 2 * (size_t)p->DP * sizeof(float));
+            p->off_pfm = off; off = align256(off + (size_t)kXStatBlocks * p->DP * sizeof(float));
+            p->off_xq = off;  off = align256(off + (size_t)n * p->DP);
+            p->off_xst = off; off = align256(off + (size_t)n * sizeof(float2));
+        }
     }
     p->total = off;
     *out = p;
@@ -360,7 +379,7 @@ km_status kmeans_assign(km_plan* plan, const float* X, const float* C, int32_t* 
     if ((st = set_device(plan)) != KM_OK) return st;
 
     if (plan->mixed && (mindist || objective))
-        return fail(KM_ENOTSUP, "BF16 plans return labels only from kmeans_assign (mindist and objective must be NULL)");
+        return fail(KM_ENOTSUP, "mixed-precision plans return labels only from kmeans_assign (mindist and objective must be NULL)");
     hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, cp_of(plan), nullptr, stream);
     if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
     if (plan->mixed) {

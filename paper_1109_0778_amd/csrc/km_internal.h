@@ -127,24 +127,27 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
         const size_t tile = (size_t)kBlock * (mode == MODE_UPDATE_WIDE ? kUpdateRows : 1);
-        b += (2 + 2 * kWaves) * tile * sizeof(int32_t);     // tile labels, per-wave lists, sorted lists
-        b += (size_t)k * sizeof(int32_t);                    // per-label cursors
+        b += 2 * tile * sizeof(int32_t);                     // labels of a tile, double-buffered
     }
     return b;
 }
 
 // ---------------------------------------------------------------- mixed path
-// BF16 MFMA distances with a proven error band and an exact FP32 recheck.
+// BF16 or FP8 MFMA distances with a proven error band and an exact FP32 recheck.
+enum MixFmt { FMT_BF16 = 0, FMT_FP8 = 1 };
 constexpr int kMixWaves = 4;                    // waves per block
 constexpr int kMixNB = 2;                       // 32-sample column blocks per wave
 constexpr int kMixTile = kMixWaves * kMixNB * 32;
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
-constexpr int kCandCap = 7;                     // candidates kept per lane (half a sample's rows)
-constexpr int kCandSlots = kCandCap + 8;        // LDS slots per lane: room for 8 appends before compaction
-constexpr int kRqInts = 16;                     // ints per recheck entry: sample, count, 14 ids
+// Candidates kept per lane (half a sample's rows); the FP8 band is about 16
+// times wider than the BF16 one, so it keeps more.
+__host__ __device__ constexpr int cand_cap(int fmt) { return fmt == FMT_FP8 ? 23 : 7; }
+__host__ __device__ constexpr int cand_slots(int fmt) { return cand_cap(fmt) + 8; }   // room for 8 appends
+__host__ __device__ constexpr int rq_ints(int fmt) { return 2 + 2 * cand_cap(fmt); }  // sample, count, ids
 constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
 constexpr int kXStatBlocks = 256;
 constexpr int kRecheckSplit = 8;                // recheck blocks per MFMA block's queue region
+constexpr float kFp8Max = 448.0f;               // largest finite e4m3 (OCP "fn") value
 
 struct XStats {                 // once per run, over all samples
     float max_xn2;              // max_i |x_i|^2 (FP32)
@@ -152,22 +155,28 @@ struct XStats {                 // once per run, over all samples
     double sum_xn2;             // sum_i |x_i|^2 (FP64)
 };
 struct CStats {                 // per iteration, over the centroids
-    float K, cmax, cn2max, pad;
+    float K, cmax, cn2max;
+    float inv2r;                // keys are kept as key / (2r): 1 for BF16, 2^-(e+1) for FP8
+    float inv_r;                // 1 / r (FP8 centroid scale r = 2^e), 2 for BF16 (unused)
+    float cl1;                  // FP8: max_j sum_f |c~_jf| of the scaled centroids
+    float pad[2];
 };
 
 struct MixArgs {
     const float* X;
     int64_t n;
     int32_t d, k, kpad;
-    const __bf16* Ab;           // [kpad][16*D16] bf16(-2 c), zero padded
-    const float* bias;          // [kpad] K + |c_j|^2, padded rows huge
+    const void* Ab;             // [kpad][16*D16] bf16(-2 c) or e4m3(-c~), zero padded
+    const float* bias;          // [kpad] (K + |c_j|^2) / (2r), padded rows huge
+    const uint8_t* Xq;          // FP8: [n][16*D16] e4m3(x / s_f), zero padded
+    const float2* xst;          // FP8: per sample (|x| upper bound, sum_f |x_f / s_f| upper bound)
     const CStats* cs;
     float u;                    // unit roundoff of the quantised format
     int32_t IB;                 // index bits in a key
     int32_t gamma_terms;        // m of the gamma_m accumulation bound
     int32_t D8;                 // chunks of the canonical FP32 distance
     int32_t* labels;
-    int32_t* rq;                // [grid][rq_per_block][kRqInts] recheck entries, one region per block
+    int32_t* rq;                // [grid][rq_per_block][rq_ints] recheck entries, one region per block
     int32_t* rq_count;          // [2][grid] entries queued by each block, then full scans among them
     int64_t rq_per_block;       // region capacity (tiles per block x samples per tile)
     int32_t* changed_part;      // [grid]
@@ -184,6 +193,7 @@ struct RecheckArgs {
     const int32_t* rq;
     const int32_t* rq_count;    // [grid]; recheck block b takes region b
     int64_t rq_per_block;
+    int32_t rq_ints;            // ints per entry
     int32_t* labels;
     int32_t* changed_part;      // [grid]
     const Ctrl* ctrl;
@@ -193,12 +203,16 @@ struct RecheckArgs {
 
 hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, double* part_sum,
                          XStats* xs, hipStream_t s);
-hipError_t launch_prep_c(const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
-                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter,
-                         hipStream_t s);
-hipError_t launch_mfma_assign(int D16, const MixArgs& a, int grid, hipStream_t s);
-size_t mfma_lds_bytes(int D16);
-int mfma_blocks_per_cu(int D16);
+// FP8 run-level prep: per-feature scales s_f (powers of two), the e4m3 copy
+// of X and the per-sample band inputs.
+hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, float* part_fmax, float* fscale,
+                             uint8_t* Xq, float2* xst, hipStream_t s);
+hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
+                         const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, const Ctrl* ctrl,
+                         int32_t iter, hipStream_t s);
+hipError_t launch_mfma_assign(int fmt, int D16, const MixArgs& a, int grid, hipStream_t s);
+size_t mfma_lds_bytes(int fmt, int D16);
+int mfma_blocks_per_cu(int fmt, int D16);
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
 
 }  // namespace km

@@ -1,8 +1,8 @@
 // Mixed-precision assign for gfx950: the dense -2 X C^T term of
-// |x - c|^2 = |x|^2 - 2 x.c + |c|^2 runs on the matrix cores in BF16 with
-// FP32 accumulation; every sample whose nearest candidates are closer than a
-// proven error band is re-checked with the canonical FP32 distance, so the
-// labels are exactly those of the FP32 path.
+// |x - c|^2 = |x|^2 - 2 x.c + |c|^2 runs on the matrix cores in BF16 or FP8
+// (e4m3) with FP32 accumulation; every sample whose nearest candidates are
+// closer than a proven error band is re-checked with the canonical FP32
+// distance, so the labels are exactly those of the FP32 path.
 //
 // Keys.  The MFMA accumulator starts at bias_j = K + |c_j|^2 (K = 2 max|x|^2
 // + 1, so every value is positive) and adds -2 x^.c^ (x^, c^ the BF16-rounded
@@ -21,6 +21,18 @@
 //   W_i = 2 B_i + 2.01 g (|x_i| + cmax)^2.
 // Samples whose candidate set {j : key_ij <= min key + W_i} has one member
 // take it; the others are re-checked exactly over their candidates.
+//
+// FP8.  Features are scaled by powers of two s_f >= max_i |x_if| / 448, so
+// x~_if = x_if / s_f is exact and within the e4m3 range; centroids become
+// c~_jf = c_jf s_f / r with one power of two r >= max |c_jf s_f| / 448.  Then
+// x.c = r sum_f x~_f c~_f, and the MFMA forms sum_f q_f q'_f with q = e4m3(x~),
+// q' = e4m3(c~) (products exact in FP32).  Keys are kept divided by 2r (exact):
+// the accumulator starts at (K + |c_j|^2) / (2r) and the operand is -q'.  With
+// u = 2^-4 and an absolute error eta = 2^-6 per element (covers e4m3
+// subnormals whether rounded or flushed),
+//   |sum x~c~ - sum q q'| <= (2u + u^2) S + (1 + u) eta (L1(c~) + L1(x~)) + D eta^2,
+// S = |x| cmax / r >= sum_f |x~_f c~_f| (Cauchy-Schwarz); the accumulation and
+// truncation terms are as above with every magnitude divided by 2r.
 #include "km_internal.h"
 #include "km_dist.h"
 
@@ -89,6 +101,84 @@ __global__ void prep_x_combine_kernel(const float* part_max, const double* part_
     }
 }
 
+// FP8 run-level prep.  (1) Per-block max |x_f| per feature: the grid's
+// threads take elements t, t + S, t + 2S, ... with S a multiple of d, so each
+// thread stays on one feature.  (2) One block turns the maxima into scales.
+// (3) One thread per sample writes its e4m3 row and its band inputs.
+__global__ __launch_bounds__(256) void prep_fmax_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                        int32_t DP, float* part_fmax)
+{
+    __shared__ uint32_t smax[16 * kMaxD16Mix];
+    const int tid = threadIdx.x;
+    for (int f = tid; f < DP; f += 256) smax[f] = 0u;
+    __syncthreads();
+    const int64_t T = (int64_t)gridDim.x * 256;
+    const int64_t S = (T / d) * d;
+    const int64_t t = (int64_t)blockIdx.x * 256 + tid;
+    if (t < S) {
+        float m = 0.0f;
+        const int64_t total = n * d;
+        for (int64_t e = t; e < total; e += S) m = fmaxf(m, fabsf(X[e]));
+        atomicMax(&smax[t % d], __float_as_uint(m));     // non-negative floats order like their bits
+    }
+    __syncthreads();
+    for (int f = tid; f < DP; f += 256) part_fmax[(size_t)blockIdx.x * DP + f] = __uint_as_float(smax[f]);
+}
+
+// smallest power of two p with m / p <= limit (1 when m == 0)
+__device__ __forceinline__ float pow2_scale(float m, float limit)
+{
+    if (!(m > 0.0f)) return 1.0f;
+    int e = 0;
+    (void)frexpf(m / limit, &e);            // m / limit < 2^e
+    float p = __builtin_ldexpf(1.0f, e - 1);
+    while (m * (1.0f / p) > limit) p *= 2.0f;
+    return p;
+}
+
+__global__ __launch_bounds__(256) void prep_fscale_kernel(const float* __restrict__ part_fmax, int nb, int32_t d,
+                                                          int32_t DP, float* fscale)
+{
+    for (int f = threadIdx.x; f < DP; f += 256) {
+        float m = 0.0f;
+        for (int b = 0; b < nb; ++b) m = fmaxf(m, part_fmax[(size_t)b * DP + f]);
+        const float sc = f < d ? pow2_scale(m, kFp8Max) : 1.0f;
+        fscale[f] = sc;
+        fscale[DP + f] = 1.0f / sc;         // exact: a power of two
+    }
+}
+
+__device__ __forceinline__ uint32_t fp8_of(float v)
+{
+    v = fminf(fmaxf(v, -kFp8Max), kFp8Max);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
+}
+
+__global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
+                                                      const float* __restrict__ fscale, uint8_t* Xq, float2* xst)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float* row = X + i * d;
+    const float* inv = fscale + DP;
+    uint32_t* out = reinterpret_cast<uint32_t*>(Xq + i * DP);
+    float s2 = 0.0f, l1 = 0.0f;
+    for (int f0 = 0; f0 < DP; f0 += 4) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int f = f0 + q;
+            const float v = f < d ? row[f] : 0.0f;
+            const float xt = v * inv[f];
+            s2 = __builtin_fmaf(v, v, s2);
+            l1 += fabsf(xt);
+            w |= fp8_of(xt) << (8 * q);
+        }
+        out[f0 / 4] = w;
+    }
+    xst[i] = make_float2(sqrtf(s2) * (1.0f + 1e-6f), l1 * (1.0f + 1e-5f));
+}
+
 // ------------------------------------------------------ per-iteration prep
 // One block: BF16 operand rows bf16(-2 c_j) (zero padded to DP features and
 // kpad rows), biases K + |c_j|^2 (huge for padded rows) and the band constants.
@@ -133,7 +223,97 @@ __global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ C
         cs->K = K;
         cs->cn2max = m;
         cs->cmax = sqrtf(m) * (1.0f + 1e-6f);
-        cs->pad = 0.0f;
+        cs->inv2r = 1.0f;
+        cs->inv_r = 2.0f;
+        cs->cl1 = 0.0f;
+        cs->pad[0] = cs->pad[1] = 0.0f;
+    }
+}
+
+// FP8: one block.  Pass 1: |c_j|^2, the largest |c_jf s_f| and |c_j|; the
+// centroid scale r; pass 2: operands e4m3(-c~), biases (K + |c_j|^2) / (2r)
+// and the largest L1 norm of the scaled centroids.
+__global__ __launch_bounds__(256) void prep_c_fp8_kernel(const float* __restrict__ Cp, int32_t k, int32_t d,
+                                                         int32_t D, int32_t kpad, int32_t DP,
+                                                         const XStats* __restrict__ xs,
+                                                         const float* __restrict__ fscale, uint8_t* Aq,
+                                                         float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter)
+{
+    __shared__ float smax[256], samax[256];
+    __shared__ float sr[2];
+    if (ctrl != nullptr && ctrl->stop_iter < iter) return;
+    const int tid = threadIdx.x;
+    const float K = xs->K;
+    float cn2max = 0.0f, amax = 0.0f;
+    for (int j = tid; j < k; j += 256) {
+        float s = 0.0f;
+        for (int f = 0; f < d; ++f) {
+            const float v = Cp[(size_t)j * D + f];
+            s = __builtin_fmaf(v, v, s);
+            amax = fmaxf(amax, fabsf(v * fscale[f]));
+        }
+        cn2max = fmaxf(cn2max, s);
+    }
+    smax[tid] = cn2max;
+    samax[tid] = amax;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (tid < s) {
+            smax[tid] = fmaxf(smax[tid], smax[tid + s]);
+            samax[tid] = fmaxf(samax[tid], samax[tid + s]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const float r = pow2_scale(samax[0], kFp8Max);
+        sr[0] = 1.0f / r;                   // exact
+        sr[1] = 0.5f / r;
+        const float m = smax[0] * (1.0f + 1e-5f);
+        cs->cn2max = m;
+        cs->cmax = sqrtf(m) * (1.0f + 1e-6f);
+    }
+    __syncthreads();
+    const float inv_r = sr[0], inv2r = sr[1];
+    float cl1 = 0.0f;
+    for (int j = tid; j < kpad; j += 256) {
+        float s = 0.0f, l1 = 0.0f;
+        if (j < k) {
+            for (int f = 0; f < d; ++f) {
+                const float v = Cp[(size_t)j * D + f];
+                s = __builtin_fmaf(v, v, s);
+                l1 += fabsf(v * fscale[f] * inv_r);
+            }
+            bias[j] = (K + s) * inv2r;
+        } else {
+            bias[j] = 3.0e38f;
+        }
+        cl1 = fmaxf(cl1, l1);
+    }
+    for (int64_t e = tid; e < (int64_t)kpad * DP / 4; e += 256) {
+        const int j = (int)(e * 4 / DP);
+        const int f0 = (int)(e * 4 - (int64_t)j * DP);
+        uint32_t w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int f = f0 + q;
+            const float v = (j < k && f < d) ? -(Cp[(size_t)j * D + f] * fscale[f] * inv_r) : 0.0f;
+            w |= fp8_of(v) << (8 * q);
+        }
+        reinterpret_cast<uint32_t*>(Aq)[e] = w;
+    }
+    __syncthreads();                        // smax is reused below
+    smax[tid] = cl1;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (tid < s) smax[tid] = fmaxf(smax[tid], smax[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        cs->K = K;
+        cs->inv2r = inv2r;
+        cs->inv_r = inv_r;
+        cs->cl1 = smax[0] * (1.0f + 1e-5f);
+        cs->pad[0] = cs->pad[1] = 0.0f;
     }
 }
 
@@ -150,14 +330,19 @@ __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
 // block.  Lane l of a 32x32 accumulator holds column l % 32 (one sample) and
 // rows 8(i/4) + 4(l/32) + i%4, i < 16 (16 centroids); lanes l and l^32 hold
 // the two halves of a sample's rows.
-template <int D16>
-__global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
+template <int D16, int FMT>
+__global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
 {
+    constexpr bool F8 = FMT == FMT_FP8;
+    constexpr int ES = F8 ? 1 : 2;         // operand bytes per feature
     constexpr int DP = 16 * D16;
-    constexpr int ROWB = DP * 2 + 16;      // padded LDS row: conflict-free 16-byte reads
+    constexpr int ROWB = DP * ES + 16;     // padded LDS row: conflict-free reads
     constexpr int NB = kMixNB;
     constexpr int CHB = kMixCK * ROWB;     // bytes of one chunk buffer
-    constexpr int V = DP * 2 / 16;         // uint4 per centroid row
+    constexpr int V = DP * ES / 16;        // uint4 per centroid row
+    constexpr int CAP = cand_cap(FMT);
+    constexpr int SLOTS = cand_slots(FMT);
+    constexpr int RQI = rq_ints(FMT);
     constexpr int PF = (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* Abuf = smem;                                                   // [2][CK][ROWB]
@@ -174,12 +359,13 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
     const int wave = tid >> 6;
     const int h = lane >> 5;
     if (tid == 0) { blk_count = 0; blk_full = 0; }
-    int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * kRqInts;
+    int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * RQI;
     const int col = lane & 31;
     const int d = a.d;
     const int64_t n = a.n;
     const uint32_t ibm = (1u << a.IB) - 1u;
     const float K = a.cs->K, cmax = a.cs->cmax, cn2max = a.cs->cn2max;
+    const float inv2r = a.cs->inv2r, inv_r = a.cs->inv_r, cl1 = a.cs->cl1;
     const float u = a.u;
     const float gm = (float)a.gamma_terms * 5.9604645e-8f;
     const float gamma_acc = gm / (1.0f - gm);
@@ -188,13 +374,14 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
     const float gcan = (10.0f + (a.D8 > 1 ? ceilf(log2f(P)) : 0.0f)) * 5.9604645e-8f;
     const int nchunks = a.kpad / kMixCK;
     const int64_t ntiles = (n + kMixTile - 1) / kMixTile;
-    uint32_t* mycand = cand + (size_t)wave * NB * kCandSlots * 64;
+    uint32_t* mycand = cand + (size_t)wave * NB * SLOTS * 64;
     int32_t changed = 0;
 
     // Chunk c of the centroid operands: registers <- global, LDS buffer <- registers.
 #define KM_LOAD_CHUNK(c_)                                                                 \
     {                                                                                     \
-        const uint4* src_ = reinterpret_cast<const uint4*>(a.Ab + (size_t)(c_) * kMixCK * DP); \
+        const uint4* src_ = reinterpret_cast<const uint4*>(                               \
+            static_cast<const unsigned char*>(a.Ab) + (size_t)(c_) * kMixCK * DP * ES);   \
         _Pragma("unroll") for (int i_ = 0; i_ < PF; ++i_) {                               \
             const int e_ = tid + i_ * 64 * kMixWaves;                                     \
             pr[i_] = (e_ < kMixCK * V) ? src_[e_] : make_uint4(0, 0, 0, 0);               \
@@ -222,8 +409,9 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
     __syncthreads();
 
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        // --- B fragments (BF16) and |x| of this wave's 2 x 32 samples
-        bf16x8 bfr[NB][D16];
+        // --- B fragments and the band of this wave's 2 x 32 samples
+        bf16x8 bfr[NB][F8 ? 1 : D16];
+        long bq[NB][F8 ? D16 : 1];
         float W[NB];
         int64_t pidx[NB];
 #pragma unroll
@@ -231,40 +419,64 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
             const int64_t p = t * kMixTile + (int64_t)wave * (NB * 32) + nb * 32 + col;
             pidx[nb] = p;
             const bool valid = p < n;
-            const float* row = a.X + (valid ? p : 0) * d;
-            float s2 = 0.0f;
+            if constexpr (F8) {
+                const uint8_t* qrow = a.Xq + (valid ? p : 0) * DP + 8 * h;
 #pragma unroll
-            for (int s = 0; s < D16; ++s) {
-                const int f0 = 16 * s + 8 * h;
-                float v[8];
-                if (valid && (d & 3) == 0 && f0 + 8 <= d) {
-                    const float4 v0 = *reinterpret_cast<const float4*>(row + f0);
-                    const float4 v1 = *reinterpret_cast<const float4*>(row + f0 + 4);
-                    v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-                    v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
-                } else {
+                for (int s = 0; s < D16; ++s) bq[nb][s] = valid ? *reinterpret_cast<const long*>(qrow + 16 * s) : 0l;
+                const float2 st = valid ? a.xst[p] : make_float2(0.0f, 0.0f);
+                const float xn = st.x;
+                const float u = a.u;
+                const float eta = 0.015625f;                        // 2^-6
+                const float S = xn * cmax * inv_r;
+                const float Sq = (1.0f + u) * eta * (cl1 + st.y) + (float)DP * eta * eta;
+                const float Eq = (2.0f * u + u * u) * S + Sq;
+                const float Pq = (1.0f + u) * (1.0f + u) * S + Sq;
+                const float emax = (K + cn2max) * inv2r + Pq;
+                const float B = Eq + (gamma_acc + trunc) * emax;
+                const float r = xn + cmax;
+                W[nb] = (2.0f * B + 2.01f * gcan * r * r * inv2r) * 1.001f;
+            } else {
+                const float* row = a.X + (valid ? p : 0) * d;
+                float s2 = 0.0f;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) v[i] = (valid && f0 + i < d) ? row[f0 + i] : 0.0f;
+                for (int s = 0; s < D16; ++s) {
+                    const int f0 = 16 * s + 8 * h;
+                    float v[8];
+                    if (valid && (d & 3) == 0 && f0 + 8 <= d) {
+                        const float4 v0 = *reinterpret_cast<const float4*>(row + f0);
+                        const float4 v1 = *reinterpret_cast<const float4*>(row + f0 + 4);
+                        v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+                        v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) v[i] = (valid && f0 + i < d) ? row[f0 + i] : 0.0f;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        s2 = __builtin_fmaf(v[i], v[i], s2);
+                        bfr[nb][s][i] = (__bf16)v[i];
+                    }
                 }
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    s2 = __builtin_fmaf(v[i], v[i], s2);
-                    bfr[nb][s][i] = (__bf16)v[i];
-                }
+                s2 += __shfl_xor(s2, 32);
+                const float xn = sqrtf(s2) * (1.0f + 1e-6f);
+                const float u = a.u;
+                const float q = 2.0f * (2.0f * u + u * u);
+                const float emax = K + cn2max + 2.0f * (1.0f + u) * (1.0f + u) * xn * cmax;
+                const float B = q * xn * cmax + (gamma_acc + trunc) * emax;
+                const float r = xn + cmax;
+                W[nb] = (2.0f * B + 2.01f * gcan * r * r) * 1.001f;
             }
-            s2 += __shfl_xor(s2, 32);
-            const float xn = sqrtf(s2) * (1.0f + 1e-6f);
-            const float q = 2.0f * (2.0f * u + u * u);
-            const float emax = K + cn2max + 2.0f * (1.0f + u) * (1.0f + u) * xn * cmax;
-            const float B = q * xn * cmax + (gamma_acc + trunc) * emax;
-            const float r = xn + cmax;
-            W[nb] = (2.0f * B + 2.01f * gcan * r * r) * 1.001f;
         }
 
-        uint32_t m[NB], thr[NB];
+        // m: running minimum key; cnt: list length; cut: smallest key dropped
+        // from a full list (every kept entry is below it); ovf: a full list
+        // that could not be split (equal values), i.e. rescan the sample
+        uint32_t m[NB], thr[NB], cut[NB];
         int cnt[NB], ovf[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) { m[nb] = 0xffffffffu; thr[nb] = 0xffffffffu; cnt[nb] = 0; ovf[nb] = 0; }
+        for (int nb = 0; nb < NB; ++nb) {
+            m[nb] = 0xffffffffu; thr[nb] = 0xffffffffu; cut[nb] = 0xffffffffu; cnt[nb] = 0; ovf[nb] = 0;
+        }
 
         // --- sweep over the centroids; the next chunk (possibly chunk 0 of the
         // next tile) is fetched into registers while this one is computed
@@ -288,13 +500,20 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
 #pragma unroll
                         for (int i = 0; i < 16; ++i) acc[nb][i] = bvv[i];
                 }
-                const unsigned char* arow = Ab_c + (tt * 32 + col) * ROWB + 16 * h;
+                const unsigned char* arow = Ab_c + (tt * 32 + col) * ROWB + 8 * ES * h;
 #pragma unroll
                 for (int s = 0; s < D16; ++s) {
-                    const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * s);
+                    if constexpr (F8) {
+                        const long af = *reinterpret_cast<const long*>(arow + 16 * s);
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfr[nb][s], acc[nb], 0, 0, 0);
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(af, bq[nb][s], acc[nb], 0, 0, 0);
+                    } else {
+                        const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * s);
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfr[nb][s], acc[nb], 0, 0, 0);
+                    }
                 }
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
@@ -310,21 +529,39 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
                     m[nb] = mm;
                     const uint32_t th = thr_key(mm, W[nb], ibm);
                     thr[nb] = th;
-                    uint32_t* lst = mycand + nb * kCandSlots * 64 + lane;
+                    uint32_t* lst = mycand + nb * SLOTS * 64 + lane;
+                    const uint32_t lim = min(th, cut[nb] - 1u);
 #pragma unroll
                     for (int half = 0; half < 2; ++half) {
 #pragma unroll
                         for (int i = 8 * half; i < 8 * half + 8; ++i) {
-                            if (key[i] <= th) { lst[cnt[nb] * 64] = key[i]; ++cnt[nb]; }
+                            if (key[i] <= lim) { lst[cnt[nb] * 64] = key[i]; ++cnt[nb]; }
                         }
-                        if (cnt[nb] > kCandCap) {
+                        if (cnt[nb] > CAP) {
                             // drop entries the (only decreasing) threshold has passed
                             int w = 0;
+                            uint32_t vmax = 0;
                             for (int q = 0; q < cnt[nb]; ++q) {
                                 const uint32_t v = lst[q * 64];
-                                if (v <= th) { lst[w * 64] = v; ++w; }
+                                if (v <= th) { lst[w * 64] = v; ++w; vmax = max(vmax, v); }
                             }
-                            if (w > kCandCap) { ovf[nb] = 1; w = kCandCap; }
+                            // still full: halve the window above the running
+                            // minimum; what falls out lowers the cut
+                            while (w > CAP) {
+                                const float lo = __uint_as_float(mm & ~ibm);
+                                const float hi = __uint_as_float(vmax & ~ibm);
+                                const uint32_t mid = (__float_as_uint(0.5f * lo + 0.5f * hi) & ~ibm) | ibm;
+                                int w2 = 0;
+                                uint32_t vm2 = 0;
+                                for (int q = 0; q < w; ++q) {
+                                    const uint32_t v = lst[q * 64];
+                                    if (v <= mid) { lst[w2 * 64] = v; ++w2; vm2 = max(vm2, v); }
+                                    else cut[nb] = min(cut[nb], v);
+                                }
+                                if (w2 == w) { ovf[nb] = 1; w = CAP; break; }
+                                w = w2;
+                                vmax = vm2;
+                            }
                             cnt[nb] = w;
                         }
                     }
@@ -344,9 +581,11 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
             const uint32_t tf = thr_key(mp, W[nb], ibm);
             int vc = 0;
             const int stored = cnt[nb];
-            for (int q = 0; q < stored; ++q) vc += (mycand[(nb * kCandSlots + q) * 64 + lane] <= tf);
+            for (int q = 0; q < stored; ++q) vc += (mycand[(nb * SLOTS + q) * 64 + lane] <= tf);
             const int vc_other = __shfl_xor(vc, 32);
-            const int ovf_any = ovf[nb] | __shfl_xor(ovf[nb], 32);
+            // a dropped key inside the final band: the list is incomplete
+            const int ovf_h = ovf[nb] | (cut[nb] <= tf ? 1 : 0);
+            const int ovf_any = ovf_h | __shfl_xor(ovf_h, 32);
             const int64_t p = pidx[nb];
             const bool valid = p < n;
             // a winner index outside [0, k) can only come from non-finite keys: rescan
@@ -368,7 +607,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
             }
             const int base0 = __shfl(vc, col);  // candidates of the lower half come first
             if (valid && !unique) {
-                int32_t* ent = rq_blk + (size_t)slot * kRqInts;
+                int32_t* ent = rq_blk + (size_t)slot * RQI;
                 if (h == 0) {
                     const bool full = ovf_any || (int)(mp & ibm) >= a.k;
                     ent[0] = (int32_t)p;
@@ -378,7 +617,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign_bf16(MixArgs a)
                 if (!ovf_any && (int)(mp & ibm) < a.k) {
                     int w = 2 + (h ? base0 : 0);
                     for (int q = 0; q < stored; ++q) {
-                        const uint32_t kq = mycand[(nb * kCandSlots + q) * 64 + lane];
+                        const uint32_t kq = mycand[(nb * SLOTS + q) * 64 + lane];
                         if (kq <= tf) ent[w++] = (int32_t)(kq & ibm);
                     }
                 }
@@ -428,14 +667,14 @@ __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
     // blocks (b, 0..gridDim.y-1) re-check the entries queued by block b of
     // the MFMA pass
     const int count = a.rq_count[blockIdx.x];
-    const int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * kRqInts;
+    const int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * a.rq_ints;
     const int wave_id = blockIdx.y * 4 + (tid >> 6);
     const int nwaves = gridDim.y * 4;
     int32_t changed = 0;
     for (int e0 = wave_id * GPW; e0 < count; e0 += nwaves * GPW) {
         const int e = e0 + grp;
         const bool valid = e < count;
-        const int32_t* ent = rq_blk + (size_t)(valid ? e : 0) * kRqInts;
+        const int32_t* ent = rq_blk + (size_t)(valid ? e : 0) * a.rq_ints;
         const int64_t p = ent[0];
         const int nc = valid ? ent[1] : 0;
         // this lane's 8 features of the sample
@@ -503,72 +742,105 @@ hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, 
     return hipGetLastError();
 }
 
-hipError_t launch_prep_c(const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
-                         const XStats* xs, __bf16* Ab, float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter,
-                         hipStream_t s)
+hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, float* part_fmax, float* fscale,
+                             uint8_t* Xq, float2* xst, hipStream_t s)
 {
-    hipLaunchKernelGGL(prep_c_kernel, dim3(1), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs, Ab, bias, cs, ctrl, iter);
+    hipLaunchKernelGGL(prep_fmax_kernel, dim3(kXStatBlocks), dim3(256), 0, s, X, n, d, DP, part_fmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prep_fscale_kernel, dim3(1), dim3(256), 0, s, part_fmax, kXStatBlocks, d, DP, fscale);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(quant_x_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, DP, fscale, Xq, xst);
     return hipGetLastError();
 }
 
-size_t mfma_lds_bytes(int D16)
+hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
+                         const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, const Ctrl* ctrl,
+                         int32_t iter, hipStream_t s)
 {
-    const size_t rowb = (size_t)D16 * 16 * 2 + 16;
-    return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
-           (size_t)kMixWaves * kMixNB * kCandSlots * 64 * sizeof(uint32_t);
+    if (fmt == FMT_FP8)
+        hipLaunchKernelGGL(prep_c_fp8_kernel, dim3(1), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs, fscale,
+                           static_cast<uint8_t*>(Ab), bias, cs, ctrl, iter);
+    else
+        hipLaunchKernelGGL(prep_c_kernel, dim3(1), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs,
+                           static_cast<__bf16*>(Ab), bias, cs, ctrl, iter);
+    return hipGetLastError();
 }
 
-template <int D16>
+size_t mfma_lds_bytes(int fmt, int D16)
+{
+    const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
+    return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
+           (size_t)kMixWaves * kMixNB * cand_slots(fmt) * 64 * sizeof(uint32_t);
+}
+
+template <int D16, int FMT>
 static hipError_t launch_mfma_d16(const MixArgs& a, int grid, hipStream_t s)
 {
-    const size_t lds = mfma_lds_bytes(D16);
+    const size_t lds = mfma_lds_bytes(FMT, D16);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign_bf16<D16>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((mfma_assign_bf16<D16>), dim3(grid), dim3(64 * kMixWaves), lds, s, a);
+    hipLaunchKernelGGL((mfma_assign<D16, FMT>), dim3(grid), dim3(64 * kMixWaves), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_assign(int D16, const MixArgs& a, int grid, hipStream_t s)
+template <int FMT>
+static hipError_t launch_mfma_fmt(int D16, const MixArgs& a, int grid, hipStream_t s)
 {
     switch (D16) {
-    case 1: return launch_mfma_d16<1>(a, grid, s);
-    case 2: return launch_mfma_d16<2>(a, grid, s);
-    case 3: return launch_mfma_d16<3>(a, grid, s);
-    case 4: return launch_mfma_d16<4>(a, grid, s);
-    case 5: return launch_mfma_d16<5>(a, grid, s);
-    case 6: return launch_mfma_d16<6>(a, grid, s);
-    case 7: return launch_mfma_d16<7>(a, grid, s);
-    case 8: return launch_mfma_d16<8>(a, grid, s);
+    case 1: return launch_mfma_d16<1, FMT>(a, grid, s);
+    case 2: return launch_mfma_d16<2, FMT>(a, grid, s);
+    case 3: return launch_mfma_d16<3, FMT>(a, grid, s);
+    case 4: return launch_mfma_d16<4, FMT>(a, grid, s);
+    case 5: return launch_mfma_d16<5, FMT>(a, grid, s);
+    case 6: return launch_mfma_d16<6, FMT>(a, grid, s);
+    case 7: return launch_mfma_d16<7, FMT>(a, grid, s);
+    case 8: return launch_mfma_d16<8, FMT>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int D16>
+hipError_t launch_mfma_assign(int fmt, int D16, const MixArgs& a, int grid, hipStream_t s)
+{
+    return fmt == FMT_FP8 ? launch_mfma_fmt<FMT_FP8>(D16, a, grid, s) : launch_mfma_fmt<FMT_BF16>(D16, a, grid, s);
+}
+
+template <int D16, int FMT>
 static int occ_mfma()
 {
+    const size_t lds = mfma_lds_bytes(FMT, D16);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -1;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_assign_bf16<D16>, 64 * kMixWaves,
-                                                     mfma_lds_bytes(D16)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_assign<D16, FMT>, 64 * kMixWaves, lds) != hipSuccess)
         return -1;
     return nb;
 }
 
-int mfma_blocks_per_cu(int D16)
+template <int FMT>
+static int occ_mfma_fmt(int D16)
 {
     switch (D16) {
-    case 1: return occ_mfma<1>();
-    case 2: return occ_mfma<2>();
-    case 3: return occ_mfma<3>();
-    case 4: return occ_mfma<4>();
-    case 5: return occ_mfma<5>();
-    case 6: return occ_mfma<6>();
-    case 7: return occ_mfma<7>();
-    case 8: return occ_mfma<8>();
+    case 1: return occ_mfma<1, FMT>();
+    case 2: return occ_mfma<2, FMT>();
+    case 3: return occ_mfma<3, FMT>();
+    case 4: return occ_mfma<4, FMT>();
+    case 5: return occ_mfma<5, FMT>();
+    case 6: return occ_mfma<6, FMT>();
+    case 7: return occ_mfma<7, FMT>();
+    case 8: return occ_mfma<8, FMT>();
     default: return -1;
     }
+}
+
+int mfma_blocks_per_cu(int fmt, int D16)
+{
+    return fmt == FMT_FP8 ? occ_mfma_fmt<FMT_FP8>(D16) : occ_mfma_fmt<FMT_BF16>(D16);
 }
 
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s)

@@ -28,107 +28,59 @@
 namespace km {
 
 
+__device__ __forceinline__ void lds_add_f64(double* p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // "process": add the tile's samples that this wave owns (label L with
-// L % 4 == wave) to the block's activation record.
-//  1. list the owned samples in increasing sample order (entry = (L << 12) |
-//     offset in the tile) and count them per label (integer LDS adds);
-//  2. turn the counts into run starts (prefix over the wave's labels) and
-//     stable-scatter the list into label order: for each 64-entry chunk, the
-//     distinct labels are taken one by one and their entries placed in lane
-//     order after the run's cursor;
-//  3. walk the sorted list 16 rows at a time (lane f loads feature f of each
-//     row, coalesced): a register accumulates the current label's run and is
-//     added into the LDS record once per run.
-// Only this wave touches these labels; every sum has a fixed order (the
-// block's tiles in order, the tile's samples in order within a run).
+// L % 4 == wave) to the block's activation record, in increasing sample
+// order.  Lane f carries feature f of a row (coalesced loads, B rows in
+// flight); the FP64 adds are LDS atomics without return, which the wave
+// issues -- and the LDS executes -- in program order, so every sum has a
+// fixed order and nothing waits on their results.
 template <int D8, int TILE>
-__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, int kc, const int32_t* lb,
-                                                int32_t* wl, int32_t* ws, int32_t* cur, double* S, int32_t* cnt,
-                                                int lane, int wave)
+__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, const int32_t* lb, double* S,
+                                                int32_t* cnt, int lane, int wave)
 {
     constexpr int FPL = (8 * D8 + 63) / 64;  // features per lane
-    constexpr int B = 16;
-    const int nlab = (kc - wave + kWaves - 1) / kWaves;   // labels this wave owns: L = 4 ll + wave
-    for (int ll = lane; ll < nlab; ll += 64) cur[ll * kWaves + wave] = 0;
-    int nown = 0;
-#pragma unroll 4
+    constexpr int B = 8;
     for (int g = 0; g < TILE / 64; ++g) {
         const int L = lb[g * 64 + lane];
-        const bool own = L >= 0 && (L & (kWaves - 1)) == wave;
-        const uint64_t mask = __ballot(own);
-        if (own) {
-            wl[nown + __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0))] =
-                (L << 12) | (g * 64 + lane);
-            __hip_atomic_fetch_add(cur + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        nown += __popcll(mask);
-    }
-    if (nown == 0) return;
-    // counts -> record counts, then exclusive prefix (run starts) in label order
-    int carry = 0;
-    for (int c0 = 0; c0 < nlab; c0 += 64) {
-        const int ll = c0 + lane;
-        const int L = ll * kWaves + wave;
-        const int c = ll < nlab ? cur[L] : 0;
-        if (ll < nlab && c) cnt[L] += c;
-        int incl = c;
+        uint64_t mask = __ballot(L >= 0 && (L & (kWaves - 1)) == wave);
+        const float* Xg = Xt + (int64_t)(g * 64) * d;
+        while (mask) {
+            int p[B];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int o = __shfl_up(incl, off);
-            if (lane >= off) incl += o;
-        }
-        if (ll < nlab) cur[L] = carry + incl - c;
-        carry += __shfl(incl, 63);
-    }
-    // stable scatter into label order
-    for (int c0 = 0; c0 < nown; c0 += 64) {
-        const int ent = (c0 + lane < nown) ? wl[c0 + lane] : -1;
-        const int L = ent >= 0 ? (ent >> 12) : -1;
-        uint64_t rem = __ballot(L >= 0);
-        const uint64_t lt = (1ull << lane) - 1ull;
-        while (rem) {
-            const int Lx = __builtin_amdgcn_readlane(L, (int)__builtin_ctzll(rem));
-            const uint64_t m = __ballot(L == Lx);
-            const int base = cur[Lx];
-            if (L == Lx) ws[base + (int)__popcll(m & lt)] = ent;
-            if (lane == (int)__builtin_ctzll(m)) cur[Lx] = base + (int)__popcll(m);
-            rem &= ~m;
-        }
-    }
-    // runs
-    double acc[FPL];
-#pragma unroll
-    for (int mm = 0; mm < FPL; ++mm) acc[mm] = 0.0;
-    for (int i0 = 0; i0 < nown; i0 += B) {
-        const int mine = (lane < B && i0 + lane < nown) ? ws[i0 + lane] : -1;
-        const int nxt_first = (i0 + B < nown) ? ws[i0 + B] : -1;   // uniform: first entry of the next batch
-        float v[B][FPL];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int ent = __builtin_amdgcn_readlane(mine, u);
-            const float* row = Xt + (int64_t)(ent >= 0 ? (ent & 4095) : 0) * d;
-#pragma unroll
-            for (int mm = 0; mm < FPL; ++mm) {
-                const int f = lane + 64 * mm;
-                v[u][mm] = (f < d) ? row[f] : 0.0f;
+            for (int u = 0; u < B; ++u) {
+                if (mask) {
+                    p[u] = (int)__builtin_ctzll(mask);
+                    mask &= mask - 1;
+                } else {
+                    p[u] = -1;
+                }
             }
-        }
+            float v[B][FPL];
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int ent = __builtin_amdgcn_readlane(mine, u);
-            if (ent >= 0) {
+            for (int u = 0; u < B; ++u) {
+                const float* row = Xg + (int64_t)(p[u] >= 0 ? p[u] : 0) * d;
 #pragma unroll
-                for (int mm = 0; mm < FPL; ++mm) acc[mm] += (double)v[u][mm];
-                const int nx = (u + 1 < B) ? __builtin_amdgcn_readlane(mine, u + 1) : nxt_first;
-                const int L = ent >> 12;
-                if (nx < 0 || (nx >> 12) != L) {      // end of this label's run: into the record
-                    double* srow = S + (size_t)L * d;
+                for (int m = 0; m < FPL; ++m) {
+                    const int f = lane + 64 * m;
+                    v[u][m] = (p[u] >= 0 && f < d) ? row[f] : 0.0f;
+                }
+            }
 #pragma unroll
-                    for (int mm = 0; mm < FPL; ++mm) {
-                        const int f = lane + 64 * mm;
-                        if (f < d) srow[f] = srow[f] + acc[mm];
-                        acc[mm] = 0.0;
+            for (int u = 0; u < B; ++u) {
+                if (p[u] >= 0) {
+                    const int Lu = __builtin_amdgcn_readlane(L, p[u]);
+                    double* srow = S + (size_t)Lu * d;
+#pragma unroll
+                    for (int m = 0; m < FPL; ++m) {
+                        const int f = lane + 64 * m;
+                        if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
                     }
+                    if (lane == 0) __hip_atomic_fetch_add(cnt + Lu, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         }
@@ -180,9 +132,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     double* S = reinterpret_cast<double*>(smem);
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
     int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [2][TILE] labels of a tile
-    int32_t* wlist = lbl + 2 * TILE;                           // [kWaves][TILE] per-wave lists
-    int32_t* wsort = wlist + kWaves * TILE;                    // [kWaves][TILE] the lists in label order
-    int32_t* cursor = wsort + kWaves * TILE;                   // [kc] per-label counts / run cursors
 
     // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
@@ -240,8 +189,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
 #pragma unroll
             for (int r = 0; r < R; ++r) lb[r * kBlock + tid] = lab[r];
             __syncthreads();
-            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, kc, lb, wlist + wave * TILE,
-                                      wsort + wave * TILE, cursor, S, cnt, lane, wave);
+            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lb, S, cnt, lane, wave);
             buf ^= 1;
         }
     }

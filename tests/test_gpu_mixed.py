@@ -1,4 +1,4 @@
-"""BF16-MFMA path with FP32 recheck (needs an MI355X).
+"""BF16- and FP8-MFMA paths with FP32 recheck (needs an MI355X).
 
 Bar: the mixed path's labels equal the FP32 path's labels bit for bit (the
 recheck band is a proven bound), so whole Lloyd trajectories coincide: same
@@ -18,11 +18,14 @@ from test_gpu_plain import (REL_TOL, _bind, _torch, check_centroids, check_label
 pytestmark = pytest.mark.gpu
 
 
-def mixed_assign(torch, B, X, C, plan=None):
+PRECS = ["bf16", "fp8"]
+
+
+def mixed_assign(torch, B, X, C, plan=None, prec="bf16"):
     dev = torch.device("cuda")
     n, d = X.shape
     k = C.shape[0]
-    plan = plan or B.Plan(n, d, k, "bf16")
+    plan = plan or B.Plan(n, d, k, prec)
     Xg = torch.from_numpy(X).to(dev)
     Cg = torch.from_numpy(np.ascontiguousarray(C, np.float32)).to(dev)
     lab = torch.full((n,), -7, dtype=torch.int32, device=dev)
@@ -36,34 +39,37 @@ SHAPES = [(3000, 8, 8), (5000, 3, 5), (4099, 17, 13), (2500, 64, 64), (1200, 128
           (20000, 128, 200), (9001, 100, 150), (5000, 24, 600), (40000, 64, 64)]
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,d,k", SHAPES)
-def test_mixed_assign_equals_fp32(n, d, k):
+def test_mixed_assign_equals_fp32(n, d, k, prec):
     torch, B = _torch(), _bind()
-    say(f"mixed assign n={n} d={d} k={k}")
+    say(f"mixed assign {prec} n={n} d={d} k={k}")
     X, C = datagen.blobs(n, d, k, max(2, k // 2), 1.5, seed=n + d + k)
-    lab_m = mixed_assign(torch, B, X, C)
+    lab_m = mixed_assign(torch, B, X, C, prec=prec)
     lab_p, _, _ = run_assign(torch, B, X, C)
     diff = np.flatnonzero(lab_m != lab_p)
     assert diff.size == 0, f"{diff.size} labels differ from the FP32 path, first {diff[:5]}"
     check_labels(lab_m, C, X, "mixed assign")
 
 
-def test_mixed_exact_ties_and_duplicates():
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_exact_ties_and_duplicates(prec):
     torch, B = _torch(), _bind()
     X, C = datagen.blobs(6000, 12, 5, 5, 1.0, seed=4)
     C2 = np.concatenate([C, C, C[:2]], 0)      # exact duplicates: every sample has a tie
-    lab_m = mixed_assign(torch, B, X, C2)
+    lab_m = mixed_assign(torch, B, X, C2, prec=prec)
     lab_p, _, _ = run_assign(torch, B, X, C2)
     assert np.array_equal(lab_m, lab_p)
     assert lab_m.max() < 5                      # the lowest index of each duplicate set wins
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,d,k,iters", [(30000, 32, 48, 6), (12000, 128, 180, 4), (5000, 7, 11, 5)])
-def test_mixed_lloyd_equals_fp32(n, d, k, iters):
+def test_mixed_lloyd_equals_fp32(n, d, k, iters, prec):
     torch, B = _torch(), _bind()
-    say(f"mixed lloyd n={n} d={d} k={k}")
+    say(f"mixed lloyd {prec} n={n} d={d} k={k}")
     X, C = datagen.blobs(n, d, k, k, 2.0, seed=5 * n + k)
-    m = run_lloyd(torch, B, X, C, iters, plan=B.Plan(n, d, k, "bf16"))
+    m = run_lloyd(torch, B, X, C, iters, plan=B.Plan(n, d, k, prec))
     p = run_lloyd(torch, B, X, C, iters, plan=B.Plan(n, d, k, "fp32"))
     assert np.array_equal(m["labels"], p["labels"])
     assert np.array_equal(m["C"], p["C"])
@@ -73,10 +79,11 @@ def test_mixed_lloyd_equals_fp32(n, d, k, iters):
     assert abs(m["J"][0] - o["J"][0]) <= 1e-9 * o["J"][0]
 
 
-def test_mixed_stepwise_against_oracle():
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_stepwise_against_oracle(prec):
     torch, B = _torch(), _bind()
     X, C = datagen.blobs(15000, 48, 30, 30, 1.5, seed=9)
-    plan = B.Plan(15000, 48, 30, "bf16")
+    plan = B.Plan(15000, 48, 30, prec)
     Ct = C.copy()
     for t in range(4):
         g = run_lloyd(torch, B, X, Ct, 1, plan=plan)
@@ -88,19 +95,21 @@ def test_mixed_stepwise_against_oracle():
         Ct = g["C"]
 
 
-def test_mixed_tolerance_mode_matches_fp32():
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_tolerance_mode_matches_fp32(prec):
     torch, B = _torch(), _bind()
     X, C = datagen.blobs(8000, 8, 6, 6, 1.0, seed=5)
     for tol in (0.0, 1e-3):
-        m = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(8000, 8, 6, "bf16"))
+        m = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(8000, 8, 6, prec))
         p = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(8000, 8, 6, "fp32"))
         assert m["iters"] == p["iters"]
         assert np.array_equal(m["C"], p["C"]) and np.array_equal(m["labels"], p["labels"])
 
 
-def test_mixed_rejects_distance_outputs():
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_rejects_distance_outputs(prec):
     torch, B = _torch(), _bind()
-    plan = B.Plan(100, 4, 3, "bf16")
+    plan = B.Plan(100, 4, 3, prec)
     X = torch.zeros(400, dtype=torch.float32, device="cuda")
     C = torch.zeros(12, dtype=torch.float32, device="cuda")
     lab = torch.zeros(100, dtype=torch.int32, device="cuda")
@@ -111,18 +120,18 @@ def test_mixed_rejects_distance_outputs():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", ["plain", "bf16"])
-def test_mixed_full_size_equals_fp32(name):
-    """Full-size workloads, launched as the benchmark launches them: the BF16
-    path's whole trajectory (labels, centroids every iteration) equals the
-    FP32 path's; the last iteration is checked against the oracle on a fixed
-    2^16-sample subset (assign) and over all samples (update)."""
+@pytest.mark.parametrize("name,prec", [("plain", "bf16"), ("bf16", "bf16"), ("fp8", "fp8"), ("fp8", "bf16")])
+def test_mixed_full_size_equals_fp32(name, prec):
+    """Full-size workloads, launched as the benchmark launches them: the
+    mixed path's whole trajectory (labels, centroids every iteration) equals
+    the FP32 path's; the last iteration is checked against the oracle on a
+    fixed 2^16-sample subset (assign) and over all samples (update)."""
     torch, B = _torch(), _bind()
     w = datagen.WORKLOADS[name]
     iters = 5
-    say(f"full size {name}: n={w.n} d={w.d} k={w.k}, {iters} iterations")
+    say(f"full size {name} ({prec}): n={w.n} d={w.d} k={w.k}, {iters} iterations")
     X, C0 = datagen.workload(name)
-    pm = B.Plan(w.n, w.d, w.k, "bf16")
+    pm = B.Plan(w.n, w.d, w.k, prec)
     pp = B.Plan(w.n, w.d, w.k, "fp32")
     a = run_lloyd(torch, B, X, C0, iters - 1, plan=pm)
     m = run_lloyd(torch, B, X, a["C"], 1, plan=pm)
@@ -136,3 +145,35 @@ def test_mixed_full_size_equals_fp32(name):
     assert np.array_equal(m["counts"], cnto)
     check_centroids(m["C"], Co, X, f"{name} full update")
     np.testing.assert_allclose(m["J"][0], p["J"][0], rtol=1e-6)
+
+
+def test_fp8_extreme_feature_scales():
+    """Features whose ranges differ by many binades (per-feature scales), a
+    constant-zero feature (scale guard), and values that land on e4m3
+    subnormals after scaling: labels still equal the FP32 path's."""
+    torch, B = _torch(), _bind()
+    X, C = datagen.blobs(20000, 20, 40, 40, 1.0, seed=17)
+    scale = np.float32(2.0) ** np.arange(-12, 8, dtype=np.float32)
+    X = (X * scale).astype(np.float32)
+    C = (C * scale).astype(np.float32)
+    X[:, 3] = 0.0
+    C[:, 3] = 0.0
+    X[:50, 5] = np.float32(1e-30)
+    lab_m = mixed_assign(torch, B, X, C, prec="fp8")
+    lab_p, _, _ = run_assign(torch, B, X, C)
+    assert np.array_equal(lab_m, lab_p)
+    check_labels(lab_m, C, X, "fp8 scales")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mixed_recheck_counters(prec):
+    """The recheck counters are plausible: every sample is either decided by
+    the MFMA pass or queued, never more than n per iteration."""
+    torch, B = _torch(), _bind()
+    n, d, k = 30000, 32, 64
+    X, C = datagen.blobs(n, d, k, k, 1.0, seed=23)
+    plan = B.Plan(n, d, k, prec)
+    run_lloyd(torch, B, X, C, 2, plan=plan)
+    cnt, full = plan.recheck_count()
+    say(f"{prec}: {cnt} rechecks, {full} full scans over 2 iterations")
+    assert 0 <= full <= cnt <= 2 * n
