@@ -127,7 +127,7 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
         const size_t tile = (size_t)kBlock * (mode == MODE_UPDATE_WIDE ? kUpdateRows : 1);
-        b += 2 * tile * sizeof(int32_t);                     // labels of a tile, double-buffered
+        b += (2 + kWaves) * tile * sizeof(int32_t);          // labels of a tile (double-buffered), owned lists
     }
     return b;
 }
@@ -143,7 +143,10 @@ constexpr int kMixCK = 64;                      // centroids per LDS chunk
 // times wider than the BF16 one, so it keeps more.
 __host__ __device__ constexpr int cand_cap(int fmt) { return fmt == FMT_FP8 ? 23 : 7; }
 __host__ __device__ constexpr int cand_slots(int fmt) { return cand_cap(fmt) + 8; }   // room for 8 appends
-__host__ __device__ constexpr int rq_ints(int fmt) { return 2 + 2 * cand_cap(fmt); }  // sample, count, ids
+// Recheck entry: sample, count, 2 pad, then the candidate ids, 16-byte
+// aligned and rounded up to a multiple of 8 (read 8 at a time).
+constexpr int kRqHead = 4;
+__host__ __device__ constexpr int rq_ints(int fmt) { return kRqHead + (2 * cand_cap(fmt) + 7) / 8 * 8; }
 constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
 constexpr int kXStatBlocks = 256;
 constexpr int kRecheckSplit = 8;                // recheck blocks per MFMA block's queue region

@@ -615,7 +615,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
                     if (full) atomicAdd(&blk_full, 1);
                 }
                 if (!ovf_any && (int)(mp & ibm) < a.k) {
-                    int w = 2 + (h ? base0 : 0);
+                    int w = kRqHead + (h ? base0 : 0);
                     for (int q = 0; q < stored; ++q) {
                         const uint32_t kq = mycand[(nb * SLOTS + q) * 64 + lane];
                         if (kq <= tf) ent[w++] = (int32_t)(kq & ibm);
@@ -674,39 +674,58 @@ __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
     for (int e0 = wave_id * GPW; e0 < count; e0 += nwaves * GPW) {
         const int e = e0 + grp;
         const bool valid = e < count;
-        const int32_t* ent = rq_blk + (size_t)(valid ? e : 0) * a.rq_ints;
+        const int32_t* ent = rq_blk + (size_t)(valid ? e : e0) * a.rq_ints;   // entry e0 < count exists
         const int64_t p = ent[0];
         const int nc = valid ? ent[1] : 0;
-        // this lane's 8 features of the sample
+        // Every load below is unconditional with a clamped address (a valid
+        // row, feature or list slot) and its value is masked afterwards, so
+        // the loads of a batch are all in flight together.
+        const int qc = q < D8 ? q : D8 - 1;
         float x[8];
-        const float* xr = a.X + p * a.d + 8 * q;
+        {
+            const float* xr = a.X + p * a.d;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[i] = (valid && q < D8 && 8 * q + i < a.d) ? xr[i] : 0.0f;
+            for (int i = 0; i < 8; ++i) {
+                const int f = 8 * qc + i;
+                const float v = xr[f < a.d ? f : a.d - 1];
+                x[i] = (q < D8 && f < a.d) ? v : 0.0f;
+            }
+        }
         // trip count: the longest candidate list of the wave
-        int trips = nc < 0 ? a.k : nc;
+        int trips = !valid ? 0 : (nc < 0 ? a.k : nc);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) trips = max(trips, __shfl_xor(trips, off));
         float best = __builtin_huge_valf();
         int bj = 0;
-        constexpr int TB = 4;                // candidates in flight per group
+        constexpr int TB = 8;                // candidates in flight per group
+        const int lastbatch = a.rq_ints - kRqHead - TB;   // the list holds a multiple of TB slots
         for (int t0 = 0; t0 < trips; t0 += TB) {
-            float cv[TB][8];
             int jj[TB];
+            {
+                const int4* lp = reinterpret_cast<const int4*>(ent + kRqHead + (t0 < lastbatch ? t0 : lastbatch));
+                const int4 l0 = lp[0], l1 = lp[1];
+                const int listed[TB] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+#pragma unroll
+                for (int u = 0; u < TB; ++u) {
+                    const int t = t0 + u;
+                    const int j = (nc < 0) ? t : (t < nc ? listed[u] : -1);
+                    jj[u] = (valid && j >= 0 && j < a.k && (nc >= 0 || t < a.k)) ? j : -1;
+                }
+            }
+            float cv[TB][8];
 #pragma unroll
             for (int u = 0; u < TB; ++u) {
-                const int t = t0 + u;
-                const int j = (nc < 0) ? (t < a.k ? t : -1) : (t < nc ? ent[2 + t] : -1);
-                jj[u] = (valid && j >= 0 && j < a.k) ? j : -1;
-                const float* cr = a.Cp + (size_t)(jj[u] >= 0 ? jj[u] : 0) * D + 8 * q;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) cv[u][i] = (q < D8) ? cr[i] : 0.0f;
+                const float4* cr = reinterpret_cast<const float4*>(a.Cp + (size_t)(jj[u] >= 0 ? jj[u] : 0) * D + 8 * qc);
+                const float4 c0 = cr[0], c1 = cr[1];
+                cv[u][0] = c0.x; cv[u][1] = c0.y; cv[u][2] = c0.z; cv[u][3] = c0.w;
+                cv[u][4] = c1.x; cv[u][5] = c1.y; cv[u][6] = c1.z; cv[u][7] = c1.w;
             }
 #pragma unroll
             for (int u = 0; u < TB; ++u) {
                 float part = 0.0f;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const float df = x[i] - cv[u][i];
+                    const float df = x[i] - (q < D8 ? cv[u][i] : 0.0f);
                     part = __builtin_fmaf(df, df, part);
                 }
 #pragma unroll

@@ -35,53 +35,58 @@ __device__ __forceinline__ void lds_add_f64(double* p, double v)
 
 // "process": add the tile's samples that this wave owns (label L with
 // L % 4 == wave) to the block's activation record, in increasing sample
-// order.  Lane f carries feature f of a row (coalesced loads, B rows in
-// flight); the FP64 adds are LDS atomics without return, which the wave
-// issues -- and the LDS executes -- in program order, so every sum has a
-// fixed order and nothing waits on their results.
+// order.  The owned samples are listed in LDS first; then B rows at a time
+// are loaded (lane f carries feature f: coalesced) with every load issued
+// before the first is used -- addresses are clamped to a valid row and
+// feature instead of branching, so no load waits on another -- and added
+// with LDS atomics without return, which the wave issues, and the LDS
+// executes, in program order: every sum has a fixed order and nothing waits
+// on their results.
 template <int D8, int TILE>
-__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, const int32_t* lb, double* S,
-                                                int32_t* cnt, int lane, int wave)
+__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, const int32_t* lb, int32_t* wl,
+                                                double* S, int32_t* cnt, int lane, int wave)
 {
     constexpr int FPL = (8 * D8 + 63) / 64;  // features per lane
-    constexpr int B = 8;
+    constexpr int B = FPL == 1 ? 32 : 16;
+    int nown = 0;
+#pragma unroll
     for (int g = 0; g < TILE / 64; ++g) {
         const int L = lb[g * 64 + lane];
-        uint64_t mask = __ballot(L >= 0 && (L & (kWaves - 1)) == wave);
-        const float* Xg = Xt + (int64_t)(g * 64) * d;
-        while (mask) {
-            int p[B];
+        const bool own = L >= 0 && (L & (kWaves - 1)) == wave;
+        const uint64_t mask = __ballot(own);
+        if (own)
+            wl[nown + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
+                (L << 12) | (g * 64 + lane);
+        nown += (int)__popcll(mask);
+    }
+    int fc[FPL];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                if (mask) {
-                    p[u] = (int)__builtin_ctzll(mask);
-                    mask &= mask - 1;
-                } else {
-                    p[u] = -1;
-                }
-            }
-            float v[B][FPL];
+    for (int m = 0; m < FPL; ++m) fc[m] = min(lane + 64 * m, d - 1);
+    for (int i0 = 0; i0 < nown; i0 += B) {
+        const int mine = (lane < B && i0 + lane < nown) ? wl[i0 + lane] : -1;
+        const int first = __builtin_amdgcn_readfirstlane(mine);     // entry i0: always valid
+        float v[B][FPL];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const float* row = Xg + (int64_t)(p[u] >= 0 ? p[u] : 0) * d;
+        for (int u = 0; u < B; ++u) {
+            int ent = __builtin_amdgcn_readlane(mine, u);
+            ent = ent >= 0 ? ent : first;
+            const float* row = Xt + (int64_t)(ent & 4095) * d;
+#pragma unroll
+            for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int ent = __builtin_amdgcn_readlane(mine, u);
+            if (ent >= 0) {
+                const int Lu = ent >> 12;
+                double* srow = S + (size_t)Lu * d;
 #pragma unroll
                 for (int m = 0; m < FPL; ++m) {
                     const int f = lane + 64 * m;
-                    v[u][m] = (p[u] >= 0 && f < d) ? row[f] : 0.0f;
+                    if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
                 }
-            }
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                if (p[u] >= 0) {
-                    const int Lu = __builtin_amdgcn_readlane(L, p[u]);
-                    double* srow = S + (size_t)Lu * d;
-#pragma unroll
-                    for (int m = 0; m < FPL; ++m) {
-                        const int f = lane + 64 * m;
-                        if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
-                    }
-                    if (lane == 0) __hip_atomic_fetch_add(cnt + Lu, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
+                if (lane == 0) __hip_atomic_fetch_add(cnt + Lu, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
     }
@@ -132,6 +137,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     double* S = reinterpret_cast<double*>(smem);
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
     int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [2][TILE] labels of a tile
+    int32_t* wlist = lbl + 2 * TILE;                           // [kWaves][TILE] owned samples per wave
 
     // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
@@ -189,7 +195,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
 #pragma unroll
             for (int r = 0; r < R; ++r) lb[r * kBlock + tid] = lab[r];
             __syncthreads();
-            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lb, S, cnt, lane, wave);
+            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lb, wlist + wave * TILE, S, cnt, lane, wave);
             buf ^= 1;
         }
     }
