@@ -23,8 +23,9 @@ throughput it carries:
                  sigma 2, seed 2, 20 iterations);
   fp8_workload   FP32, FP8 and BF16 on n = 2^24, d = 32, k = 256 (256
                  anisotropic blobs, seed 3, 15 iterations);
-  batched_workload  512 independent instances advanced together (autotuned
-                 schedule, one graph launch), next to per-instance calls;
+  batched_workload  512 independent instances advanced together with BF16
+                 MFMA distances (autotuned schedule, one graph launch), next
+                 to the FP32 batch and to per-instance FP32 calls;
   cpu_baseline   the FP64 oracle timed on this host's cores on a bounded sample
                  of the headline workload.
 """
@@ -178,24 +179,16 @@ def mixed_report(B, torch, w, X, C0, steps, warmup, fp, precision="bf16"):
             "full_scan_fraction_last_iter": mx["full_scans"] / w.n, "roofline": roof}
 
 
-def batched_report(B, torch, iters, per_instance_sample=32):
-    """The 512-instance workload: autotuned schedule, one graph launch for all
-    iterations of all instances, timed; next to it the same instances through
-    single-instance kmeans_lloyd calls (a sample, extrapolated)."""
-    import numpy as np
-    from paper_1109_0778_amd import autotune, datagen
-    dev = torch.device("cuda", 0)
-    inst, shapes = [], []
-    for s_ in range(datagen.BATCH_COUNT):
-        shp, X, C = datagen.batch_instance(s_)
-        shapes.append(shp)
-        inst.append({"X": torch.from_numpy(X).to(dev), "C": torch.from_numpy(C).to(dev),
-                     "labels": torch.empty(shp.n, dtype=torch.int32, device=dev),
-                     "counts": torch.empty(shp.k, dtype=torch.int64, device=dev),
-                     "obj_hist": torch.zeros(iters, dtype=torch.float64, device=dev)})
-    C0 = [t["C"].clone() for t in inst]
-    batch = B.Batch(inst)
-    choice, tune_ms = autotune.tune_batch(batch, use_cache=False)
+def _batched_run(B, torch, inst, C0, iters, precision, schedule=None):
+    """Autotune (or set) the schedule, capture the iterations as one graph,
+    reset the centroids and time one graph launch."""
+    from paper_1109_0778_amd import autotune
+    batch = B.Batch(inst, precision=precision)
+    if schedule is None:
+        choice, tune_ms = autotune.tune_batch(batch, use_cache=False)
+    else:
+        batch.set_schedule(*schedule)
+        choice, tune_ms = tuple(schedule), {}
     batch.use_graphs(True)
     B.kmeans_lloyd_batched(batch, iters)            # capture + warm-up
     torch.cuda.synchronize()
@@ -206,6 +199,36 @@ def batched_report(B, torch, iters, per_instance_sample=32):
     B.kmeans_lloyd_batched(batch, iters)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    out = [(t["labels"].clone(), t["C"].clone()) for t in inst]
+    for t, c in zip(inst, C0):
+        t["C"].copy_(c)
+    del batch
+    torch.cuda.synchronize()
+    return el, choice, tune_ms, out
+
+
+def batched_report(B, torch, iters, per_instance_sample=32):
+    """The 512-instance workload with BF16 MFMA distances (and the FP32 batch
+    beside it): autotuned schedule, one graph launch for all iterations of all
+    instances, timed; the FP32 batch re-run at the BF16 schedule must give the
+    same labels and centroids; next to them the same instances through
+    single-instance FP32 kmeans_lloyd calls (a sample, extrapolated)."""
+    import numpy as np
+    from paper_1109_0778_amd import datagen
+    dev = torch.device("cuda", 0)
+    inst, shapes = [], []
+    for s_ in range(datagen.BATCH_COUNT):
+        shp, X, C = datagen.batch_instance(s_)
+        shapes.append(shp)
+        inst.append({"X": torch.from_numpy(X).to(dev), "C": torch.from_numpy(C).to(dev),
+                     "labels": torch.empty(shp.n, dtype=torch.int32, device=dev),
+                     "counts": torch.empty(shp.k, dtype=torch.int64, device=dev),
+                     "obj_hist": torch.zeros(iters, dtype=torch.float64, device=dev)})
+    C0 = [t["C"].clone() for t in inst]
+    el32, ch32, tm32, _ = _batched_run(B, torch, inst, C0, iters, "fp32")
+    el16, ch16, tm16, res16 = _batched_run(B, torch, inst, C0, iters, "bf16")
+    _, _, _, res32s = _batched_run(B, torch, inst, C0, iters, "fp32", schedule=ch16)
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(res16, res32s))
     pts = sum(s_.n for s_ in shapes)
     evals = sum(s_.n * s_.k for s_ in shapes)
     nbytes = sum(s_.n * s_.d * 4 + 8 * s_.n for s_ in shapes)
@@ -226,18 +249,23 @@ def batched_report(B, torch, iters, per_instance_sample=32):
         torch.cuda.synchronize()
         el_single += time.perf_counter() - t1
     el_single *= len(inst) / per_instance_sample
-    log(f"batched: {len(inst)} instances x {iters} iterations in {el * 1e3:.1f} ms "
-        f"(per-instance launches, extrapolated: {el_single * 1e3:.1f} ms); schedule {choice}")
+    log(f"batched: {len(inst)} instances x {iters} iterations: BF16 {el16 * 1e3:.1f} ms (schedule {ch16}), "
+        f"FP32 {el32 * 1e3:.1f} ms (schedule {ch32}); identical to FP32 at the same schedule: {same}; "
+        f"per-instance FP32 launches, extrapolated: {el_single * 1e3:.1f} ms")
     return {"workload": f"batched: {len(inst)} instances, n log-uniform [1e3, 2e5] (total {pts}), d in {{16,32,64}}, "
                         f"k uniform [4,128], blobs = k, sigma 1, seeds 0..{len(inst) - 1}, {iters} iterations",
-            "value": len(inst) * iters / el, "unit": "instance-iterations/s",
-            "ms_per_round": el * 1e3 / iters,
-            "dist_evals_per_s": evals * iters / el,
-            "hbm_gbps_algorithmic": nbytes * iters / el / 1e9,
+            "precision": "bf16", "value": len(inst) * iters / el16, "unit": "instance-iterations/s",
+            "ms_per_round": el16 * 1e3 / iters,
+            "dist_evals_per_s": evals * iters / el16,
+            "hbm_gbps_algorithmic": nbytes * iters / el16 / 1e9,
+            "fp32_batched_value": len(inst) * iters / el32,
+            "speedup_vs_fp32_batched": el32 / el16,
+            "labels_and_centroids_equal_fp32_batched": bool(same),
             "per_instance_launches_value": len(inst) * iters / el_single,
-            "speedup_vs_per_instance_launches": el_single / el,
-            "schedule": {"tiles_per_block": choice[0], "order": choice[1], "candidates_ms": tune_ms},
-            "precision": "fp32", "graph": True}
+            "speedup_vs_per_instance_launches": el_single / el16,
+            "schedule": {"tiles_per_block": ch16[0], "order": ch16[1], "candidates_ms": tm16},
+            "schedule_fp32": {"tiles_per_block": ch32[0], "order": ch32[1], "candidates_ms": tm32},
+            "graph": True}
 
 
 def cpu_baseline(X, C0, iters, budget_s):

@@ -6,7 +6,8 @@ partial records to merge; more, shorter blocks fill the 256 CUs better) and on
 the order blocks are launched in (largest work first evens out the tail).  The
 tuner times one Lloyd iteration of every candidate on the batch itself, with
 HIP events, and keeps the fastest; results are cached in a JSON file keyed by
-the GPU architecture and a signature of the batch's shapes.
+the GPU architecture, the distance precision and a signature of the batch's
+shapes.
 """
 from __future__ import annotations
 
@@ -14,7 +15,7 @@ import hashlib
 import json
 import os
 
-CANDIDATES = [(tpb, order) for tpb in (4, 8, 16, 32, 64) for order in (1, 0)]
+CANDIDATES = [(tpb, order) for tpb in (1, 2, 4, 8, 16, 32) for order in (1, 0)]
 
 
 def cache_path() -> str:
@@ -63,7 +64,7 @@ def tune_batch(batch, reps: int = 2, use_cache: bool = True, verbose: bool = Fal
     import torch
     from . import binding as B
 
-    key = f"{_arch()}:{signature(batch.instances)}"
+    key = f"{_arch()}:{getattr(batch, 'precision', 'fp32')}:{signature(batch.instances)}"
     db = _load() if use_cache else {}
     if key in db:
         tpb, order = db[key]["choice"]

@@ -227,6 +227,7 @@ class Batch:
     def __init__(self, instances, precision: str = "fp32", device=None):
         import torch
         self.instances = instances
+        self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         arr = (KmInstance * len(instances))()
         for i, t in enumerate(instances):

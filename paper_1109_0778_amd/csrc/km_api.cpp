@@ -201,6 +201,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.rq = reinterpret_cast<int32_t*>(ws + p->off_rq);
     m.rq_count = reinterpret_cast<int32_t*>(ws + p->off_rqc);
     m.rq_per_block = p->rq_per_block;
+    m.nreg = p->grid_mfma;
     m.changed_part = changed;
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
@@ -213,6 +214,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     RecheckArgs r{};
     r.X = X; r.Cp = reinterpret_cast<const float*>(ws + p->off_cp); r.n = p->n; r.d = p->d; r.k = p->k;
     r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = rq_ints(p->fmt);
+    r.nreg = p->grid_mfma;
     r.labels = labels; r.changed_part = changed + p->grid_mfma;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
     return launch_recheck(p->D8, r, p->grid_mfma, s);

@@ -1,8 +1,12 @@
 // Host side of the batched C ABI: many independent Lloyd problems advanced
-// together.  Every iteration is one launch of the per-sample pass per shape
-// class (instances grouped by padded dimension and by the LDS their record
-// needs) over a table of (instance, tile range, partial slot) blocks, plus one
-// finalize launch over (instance, 64-element chunk) blocks.
+// together.  FP32: every iteration is one launch of the fused per-sample pass
+// per shape class (instances grouped by padded dimension and by the LDS their
+// record needs) over a table of (instance, tile range, partial slot) blocks,
+// plus one finalize launch over (instance, 64-element chunk) blocks.  BF16:
+// per iteration one centroid-prep launch (a block per instance), the MFMA
+// pass per operand width and the exact recheck per feature width over their
+// own work tables, the update pass per shape class, the finalize and the
+// objective; the |x| statistics once per call.
 #include "kmeans_mi355x.h"
 #include "km_internal.h"
 
@@ -43,16 +47,19 @@ km_status bhip(hipError_t e, const char* what)
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Group {
-    int D8;
+    int D8;               // D8 (pass, recheck) or D16 (MFMA pass)
     size_t lds;
     int first, count;     // range in the work table
 };
+
+constexpr int kBatchRecheckSplit = 2;   // recheck blocks per queue region
 
 }  // namespace
 
 struct km_batch {
     std::vector<km_instance> inst;
     int device = 0;
+    bool mixed = false;    // BF16 MFMA distances + exact FP32 recheck
     int tpb = 16;          // tiles per block
     int order = 1;         // 0: instance order, 1: decreasing work per block
     // derived layout
@@ -62,6 +69,12 @@ struct km_batch {
     std::vector<BatchFinWork> fwork;
     std::vector<Group> groups;
     size_t off_pa = 0, off_fa = 0, off_work = 0, off_fwork = 0, total = 0;
+    // mixed path
+    std::vector<int> nreg;                 // MFMA queue regions per instance
+    std::vector<size_t> off_xs, off_ab, off_bias, off_cs, off_rq, off_rqc, off_chg, off_jt;
+    std::vector<BatchWork> mwork, rwork;   // MFMA rows, recheck rows
+    std::vector<Group> mgroups, rgroups;
+    size_t off_bm = 0, off_mwork = 0, off_rwork = 0;
     unsigned char* ws = nullptr;
     // graph
     bool use_graph = false;
@@ -83,6 +96,41 @@ struct km_batch {
 namespace {
 
 int d8_of(int d) { return (d + 7) / 8; }
+int d16_of(int d) { return (d + 15) / 16; }
+int kpad_of(int k) { return (k + kMixCK - 1) / kMixCK * kMixCK; }
+int ib_of(int kpad)
+{
+    int ib = 1;
+    while ((1 << ib) < kpad) ++ib;
+    return ib;
+}
+
+// Rows grouped by key, optionally in decreasing cost, appended to `out`.
+void emit_groups(std::map<std::pair<int, size_t>, std::vector<BatchWork>>& by, std::map<std::pair<int, size_t>,
+                 std::vector<double>>& costs, int order, std::vector<BatchWork>& out, std::vector<Group>& groups)
+{
+    out.clear();
+    groups.clear();
+    for (auto& kv : by) {
+        std::vector<BatchWork>& v = kv.second;
+        if (order == 1) {
+            std::vector<double>& c = costs[kv.first];
+            std::vector<int> idx(v.size());
+            for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int)q;
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c[a] > c[b]; });
+            std::vector<BatchWork> s(v.size());
+            for (size_t q = 0; q < idx.size(); ++q) s[q] = v[idx[q]];
+            v.swap(s);
+        }
+        Group g;
+        g.D8 = kv.first.first;
+        g.lds = kv.first.second;
+        g.first = (int)out.size();
+        g.count = (int)v.size();
+        groups.push_back(g);
+        out.insert(out.end(), v.begin(), v.end());
+    }
+}
 
 size_t lds_bucket(size_t lds)
 {
@@ -100,7 +148,6 @@ void layout(km_batch* B)
     B->off_cp.assign(m, 0); B->off_S.assign(m, 0); B->off_cnt.assign(m, 0);
     B->off_J.assign(m, 0); B->off_ch.assign(m, 0); B->off_bad.assign(m, 0);
     std::map<std::pair<int, size_t>, std::vector<BatchWork>> by_group;
-    std::vector<double> cost_of;   // parallel to by_group vectors (work per block)
     std::map<std::pair<int, size_t>, std::vector<double>> costs;
     B->fwork.clear();
     size_t off = 0;
@@ -130,26 +177,55 @@ void layout(km_batch* B)
         B->off_ch[i] = off;  off = al256(off + (size_t)nb * sizeof(int32_t));
         B->off_bad[i] = off; off = al256(off + (size_t)nb * sizeof(int32_t));
     }
-    B->work.clear();
-    B->groups.clear();
-    for (auto& kv : by_group) {
-        std::vector<BatchWork>& v = kv.second;
-        if (B->order == 1) {
-            std::vector<double>& c = costs[kv.first];
-            std::vector<int> idx(v.size());
-            for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int)q;
-            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c[a] > c[b]; });
-            std::vector<BatchWork> s(v.size());
-            for (size_t q = 0; q < idx.size(); ++q) s[q] = v[idx[q]];
-            v.swap(s);
+    emit_groups(by_group, costs, B->order, B->work, B->groups);
+    if (B->mixed) {
+        // MFMA rows of 2 * tpb 128-sample tiles (the same samples as a pass row),
+        // one queue region per row; recheck rows: kBatchRecheckSplit per region
+        const int tpm = 2 * B->tpb;
+        std::map<std::pair<int, size_t>, std::vector<BatchWork>> by_m, by_r;
+        std::map<std::pair<int, size_t>, std::vector<double>> c_m, c_r;
+        B->nreg.assign(m, 0);
+        B->off_xs.assign(m, 0); B->off_ab.assign(m, 0); B->off_bias.assign(m, 0); B->off_cs.assign(m, 0);
+        B->off_rq.assign(m, 0); B->off_rqc.assign(m, 0); B->off_chg.assign(m, 0); B->off_jt.assign(m, 0);
+        for (int i = 0; i < m; ++i) {
+            const km_instance& x = B->inst[i];
+            const int D16 = d16_of(x.d), kpad = kpad_of(x.k);
+            const int64_t mt = (x.n + kMixTile - 1) / kMixTile;
+            const int nr = (int)((mt + tpm - 1) / tpm);
+            B->nreg[i] = nr;
+            for (int r = 0; r < nr; ++r) {
+                BatchWork w;
+                w.inst = i;
+                w.slot = r;
+                w.t0 = (int64_t)r * tpm;
+                w.t1 = std::min<int64_t>(mt, w.t0 + tpm);
+                by_m[std::make_pair(D16, (size_t)0)].push_back(w);
+                c_m[std::make_pair(D16, (size_t)0)].push_back((double)(w.t1 - w.t0) * kpad * D16);
+                for (int y = 0; y < kBatchRecheckSplit; ++y) {
+                    BatchWork rw;
+                    rw.inst = i;
+                    rw.slot = r;
+                    rw.t0 = y;
+                    rw.t1 = kBatchRecheckSplit;
+                    by_r[std::make_pair(d8_of(x.d), (size_t)0)].push_back(rw);
+                    c_r[std::make_pair(d8_of(x.d), (size_t)0)].push_back((double)(w.t1 - w.t0) * x.d);
+                }
+            }
+            B->off_xs[i] = off;   off = al256(off + sizeof(XStats));
+            B->off_ab[i] = off;   off = al256(off + (size_t)kpad * 16 * D16 * sizeof(__bf16));
+            B->off_bias[i] = off; off = al256(off + (size_t)kpad * sizeof(float));
+            B->off_cs[i] = off;   off = al256(off + sizeof(CStats));
+            B->off_rq[i] = off;   off = al256(off + (size_t)nr * tpm * kMixTile * rq_ints(FMT_BF16) * sizeof(int32_t));
+            B->off_rqc[i] = off;  off = al256(off + 2 * (size_t)nr * sizeof(int32_t));
+            B->off_chg[i] = off;  off = al256(off + (size_t)(1 + kBatchRecheckSplit) * nr * sizeof(int32_t));
+            B->off_jt[i] = off;   off = al256(off + (size_t)finalize_blocks(x.k, x.d) * sizeof(double));
         }
-        Group g;
-        g.D8 = kv.first.first;
-        g.lds = kv.first.second;
-        g.first = (int)B->work.size();
-        g.count = (int)v.size();
-        B->groups.push_back(g);
-        B->work.insert(B->work.end(), v.begin(), v.end());
+        emit_groups(by_m, c_m, B->order, B->mwork, B->mgroups);
+        emit_groups(by_r, c_r, B->order, B->rwork, B->rgroups);
+        for (Group& g : B->mgroups) g.lds = mfma_lds_bytes(FMT_BF16, g.D8);
+        B->off_bm = off;    off = al256(off + (size_t)m * sizeof(BatchMix));
+        B->off_mwork = off; off = al256(off + B->mwork.size() * sizeof(BatchWork));
+        B->off_rwork = off; off = al256(off + B->rwork.size() * sizeof(BatchWork));
     }
     B->off_pa = off;    off = al256(off + (size_t)m * sizeof(PassArgs));
     B->off_fa = off;    off = al256(off + (size_t)m * sizeof(FinArgs));
@@ -178,13 +254,52 @@ km_status upload(km_batch* B)
         PassArgs& a = pa[i];
         std::memset(&a, 0, sizeof a);
         a.X = x.X; a.Cp = Cp; a.labels = x.labels; a.mindist = nullptr; a.part = pt; a.ctrl = nullptr;
-        a.n = x.n; a.d = x.d; a.k = x.k; a.iter = 0; a.count_changed = 1; a.kc = x.k;
+        a.n = x.n; a.d = x.d; a.k = x.k; a.iter = 0; a.count_changed = 0; a.kc = x.k;
         FinArgs& f = fa[i];
         std::memset(&f, 0, sizeof f);
         f.part = pt; f.G = B->nslots[i]; f.GJ = B->nslots[i]; f.GC = B->nslots[i];
         f.k = x.k; f.d = x.d; f.D = 8 * D8;
         f.C_old = Cp; f.ld_old = 8 * D8; f.C_new = x.C; f.ld_new = x.d; f.Cp_out = Cp;
         f.counts = x.counts; f.ctrl = nullptr; f.obj_hist = x.obj_hist; f.tol = -1.0; f.want_J = 1; f.jmode = 0;
+        if (B->mixed) {
+            f.jmode = 1;
+            f.Jterm = reinterpret_cast<double*>(ws + B->off_jt[i]);
+            f.sum_xn2 = &reinterpret_cast<const XStats*>(ws + B->off_xs[i])->sum_xn2;
+        }
+    }
+    std::vector<BatchMix> bm(B->mixed ? m : 0);
+    for (int i = 0; B->mixed && i < m; ++i) {
+        const km_instance& x = B->inst[i];
+        const int D16 = d16_of(x.d), kpad = kpad_of(x.k);
+        BatchMix& b = bm[i];
+        std::memset(&b, 0, sizeof b);
+        const int nr = B->nreg[i];
+        int32_t* chg = reinterpret_cast<int32_t*>(ws + B->off_chg[i]);
+        MixArgs& mm = b.m;
+        mm.X = x.X; mm.n = x.n; mm.d = x.d; mm.k = x.k; mm.kpad = kpad;
+        mm.Ab = ws + B->off_ab[i];
+        mm.bias = reinterpret_cast<const float*>(ws + B->off_bias[i]);
+        mm.cs = reinterpret_cast<const CStats*>(ws + B->off_cs[i]);
+        mm.Xq = nullptr; mm.xst = nullptr;
+        mm.u = 0.00390625f;                  // BF16 unit roundoff 2^-8
+        mm.IB = ib_of(kpad);
+        mm.gamma_terms = 2 * 16 * D16 + 8;
+        mm.D8 = d8_of(x.d);
+        mm.labels = x.labels;
+        mm.rq = reinterpret_cast<int32_t*>(ws + B->off_rq[i]);
+        mm.rq_count = reinterpret_cast<int32_t*>(ws + B->off_rqc[i]);
+        mm.rq_per_block = (int64_t)2 * B->tpb * kMixTile;
+        mm.nreg = nr;
+        mm.changed_part = chg;
+        mm.ctrl = nullptr; mm.iter = 0; mm.count_changed = 0;
+        RecheckArgs& r = b.r;
+        r.X = x.X; r.Cp = reinterpret_cast<const float*>(ws + B->off_cp[i]); r.n = x.n; r.d = x.d; r.k = x.k;
+        r.rq = mm.rq; r.rq_count = mm.rq_count; r.rq_per_block = mm.rq_per_block; r.rq_ints = rq_ints(FMT_BF16);
+        r.nreg = nr; r.labels = x.labels; r.changed_part = chg + nr; r.ctrl = nullptr; r.iter = 0; r.count_changed = 0;
+        b.Cp = r.Cp;
+        b.D = 8 * d8_of(x.d);
+        b.DP = 16 * D16;
+        b.xs = reinterpret_cast<XStats*>(ws + B->off_xs[i]);
     }
     hipError_t e;
     if ((e = hipMemcpy(ws + B->off_pa, pa.data(), pa.size() * sizeof(PassArgs), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -194,6 +309,13 @@ km_status upload(km_batch* B)
         (e = hipMemcpy(ws + B->off_fwork, B->fwork.data(), B->fwork.size() * sizeof(BatchFinWork),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bhip(e, "hipMemcpy(batch tables)");
+    if (B->mixed &&
+        ((e = hipMemcpy(ws + B->off_bm, bm.data(), bm.size() * sizeof(BatchMix), hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = hipMemcpy(ws + B->off_mwork, B->mwork.data(), B->mwork.size() * sizeof(BatchWork),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = hipMemcpy(ws + B->off_rwork, B->rwork.data(), B->rwork.size() * sizeof(BatchWork),
+                        hipMemcpyHostToDevice)) != hipSuccess))
+        return bhip(e, "hipMemcpy(batch mixed tables)");
     return KM_OK;
 }
 
@@ -204,15 +326,32 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
     const PassArgs* pa = reinterpret_cast<const PassArgs*>(ws + B->off_pa);
     const BatchWork* work = reinterpret_cast<const BatchWork*>(ws + B->off_work);
     const BatchFinWork* fwork = reinterpret_cast<const BatchFinWork*>(ws + B->off_fwork);
-    hipError_t e = launch_batch_pad(fa, nullptr, (int)B->inst.size(), s);
+    const int m = (int)B->inst.size();
+    hipError_t e = launch_batch_pad(fa, nullptr, m, s);
     if (e != hipSuccess) return bhip(e, "batch pad launch");
+    const BatchMix* bm = reinterpret_cast<const BatchMix*>(ws + B->off_bm);
+    const BatchWork* mwork = reinterpret_cast<const BatchWork*>(ws + B->off_mwork);
+    const BatchWork* rwork = reinterpret_cast<const BatchWork*>(ws + B->off_rwork);
+    if (B->mixed && (e = launch_batch_prep_x(bm, m, s)) != hipSuccess) return bhip(e, "batch prep_x launch");
     for (int32_t t = 0; t < iters; ++t) {
+        if (B->mixed) {
+            if ((e = launch_batch_prep_c(bm, m, s)) != hipSuccess) return bhip(e, "batch prep_c launch");
+            for (const Group& g : B->mgroups)
+                if ((e = launch_batch_mfma(g.D8, mwork + g.first, g.count, bm, t, s)) != hipSuccess)
+                    return bhip(e, "batch MFMA launch");
+            for (const Group& g : B->rgroups)
+                if ((e = launch_batch_recheck(g.D8, rwork + g.first, g.count, bm, t, s)) != hipSuccess)
+                    return bhip(e, "batch recheck launch");
+        }
         for (const Group& g : B->groups) {
-            if ((e = launch_batch_pass(g.D8, work + g.first, g.count, pa, t, g.lds, s)) != hipSuccess)
+            if ((e = launch_batch_pass(g.D8, B->mixed ? MODE_UPDATE : MODE_FUSED, work + g.first, g.count, pa, t,
+                                       g.lds, s)) != hipSuccess)
                 return bhip(e, "batch pass launch");
         }
         if ((e = launch_batch_finalize(fwork, (int)B->fwork.size(), fa, t, s)) != hipSuccess)
             return bhip(e, "batch finalize launch");
+        if (B->mixed && (e = launch_batch_objective(fa, m, t, s)) != hipSuccess)
+            return bhip(e, "batch objective launch");
     }
     return KM_OK;
 }
@@ -228,7 +367,7 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
     *out = nullptr;
     if (!inst || count < 1) return berr(KM_EINVAL, "need at least one instance");
     if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3) return berr(KM_EINVAL, "unknown precision %d", (int)prec);
-    if (prec != KM_FP32) return berr(KM_ENOTSUP, "batched Lloyd supports FP32 distances only");
+    if (prec == KM_FP8_E4M3) return berr(KM_ENOTSUP, "batched Lloyd supports FP32 and BF16 distances");
     for (int32_t i = 0; i < count; ++i) {
         const km_instance& x = inst[i];
         if (x.n < 1 || x.n >= ((int64_t)1 << 31)) return berr(KM_EINVAL, "instance %d: n outside [1, 2^31)", i);
@@ -240,6 +379,8 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
         if (x.d > 8 * kMaxD8Plain) return berr(KM_ENOTSUP, "instance %d: batched Lloyd supports d <= 128", i);
         if (plain_lds_bytes(x.k, x.d, MODE_FUSED) > 80 * 1024)
             return berr(KM_ENOTSUP, "instance %d: k*d too large for a batched per-label record", i);
+        if (prec == KM_BF16 && kpad_of(x.k) > 16384)
+            return berr(KM_ENOTSUP, "instance %d: BF16 distances support k <= 16384", i);
     }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -248,6 +389,7 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
     if (!B) return berr(KM_EINVAL, "out of host memory");
     B->inst.assign(inst, inst + count);
     B->device = dev;
+    B->mixed = prec == KM_BF16;
     layout(B);
     *out = B;
     return KM_OK;

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(128) void batch_finalize_kernel(const BatchFinWork*
     const int64_t kd = (int64_t)a.k * a.d;
     if (wave == 0) {
         const int64_t e = (int64_t)w.chunk * 64 + lane;
+        double term = 0.0;
         if (e < kd) {
             const int j = (int)(e / a.d);
             const int f = (int)(e - (int64_t)j * a.d);
@@ -154,14 +155,41 @@ __global__ __launch_bounds__(128) void batch_finalize_kernel(const BatchFinWork*
             a.C_new[(size_t)j * a.ld_new + f] = v;
             if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
             if (a.counts && f == 0) a.counts[j] = c;
+            const double co = (double)old;
+            term = (double)c * co * co - 2.0 * co * S;
         }
-    } else if (w.chunk == 0) {
+        if (a.jmode == 1) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
+            if (lane == 0) a.Jterm[w.chunk] = term;
+        }
+    } else if (w.chunk == 0 && a.jmode == 0) {
         double J = 0.0;
         for (int b = lane; b < a.GJ; b += 64) J += a.part.J[b];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) J += __shfl_xor(J, off);
         if (lane == 0 && a.obj_hist) a.obj_hist[iter] = J;
     }
+}
+
+// Batched objective with jmode 1: sum_i |x_i|^2 plus the Jterm shares of the
+// instance's finalize blocks, in a fixed order; one wave per instance.
+__global__ __launch_bounds__(64) void batch_objective_kernel(const FinArgs* __restrict__ fa, int32_t iter)
+{
+    const FinArgs a = fa[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int nb = finalize_blocks(a.k, a.d);
+    double J = 0.0;
+    for (int b = lane; b < nb; b += 64) J += a.Jterm[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) J += __shfl_xor(J, off);
+    if (lane == 0 && a.obj_hist) a.obj_hist[iter] = *a.sum_xn2 + J;
+}
+
+hipError_t launch_batch_objective(const FinArgs* fa, int ninst, int iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_objective_kernel, dim3(ninst), dim3(64), 0, s, fa, iter);
+    return hipGetLastError();
 }
 
 // Batched: each instance's C (in FinArgs.C_new, row stride d) padded into its

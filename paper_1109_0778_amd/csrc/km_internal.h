@@ -97,12 +97,17 @@ hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, dim3 grid, si
                              hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 __host__ __device__ inline int finalize_blocks(int k, int d) { return (int)(((int64_t)k * d + 63) / 64); }
-hipError_t launch_batch_pass(int D8, const BatchWork* work, int nwork, const PassArgs* insts, int iter,
+// Batched per-sample pass (mode FUSED, or UPDATE from the labels a mixed
+// assign wrote) over a work table.
+hipError_t launch_batch_pass(int D8, Mode mode, const BatchWork* work, int nwork, const PassArgs* insts, int iter,
                              size_t lds_bytes, hipStream_t s);
-// Batched finalize: one block per (instance, 64 elements); also pads the
-// instances' centroids at the start of a call (pad = true).
+// Batched finalize: one block per (instance, 64 elements); with jmode 1 each
+// block writes its Jterm share and launch_batch_objective (one wave per
+// instance) forms the objective.  batch_pad pads the instances' centroids at
+// the start of a call.
 struct BatchFinWork { int32_t inst; int32_t chunk; };
 hipError_t launch_batch_finalize(const BatchFinWork* work, int nwork, const FinArgs* fa, int iter, hipStream_t s);
+hipError_t launch_batch_objective(const FinArgs* fa, int ninst, int iter, hipStream_t s);
 hipError_t launch_batch_pad(const FinArgs* fa, const float* const* C_in, int ninst, hipStream_t s);
 // Resident blocks per CU of the plain pass (HIP occupancy query), -1 on error.
 int plain_blocks_per_cu(int D8, Mode mode, size_t lds_bytes);
@@ -136,7 +141,7 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
 // BF16 or FP8 MFMA distances with a proven error band and an exact FP32 recheck.
 enum MixFmt { FMT_BF16 = 0, FMT_FP8 = 1 };
 constexpr int kMixWaves = 4;                    // waves per block
-constexpr int kMixNB = 2;                       // 32-sample column blocks per wave
+constexpr int kMixNB = 1;                       // 32-sample column blocks per wave
 constexpr int kMixTile = kMixWaves * kMixNB * 32;
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
 // Candidates kept per lane (half a sample's rows); the FP8 band is about 16
@@ -179,10 +184,11 @@ struct MixArgs {
     int32_t gamma_terms;        // m of the gamma_m accumulation bound
     int32_t D8;                 // chunks of the canonical FP32 distance
     int32_t* labels;
-    int32_t* rq;                // [grid][rq_per_block][rq_ints] recheck entries, one region per block
-    int32_t* rq_count;          // [2][grid] entries queued by each block, then full scans among them
+    int32_t* rq;                // [nreg][rq_per_block][rq_ints] recheck entries, one region per block
+    int32_t* rq_count;          // [2][nreg] entries queued in each region, then full scans among them
     int64_t rq_per_block;       // region capacity (tiles per block x samples per tile)
-    int32_t* changed_part;      // [grid]
+    int32_t nreg;               // queue regions (one per MFMA block or work row)
+    int32_t* changed_part;      // [nreg]
     const Ctrl* ctrl;
     int32_t iter;
     int32_t count_changed;
@@ -197,6 +203,7 @@ struct RecheckArgs {
     const int32_t* rq_count;    // [grid]; recheck block b takes region b
     int64_t rq_per_block;
     int32_t rq_ints;            // ints per entry
+    int32_t nreg;               // queue regions; changed_part is [splits][nreg]
     int32_t* labels;
     int32_t* changed_part;      // [grid]
     const Ctrl* ctrl;
@@ -217,5 +224,22 @@ hipError_t launch_mfma_assign(int fmt, int D16, const MixArgs& a, int grid, hipS
 size_t mfma_lds_bytes(int fmt, int D16);
 int mfma_blocks_per_cu(int fmt, int D16);
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
+
+// Batched mixed path: one record per instance.  The per-iteration prep and
+// the |x| statistics run one block per instance; the MFMA pass and the
+// recheck run over work tables (BatchWork: instance, queue region, tile range
+// [t0, t1) of 128-sample tiles for the MFMA pass; instance, region, split t0
+// of t1 splits for the recheck).
+struct BatchMix {
+    MixArgs m;
+    RecheckArgs r;
+    const float* Cp;            // [k][D] padded FP32 centroids
+    int32_t D, DP;
+    XStats* xs;
+};
+hipError_t launch_batch_prep_x(const BatchMix* bm, int ninst, hipStream_t s);
+hipError_t launch_batch_prep_c(const BatchMix* bm, int ninst, hipStream_t s);
+hipError_t launch_batch_mfma(int D16, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s);
+hipError_t launch_batch_recheck(int D8, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s);
 
 }  // namespace km

@@ -183,10 +183,9 @@ __global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ 
 // One block: BF16 operand rows bf16(-2 c_j) (zero padded to DP features and
 // kpad rows), biases K + |c_j|^2 (huge for padded rows) and the band constants.
 // The centroid loop invariants are hoisted here, out of the per-sample pass.
-__global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ Cp, int32_t k, int32_t d,
-                                                     int32_t D, int32_t kpad, int32_t DP,
-                                                     const XStats* __restrict__ xs, __bf16* Ab,
-                                                     float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter)
+__device__ __forceinline__ void prep_c_body(const float* __restrict__ Cp, int32_t k, int32_t d, int32_t D,
+                                            int32_t kpad, int32_t DP, const XStats* __restrict__ xs, __bf16* Ab,
+                                            float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter)
 {
     __shared__ float smax[256];
     if (ctrl != nullptr && ctrl->stop_iter < iter) return;
@@ -227,6 +226,65 @@ __global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ C
         cs->inv_r = 2.0f;
         cs->cl1 = 0.0f;
         cs->pad[0] = cs->pad[1] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ Cp, int32_t k, int32_t d,
+                                                     int32_t D, int32_t kpad, int32_t DP,
+                                                     const XStats* __restrict__ xs, __bf16* Ab,
+                                                     float* bias, CStats* cs, const Ctrl* ctrl, int32_t iter)
+{
+    prep_c_body(Cp, k, d, D, kpad, DP, xs, Ab, bias, cs, ctrl, iter);
+}
+
+// Batched (BF16): one block per instance.
+__global__ __launch_bounds__(256) void batch_prep_c_kernel(const BatchMix* __restrict__ bm)
+{
+    const BatchMix& b = bm[blockIdx.x];
+    prep_c_body(b.Cp, b.m.k, b.m.d, b.D, b.m.kpad, b.DP, b.xs,
+                const_cast<__bf16*>(static_cast<const __bf16*>(b.m.Ab)), const_cast<float*>(b.m.bias),
+                const_cast<CStats*>(b.m.cs), nullptr, 0);
+}
+
+// Batched run-level statistics: one block per instance, rows in a fixed
+// order per thread, then a fixed tree.
+__global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchMix* __restrict__ bm)
+{
+    __shared__ float smax[256];
+    __shared__ double ssum[256];
+    const BatchMix& b = bm[blockIdx.x];
+    const float* X = b.m.X;
+    const int64_t n = b.m.n;
+    const int d = b.m.d;
+    const int tid = threadIdx.x;
+    float mx = 0.0f;
+    double sm = 0.0;
+    for (int64_t i = tid; i < n; i += 256) {
+        const float* row = X + i * d;
+        float s32 = 0.0f;
+        double s64 = 0.0;
+        for (int f = 0; f < d; ++f) {
+            const float v = row[f];
+            s32 = __builtin_fmaf(v, v, s32);
+            s64 += (double)v * (double)v;
+        }
+        mx = fmaxf(mx, s32);
+        sm += s64;
+    }
+    smax[tid] = mx;
+    ssum[tid] = sm;
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+        if (tid < st) {
+            smax[tid] = fmaxf(smax[tid], smax[tid + st]);
+            ssum[tid] = ssum[tid] + ssum[tid + st];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        b.xs->max_xn2 = smax[0];
+        b.xs->K = 2.0f * smax[0] * (1.0f + 1e-5f) + 1.0f;
+        b.xs->sum_xn2 = ssum[0];
     }
 }
 
@@ -324,14 +382,18 @@ __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
     return (__float_as_uint(v + W) & ~ibm) | ibm;
 }
 
-// Block = 4 waves; wave w holds the BF16 B-fragments of 2 x 32 samples (the
-// 32-sample column blocks of a 32x32x16 MFMA) for the whole sweep over the
+// Block = 4 waves; wave w holds the B fragments of kMixNB x 32 samples (the
+// 32-sample column blocks of a 32x32x16 MFMA; one block per wave measured
+// fastest: fewer registers, more resident waves) for the whole sweep over the
 // centroids, which stream through LDS in chunks of 64 rows shared by the
 // block.  Lane l of a 32x32 accumulator holds column l % 32 (one sample) and
 // rows 8(i/4) + 4(l/32) + i%4, i < 16 (16 centroids); lanes l and l^32 hold
 // the two halves of a sample's rows.
+// One block's share of the MFMA pass: 128-sample tiles t_first, t_first +
+// t_step, ... below t_end; its recheck entries go to queue region `region`.
 template <int D16, int FMT>
-__global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
+__device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
+                                          int region, unsigned char* smem)
 {
     constexpr bool F8 = FMT == FMT_FP8;
     constexpr int ES = F8 ? 1 : 2;         // operand bytes per feature
@@ -344,7 +406,6 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
     constexpr int SLOTS = cand_slots(FMT);
     constexpr int RQI = rq_ints(FMT);
     constexpr int PF = (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
-    extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* Abuf = smem;                                                   // [2][CK][ROWB]
     float* bbuf = reinterpret_cast<float*>(smem + 2 * CHB);                       // [2][CK]
     uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + 2 * kMixCK);              // [waves][NB][SLOTS][64]
@@ -359,7 +420,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
     const int wave = tid >> 6;
     const int h = lane >> 5;
     if (tid == 0) { blk_count = 0; blk_full = 0; }
-    int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * RQI;
+    int32_t* rq_blk = a.rq + (size_t)region * a.rq_per_block * RQI;
     const int col = lane & 31;
     const int d = a.d;
     const int64_t n = a.n;
@@ -374,6 +435,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
     const float gcan = (10.0f + (a.D8 > 1 ? ceilf(log2f(P)) : 0.0f)) * 5.9604645e-8f;
     const int nchunks = a.kpad / kMixCK;
     const int64_t ntiles = (n + kMixTile - 1) / kMixTile;
+    const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     uint32_t* mycand = cand + (size_t)wave * NB * SLOTS * 64;
     int32_t changed = 0;
 
@@ -402,14 +464,14 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
     uint4 pr[PF];
     float pb = 0.0f;
     int cur = 0;
-    if (blockIdx.x < ntiles) {
+    if (t_first < t_last) {
         KM_LOAD_CHUNK(0)
         KM_STORE_CHUNK(0)
     }
     __syncthreads();
 
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        // --- B fragments and the band of this wave's 2 x 32 samples
+    for (int64_t t = t_first; t < t_last; t += t_step) {
+        // --- B fragments and the band of this wave's samples
         bf16x8 bfr[NB][F8 ? 1 : D16];
         long bq[NB][F8 ? D16 : 1];
         float W[NB];
@@ -481,7 +543,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
         // --- sweep over the centroids; the next chunk (possibly chunk 0 of the
         // next tile) is fetched into registers while this one is computed
         for (int c = 0; c < nchunks; ++c) {
-            const bool pref = nchunks > 1 && (c + 1 < nchunks || t + gridDim.x < ntiles);
+            const bool pref = nchunks > 1 && (c + 1 < nchunks || t + t_step < t_last);
             if (pref) KM_LOAD_CHUNK(c + 1 < nchunks ? c + 1 : 0)
             const unsigned char* Ab_c = Abuf + cur * CHB;
             const float* bb_c = bbuf + cur * kMixCK;
@@ -635,10 +697,30 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
     if (tid == 0) {
         int32_t c = 0;
         for (int w = 0; w < kMixWaves; ++w) c += sred[w];
-        a.changed_part[blockIdx.x] = c;
-        a.rq_count[blockIdx.x] = blk_count;
-        a.rq_count[gridDim.x + blockIdx.x] = blk_full;
+        a.changed_part[region] = c;
+        a.rq_count[region] = blk_count;
+        a.rq_count[a.nreg + region] = blk_full;
     }
+}
+
+template <int D16, int FMT>
+__global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    mfma_body<D16, FMT>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
+}
+
+// Batched instances (BF16): row b of the work table runs tiles [t0, t1) of
+// instance work[b].inst into its queue region work[b].slot.
+template <int D16>
+__global__ __launch_bounds__(64 * kMixWaves) void batch_mfma(const BatchWork* __restrict__ work,
+                                                             const BatchMix* __restrict__ bm, int32_t iter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchWork w = work[blockIdx.x];
+    MixArgs a = bm[w.inst].m;
+    a.iter = iter;
+    mfma_body<D16, FMT_BF16>(a, w.t0, w.t1, 1, w.slot, smem);
 }
 
 // ------------------------------------------------------------ exact recheck
@@ -652,7 +734,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
 // lexicographic (distance, index) minimum over the candidates; entries
 // flagged -1 scan all k centroids in index order.
 template <int D8>
-__global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
+__device__ __forceinline__ void recheck_body(const RecheckArgs& a, int region, int y, int ny)
 {
     constexpr int D = 8 * D8;
     constexpr int GS = D8 <= 1 ? 1 : D8 <= 2 ? 2 : D8 <= 4 ? 4 : D8 <= 8 ? 8 : 16;
@@ -664,12 +746,12 @@ __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
     const int q = lane % GS;
     const int grp = lane / GS;
     const int leader = lane - q;
-    // blocks (b, 0..gridDim.y-1) re-check the entries queued by block b of
-    // the MFMA pass
-    const int count = a.rq_count[blockIdx.x];
-    const int32_t* rq_blk = a.rq + (size_t)blockIdx.x * a.rq_per_block * a.rq_ints;
-    const int wave_id = blockIdx.y * 4 + (tid >> 6);
-    const int nwaves = gridDim.y * 4;
+    // ny blocks re-check the entries of one queue region, block y taking
+    // every ny-th group of waves
+    const int count = a.rq_count[region];
+    const int32_t* rq_blk = a.rq + (size_t)region * a.rq_per_block * a.rq_ints;
+    const int wave_id = y * 4 + (tid >> 6);
+    const int nwaves = ny * 4;
     int32_t changed = 0;
     for (int e0 = wave_id * GPW; e0 < count; e0 += nwaves * GPW) {
         const int e = e0 + grp;
@@ -747,7 +829,25 @@ __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
     for (int off = 32; off >= 1; off >>= 1) changed += __shfl_xor(changed, off);
     if ((tid & 63) == 0) sred[tid >> 6] = changed;
     __syncthreads();
-    if (tid == 0) a.changed_part[blockIdx.y * gridDim.x + blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+    if (tid == 0) a.changed_part[y * a.nreg + region] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+template <int D8>
+__global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a)
+{
+    recheck_body<D8>(a, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// Batched: row b of the work table re-checks region work[b].slot of instance
+// work[b].inst as split t0 of t1.
+template <int D8>
+__global__ __launch_bounds__(256) void batch_recheck(const BatchWork* __restrict__ work,
+                                                     const BatchMix* __restrict__ bm, int32_t iter)
+{
+    const BatchWork w = work[blockIdx.x];
+    RecheckArgs a = bm[w.inst].r;
+    a.iter = iter;
+    recheck_body<D8>(a, w.slot, (int)w.t0, (int)w.t1);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -860,6 +960,58 @@ static int occ_mfma_fmt(int D16)
 int mfma_blocks_per_cu(int fmt, int D16)
 {
     return fmt == FMT_FP8 ? occ_mfma_fmt<FMT_FP8>(D16) : occ_mfma_fmt<FMT_BF16>(D16);
+}
+
+hipError_t launch_batch_prep_x(const BatchMix* bm, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_prep_x_kernel, dim3(ninst), dim3(256), 0, s, bm);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prep_c(const BatchMix* bm, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_prep_c_kernel, dim3(ninst), dim3(256), 0, s, bm);
+    return hipGetLastError();
+}
+
+template <int D16>
+static hipError_t launch_batch_mfma_d16(const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s)
+{
+    const size_t lds = mfma_lds_bytes(FMT_BF16, D16);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_mfma<D16>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((batch_mfma<D16>), dim3(nwork), dim3(64 * kMixWaves), lds, s, work, bm, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_mfma(int D16, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s)
+{
+    switch (D16) {
+    case 1: return launch_batch_mfma_d16<1>(work, nwork, bm, iter, s);
+    case 2: return launch_batch_mfma_d16<2>(work, nwork, bm, iter, s);
+    case 3: return launch_batch_mfma_d16<3>(work, nwork, bm, iter, s);
+    case 4: return launch_batch_mfma_d16<4>(work, nwork, bm, iter, s);
+    case 5: return launch_batch_mfma_d16<5>(work, nwork, bm, iter, s);
+    case 6: return launch_batch_mfma_d16<6>(work, nwork, bm, iter, s);
+    case 7: return launch_batch_mfma_d16<7>(work, nwork, bm, iter, s);
+    case 8: return launch_batch_mfma_d16<8>(work, nwork, bm, iter, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_recheck(int D8, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s)
+{
+    switch (D8) {
+#define KM_BRC(N) case N: hipLaunchKernelGGL((batch_recheck<N>), dim3(nwork), dim3(256), 0, s, work, bm, iter); break;
+    KM_BRC(1) KM_BRC(2) KM_BRC(3) KM_BRC(4) KM_BRC(5) KM_BRC(6) KM_BRC(7) KM_BRC(8)
+    KM_BRC(9) KM_BRC(10) KM_BRC(11) KM_BRC(12) KM_BRC(13) KM_BRC(14) KM_BRC(15) KM_BRC(16)
+#undef KM_BRC
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s)

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
 
 // Batched instances: block b runs tiles [t0, t1) of instance work[b].inst into
 // that instance's partial slot work[b].slot.
-template <int D8>
+template <int D8, int MODE>
 __global__ __launch_bounds__(kBlock) void batch_pass(const BatchWork* __restrict__ work,
                                                      const PassArgs* __restrict__ insts, int32_t iter)
 {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void batch_pass(const BatchWork* __restrict
     const BatchWork w = work[blockIdx.x];
     PassArgs a = insts[w.inst];
     a.iter = iter;
-    pass_body<D8, MODE_FUSED>(a, w.t0, w.t1, 1, w.slot, 0, smem);
+    pass_body<D8, MODE>(a, w.t0, w.t1, 1, w.slot, 0, smem);
 }
 
 template <int D8, int MODE>
@@ -306,24 +306,33 @@ int plain_blocks_per_cu(int D8, Mode mode, size_t lds)
     }
 }
 
-template <int D8>
-static hipError_t launch_batch_d8(const BatchWork* work, int nwork, const PassArgs* insts, int iter, size_t lds,
-                                  hipStream_t s)
+template <int D8, int MODE>
+static hipError_t launch_batch_mode(const BatchWork* work, int nwork, const PassArgs* insts, int iter, size_t lds,
+                                    hipStream_t s)
 {
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_pass<D8>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_pass<D8, MODE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((batch_pass<D8>), dim3(nwork), dim3(kBlock), lds, s, work, insts, iter);
+    hipLaunchKernelGGL((batch_pass<D8, MODE>), dim3(nwork), dim3(kBlock), lds, s, work, insts, iter);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_pass(int D8, const BatchWork* work, int nwork, const PassArgs* insts, int iter, size_t lds,
-                             hipStream_t s)
+template <int D8>
+static hipError_t launch_batch_d8(Mode mode, const BatchWork* work, int nwork, const PassArgs* insts, int iter,
+                                  size_t lds, hipStream_t s)
 {
+    if (mode == MODE_UPDATE) return launch_batch_mode<D8, MODE_UPDATE>(work, nwork, insts, iter, lds, s);
+    return launch_batch_mode<D8, MODE_FUSED>(work, nwork, insts, iter, lds, s);
+}
+
+hipError_t launch_batch_pass(int D8, Mode mode, const BatchWork* work, int nwork, const PassArgs* insts, int iter,
+                             size_t lds, hipStream_t s)
+{
+    if (mode != MODE_FUSED && mode != MODE_UPDATE) return hipErrorInvalidValue;
     switch (D8) {
-#define KM_BP(N) case N: return launch_batch_d8<N>(work, nwork, insts, iter, lds, s);
+#define KM_BP(N) case N: return launch_batch_d8<N>(mode, work, nwork, insts, iter, lds, s);
     KM_BP(1) KM_BP(2) KM_BP(3) KM_BP(4) KM_BP(5) KM_BP(6) KM_BP(7) KM_BP(8)
     KM_BP(9) KM_BP(10) KM_BP(11) KM_BP(12) KM_BP(13) KM_BP(14) KM_BP(15) KM_BP(16)
 #undef KM_BP

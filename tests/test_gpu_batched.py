@@ -94,6 +94,51 @@ def test_batched_equals_single_instance_path_statistically():
         assert np.all(np.abs(a - b) <= ulp)
 
 
+def test_batched_bf16_stepwise_against_oracle():
+    """BF16 MFMA distances + exact recheck in the batched launches: each
+    instance checked against the oracle every iteration, like the FP32 batch."""
+    torch, B = _torch(), _bind()
+    inst, host = make_batch(torch, B, SHAPES, seed0=200)
+    batch = B.Batch(inst, precision="bf16")
+    Cs = [C.copy() for _, C in host]
+    for t in range(3):
+        B.kmeans_lloyd_batched(batch, 1)
+        torch.cuda.synchronize()
+        for i, ((X, _), ti) in enumerate(zip(host, inst)):
+            say(f"bf16 t={t} instance {i} shape {X.shape} k={Cs[i].shape[0]}")
+            lab = ti["labels"].cpu().numpy()
+            _, _, J, _, _ = check_labels(lab, Cs[i], X, f"bf16 instance {i} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(ti["counts"].cpu().numpy(), cnto)
+            Cg = ti["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"bf16 instance {i} t={t}")
+            assert abs(ti["obj_hist"][0].item() - J) <= 1e-9 * J + 1e-30
+            Cs[i] = Cg
+
+
+@pytest.mark.parametrize("tpb,order", [(1, 0), (4, 1), (16, 0)])
+def test_batched_bf16_equals_fp32_batch(tpb, order):
+    """At a common schedule the BF16 batch's labels, counts and centroids equal
+    the FP32 batch's bit for bit (same labels, same reduction order), iteration
+    after iteration, with and without graph launch."""
+    torch, B = _torch(), _bind()
+    inst32, host = make_batch(torch, B, SHAPES, seed0=300, iters=4)
+    inst16, _ = make_batch(torch, B, SHAPES, seed0=300, iters=4)
+    b32 = B.Batch(inst32)
+    b16 = B.Batch(inst16, precision="bf16")
+    b32.set_schedule(tpb, order)
+    b16.set_schedule(tpb, order)
+    b16.use_graphs(True)
+    for rep in range(2):
+        B.kmeans_lloyd_batched(b32, 4)
+        B.kmeans_lloyd_batched(b16, 4)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(inst32, inst16)):
+            assert torch.equal(a["labels"], b["labels"]), f"instance {i} rep {rep}"
+            assert torch.equal(a["C"], b["C"]) and torch.equal(a["counts"], b["counts"]), f"instance {i} rep {rep}"
+            np.testing.assert_allclose(b["obj_hist"].cpu().numpy(), a["obj_hist"].cpu().numpy(), rtol=1e-6)
+
+
 def test_batched_rejects_bad_instances():
     torch, B = _torch(), _bind()
     dev = torch.device("cuda")
@@ -110,7 +155,8 @@ def test_batched_rejects_bad_instances():
 
 
 @pytest.mark.slow
-def test_batched_workload_sampled():
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_workload_sampled(prec):
     """The 512-instance workload (n log-uniform in [1e3, 2e5], d in {16, 32,
     64}, k uniform in [4, 128], seeds 0..511), autotuned and graph-launched as
     the benchmark runs it: 24 iterations, then iteration 25 checked against the
@@ -126,7 +172,7 @@ def test_batched_workload_sampled():
                      "labels": torch.empty(shp.n, dtype=torch.int32, device=dev),
                      "counts": torch.empty(shp.k, dtype=torch.int64, device=dev),
                      "obj_hist": torch.zeros(datagen.BATCH_ITERS, dtype=torch.float64, device=dev)})
-    batch = B.Batch(inst)
+    batch = B.Batch(inst, precision=prec)
     choice, _ = autotune.tune_batch(batch, use_cache=False)
     say(f"autotuned schedule {choice}")
     batch.use_graphs(True)
