@@ -35,9 +35,9 @@ __device__ __forceinline__ void lds_add_f64(double* p, double v)
 
 // "process": add the tile's samples that this wave owns (label L with
 // L % 4 == wave) to the block's activation record, in increasing sample
-// order.  The owned samples are listed in LDS first; then B rows at a time
-// are loaded (lane f carries feature f: coalesced) with every load issued
-// before the first is used -- addresses are clamped to a valid row and
+// order.  The owned samples are listed (and counted) in LDS first; then B
+// rows at a time are loaded (lane f carries feature f: coalesced) with every
+// load issued before the first is used -- addresses are clamped to a valid row and
 // feature instead of branching, so no load waits on another -- and added
 // with LDS atomics without return, which the wave issues, and the LDS
 // executes, in program order: every sum has a fixed order and nothing waits
@@ -54,10 +54,13 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
         const int L = lb[g * 64 + lane];
         const bool own = L >= 0 && (L & (kWaves - 1)) == wave;
         const uint64_t mask = __ballot(own);
-        if (own)
+        if (own) {
             wl[nown + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
                 (L << 12) | (g * 64 + lane);
+            // counts are integers: any order of these adds gives the same total
+            __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         nown += (int)__popcll(mask);
     }
     int fc[FPL];
@@ -86,7 +89,6 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
                     const int f = lane + 64 * m;
                     if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
                 }
-                if (lane == 0) __hip_atomic_fetch_add(cnt + Lu, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
     }
