@@ -70,6 +70,7 @@ struct km_plan {
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
     size_t off_fsc = 0, off_pfm = 0, off_xq = 0, off_xst = 0;   // FP8 only
+    size_t off_pcn = 0;                                          // BF16: per-block max |c|^2
     // workspace
     unsigned char* ws;
     size_t ws_bytes;
@@ -184,7 +185,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
                                  p->DP, reinterpret_cast<const XStats*>(ws + p->off_xs),
                                  f8 ? reinterpret_cast<const float*>(ws + p->off_fsc) : nullptr, ws + p->off_ab,
                                  reinterpret_cast<float*>(ws + p->off_bias), reinterpret_cast<CStats*>(ws + p->off_cs),
-                                 ctrl, iter, s);
+                                 f8 ? nullptr : reinterpret_cast<float*>(ws + p->off_pcn), ctrl, iter, s);
     if (e != hipSuccess) return e;
     MixArgs m{};
     m.X = X; m.n = p->n; m.d = p->d; m.k = p->k; m.kpad = p->kpad;
@@ -339,6 +340,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_ab = off;   off = align256(off + (size_t)p->kpad * p->DP * (p->fmt == FMT_FP8 ? 1 : 2));
         p->off_bias = off; off = align256(off + (size_t)p->kpad * sizeof(float));
         p->off_cs = off;   off = align256(off + sizeof(CStats));
+        p->off_pcn = off;  off = align256(off + (size_t)prep_c_blocks(p->kpad) * sizeof(float));
         p->off_rqc = off;  off = align256(off + 2 * (size_t)p->grid_mfma * sizeof(int32_t));
         p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(p->fmt) * sizeof(int32_t));
         if (p->fmt == FMT_FP8) {

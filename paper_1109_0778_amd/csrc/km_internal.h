@@ -217,9 +217,12 @@ hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, 
 // of X and the per-sample band inputs.
 hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, float* part_fmax, float* fscale,
                              uint8_t* Xq, float2* xst, hipStream_t s);
+// Per-iteration centroid prep.  BF16 with part_cn2 (prep_c_blocks(kpad)
+// floats): row blocks + a reduce; otherwise one block.
+int prep_c_blocks(int kpad);
 hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
-                         const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, const Ctrl* ctrl,
-                         int32_t iter, hipStream_t s);
+                         const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, float* part_cn2,
+                         const Ctrl* ctrl, int32_t iter, hipStream_t s);
 hipError_t launch_mfma_assign(int fmt, int D16, const MixArgs& a, int grid, hipStream_t s);
 size_t mfma_lds_bytes(int fmt, int D16);
 int mfma_blocks_per_cu(int fmt, int D16);

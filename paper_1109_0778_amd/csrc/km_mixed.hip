@@ -237,6 +237,69 @@ __global__ __launch_bounds__(256) void prep_c_kernel(const float* __restrict__ C
     prep_c_body(Cp, k, d, D, kpad, DP, xs, Ab, bias, cs, ctrl, iter);
 }
 
+// The same, spread over kPrepRows-row blocks (large k x d): each block writes
+// its rows' operands and biases and the largest |c_j|^2 among them; a
+// one-wave kernel reduces those maxima into the band constants.
+constexpr int kPrepRows = 32;
+__global__ __launch_bounds__(256) void prep_c_rows_kernel(const float* __restrict__ Cp, int32_t k, int32_t d,
+                                                          int32_t D, int32_t kpad, int32_t DP,
+                                                          const XStats* __restrict__ xs, __bf16* Ab, float* bias,
+                                                          float* part_cn2, const Ctrl* ctrl, int32_t iter)
+{
+    __shared__ float smax[kPrepRows];
+    if (ctrl != nullptr && ctrl->stop_iter < iter) return;
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * kPrepRows;
+    if (tid < kPrepRows) {
+        const int j = r0 + tid;
+        float s = 0.0f;
+        if (j < k) {
+            for (int f = 0; f < d; ++f) {
+                const float v = Cp[(size_t)j * D + f];
+                s = __builtin_fmaf(v, v, s);
+            }
+        }
+        if (j < kpad) bias[j] = j < k ? xs->K + s : 3.0e38f;
+        smax[tid] = s;
+    }
+    for (int e = tid; e < kPrepRows * DP; e += 256) {
+        const int j = r0 + e / DP;
+        const int f = e - (e / DP) * DP;
+        if (j < kpad) {
+            const float v = (j < k && f < d) ? -2.0f * Cp[(size_t)j * D + f] : 0.0f;
+            Ab[(size_t)j * DP + f] = (__bf16)v;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float m = 0.0f;
+        for (int q = 0; q < kPrepRows; ++q) m = fmaxf(m, smax[q]);
+        part_cn2[blockIdx.x] = m;
+    }
+}
+
+__global__ __launch_bounds__(64) void prep_c_stats_kernel(const float* __restrict__ part_cn2, int nb,
+                                                          const XStats* __restrict__ xs, CStats* cs,
+                                                          const Ctrl* ctrl, int32_t iter)
+{
+    if (ctrl != nullptr && ctrl->stop_iter < iter) return;
+    const int lane = threadIdx.x;
+    float m = 0.0f;
+    for (int b = lane; b < nb; b += 64) m = fmaxf(m, part_cn2[b]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (lane == 0) {
+        const float mm = m * (1.0f + 1e-5f);
+        cs->K = xs->K;
+        cs->cn2max = mm;
+        cs->cmax = sqrtf(mm) * (1.0f + 1e-6f);
+        cs->inv2r = 1.0f;
+        cs->inv_r = 2.0f;
+        cs->cl1 = 0.0f;
+        cs->pad[0] = cs->pad[1] = 0.0f;
+    }
+}
+
 // Batched (BF16): one block per instance.
 __global__ __launch_bounds__(256) void batch_prep_c_kernel(const BatchMix* __restrict__ bm)
 {
@@ -873,10 +936,21 @@ hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, f
     return hipGetLastError();
 }
 
+int prep_c_blocks(int kpad) { return (kpad + kPrepRows - 1) / kPrepRows; }
+
 hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
-                         const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, const Ctrl* ctrl,
-                         int32_t iter, hipStream_t s)
+                         const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, float* part_cn2,
+                         const Ctrl* ctrl, int32_t iter, hipStream_t s)
 {
+    if (fmt == FMT_BF16 && part_cn2 != nullptr) {
+        const int nb = prep_c_blocks(kpad);
+        hipLaunchKernelGGL(prep_c_rows_kernel, dim3(nb), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs,
+                           static_cast<__bf16*>(Ab), bias, part_cn2, ctrl, iter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(prep_c_stats_kernel, dim3(1), dim3(64), 0, s, part_cn2, nb, xs, cs, ctrl, iter);
+        return hipGetLastError();
+    }
     if (fmt == FMT_FP8)
         hipLaunchKernelGGL(prep_c_fp8_kernel, dim3(1), dim3(256), 0, s, Cp, k, d, D, kpad, DP, xs, fscale,
                            static_cast<uint8_t*>(Ab), bias, cs, ctrl, iter);

@@ -36,7 +36,8 @@ def mixed_assign(torch, B, X, C, plan=None, prec="bf16"):
 
 SHAPES = [(3000, 8, 8), (5000, 3, 5), (4099, 17, 13), (2500, 64, 64), (1200, 128, 9),
           (257, 33, 40), (700, 1, 4), (20000, 24, 100), (999, 96, 3), (64, 5, 64),
-          (20000, 128, 200), (9001, 100, 150), (5000, 24, 600), (40000, 64, 64)]
+          (20000, 128, 200), (9001, 100, 150), (5000, 24, 600), (40000, 64, 64),
+          (20000, 8, 16384), (3000, 40, 1500)]   # the largest k the mixed path takes; k above the row-block size
 
 
 @pytest.mark.parametrize("prec", PRECS)
