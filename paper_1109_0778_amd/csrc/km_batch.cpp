@@ -71,10 +71,16 @@ struct km_batch {
     size_t off_pa = 0, off_fa = 0, off_work = 0, off_fwork = 0, total = 0;
     // mixed path
     std::vector<int> nreg;                 // MFMA queue regions per instance
-    std::vector<size_t> off_xs, off_ab, off_bias, off_cs, off_rq, off_rqc, off_chg, off_jt;
-    std::vector<BatchWork> mwork, rwork;   // MFMA rows, recheck rows
+    std::vector<size_t> off_xs, off_ab, off_bias, off_cs, off_rq, off_rqc, off_chg, off_jt, off_xpm, off_xps;
+    std::vector<int> nxb;
+    std::vector<BatchWork> mwork, rwork, xwork;   // MFMA rows, recheck rows, statistics rows
     std::vector<Group> mgroups, rgroups;
-    size_t off_bm = 0, off_mwork = 0, off_rwork = 0;
+    size_t off_bm = 0, off_mwork = 0, off_rwork = 0, off_xwork = 0;
+    // side streams: the launches of one phase (one per shape class) are
+    // forked onto them and joined back, so classes overlap (graph branches)
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
     unsigned char* ws = nullptr;
     // graph
     bool use_graph = false;
@@ -90,6 +96,11 @@ struct km_batch {
     {
         drop_graph();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (int i = 0; i < kSide; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
     }
 };
 
@@ -187,6 +198,8 @@ void layout(km_batch* B)
         B->nreg.assign(m, 0);
         B->off_xs.assign(m, 0); B->off_ab.assign(m, 0); B->off_bias.assign(m, 0); B->off_cs.assign(m, 0);
         B->off_rq.assign(m, 0); B->off_rqc.assign(m, 0); B->off_chg.assign(m, 0); B->off_jt.assign(m, 0);
+        B->off_xpm.assign(m, 0); B->off_xps.assign(m, 0); B->nxb.assign(m, 0);
+        B->xwork.clear();
         for (int i = 0; i < m; ++i) {
             const km_instance& x = B->inst[i];
             const int D16 = d16_of(x.d), kpad = kpad_of(x.k);
@@ -219,6 +232,12 @@ void layout(km_batch* B)
             B->off_rqc[i] = off;  off = al256(off + 2 * (size_t)nr * sizeof(int32_t));
             B->off_chg[i] = off;  off = al256(off + (size_t)(1 + kBatchRecheckSplit) * nr * sizeof(int32_t));
             B->off_jt[i] = off;   off = al256(off + (size_t)finalize_blocks(x.k, x.d) * sizeof(double));
+            const int nx = (int)((x.n + kPrepXRows - 1) / kPrepXRows);
+            B->nxb[i] = nx;
+            for (int b = 0; b < nx; ++b)
+                B->xwork.push_back(BatchWork{i, b, (int64_t)b * kPrepXRows, std::min<int64_t>(x.n, (int64_t)(b + 1) * kPrepXRows)});
+            B->off_xpm[i] = off;  off = al256(off + (size_t)nx * sizeof(float));
+            B->off_xps[i] = off;  off = al256(off + (size_t)nx * sizeof(double));
         }
         emit_groups(by_m, c_m, B->order, B->mwork, B->mgroups);
         emit_groups(by_r, c_r, B->order, B->rwork, B->rgroups);
@@ -226,6 +245,7 @@ void layout(km_batch* B)
         B->off_bm = off;    off = al256(off + (size_t)m * sizeof(BatchMix));
         B->off_mwork = off; off = al256(off + B->mwork.size() * sizeof(BatchWork));
         B->off_rwork = off; off = al256(off + B->rwork.size() * sizeof(BatchWork));
+        B->off_xwork = off; off = al256(off + B->xwork.size() * sizeof(BatchWork));
     }
     B->off_pa = off;    off = al256(off + (size_t)m * sizeof(PassArgs));
     B->off_fa = off;    off = al256(off + (size_t)m * sizeof(FinArgs));
@@ -300,6 +320,9 @@ km_status upload(km_batch* B)
         b.D = 8 * d8_of(x.d);
         b.DP = 16 * D16;
         b.xs = reinterpret_cast<XStats*>(ws + B->off_xs[i]);
+        b.xpart_max = reinterpret_cast<float*>(ws + B->off_xpm[i]);
+        b.xpart_sum = reinterpret_cast<double*>(ws + B->off_xps[i]);
+        b.nxb = B->nxb[i];
     }
     hipError_t e;
     if ((e = hipMemcpy(ws + B->off_pa, pa.data(), pa.size() * sizeof(PassArgs), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -314,6 +337,8 @@ km_status upload(km_batch* B)
          (e = hipMemcpy(ws + B->off_mwork, B->mwork.data(), B->mwork.size() * sizeof(BatchWork),
                         hipMemcpyHostToDevice)) != hipSuccess ||
          (e = hipMemcpy(ws + B->off_rwork, B->rwork.data(), B->rwork.size() * sizeof(BatchWork),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = hipMemcpy(ws + B->off_xwork, B->xwork.data(), B->xwork.size() * sizeof(BatchWork),
                         hipMemcpyHostToDevice)) != hipSuccess))
         return bhip(e, "hipMemcpy(batch mixed tables)");
     return KM_OK;
@@ -332,22 +357,53 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
     const BatchMix* bm = reinterpret_cast<const BatchMix*>(ws + B->off_bm);
     const BatchWork* mwork = reinterpret_cast<const BatchWork*>(ws + B->off_mwork);
     const BatchWork* rwork = reinterpret_cast<const BatchWork*>(ws + B->off_rwork);
-    if (B->mixed && (e = launch_batch_prep_x(bm, m, s)) != hipSuccess) return bhip(e, "batch prep_x launch");
+    const BatchWork* xwork = reinterpret_cast<const BatchWork*>(ws + B->off_xwork);
+    // one launch per shape class of a phase, spread over the side streams
+    auto fork = [&](int nclass) -> hipError_t {
+        hipError_t ee = hipEventRecord(B->ev_fork, s);
+        for (int i = 0; ee == hipSuccess && i < std::min(nclass, km_batch::kSide); ++i)
+            ee = hipStreamWaitEvent(B->side[i], B->ev_fork, 0);
+        return ee;
+    };
+    auto join = [&](int nclass) -> hipError_t {
+        hipError_t ee = hipSuccess;
+        for (int i = 0; ee == hipSuccess && i < std::min(nclass, km_batch::kSide); ++i) {
+            ee = hipEventRecord(B->ev_join[i], B->side[i]);
+            if (ee == hipSuccess) ee = hipStreamWaitEvent(s, B->ev_join[i], 0);
+        }
+        return ee;
+    };
+    auto lane_of = [&](int g) { return B->side[g % km_batch::kSide]; };
+    if (B->mixed && (e = launch_batch_prep_x(xwork, (int)B->xwork.size(), bm, m, s)) != hipSuccess)
+        return bhip(e, "batch prep_x launch");
     for (int32_t t = 0; t < iters; ++t) {
         if (B->mixed) {
             if ((e = launch_batch_prep_c(bm, m, s)) != hipSuccess) return bhip(e, "batch prep_c launch");
-            for (const Group& g : B->mgroups)
-                if ((e = launch_batch_mfma(g.D8, mwork + g.first, g.count, bm, t, s)) != hipSuccess)
+            const int nm = (int)B->mgroups.size(), nr = (int)B->rgroups.size();
+            if ((e = fork(nm)) != hipSuccess) return bhip(e, "batch fork");
+            for (int g = 0; g < nm; ++g) {
+                const Group& G = B->mgroups[g];
+                if ((e = launch_batch_mfma(G.D8, mwork + G.first, G.count, bm, t, lane_of(g))) != hipSuccess)
                     return bhip(e, "batch MFMA launch");
-            for (const Group& g : B->rgroups)
-                if ((e = launch_batch_recheck(g.D8, rwork + g.first, g.count, bm, t, s)) != hipSuccess)
+            }
+            if ((e = join(nm)) != hipSuccess) return bhip(e, "batch join");
+            if ((e = fork(nr)) != hipSuccess) return bhip(e, "batch fork");
+            for (int g = 0; g < nr; ++g) {
+                const Group& G = B->rgroups[g];
+                if ((e = launch_batch_recheck(G.D8, rwork + G.first, G.count, bm, t, lane_of(g))) != hipSuccess)
                     return bhip(e, "batch recheck launch");
+            }
+            if ((e = join(nr)) != hipSuccess) return bhip(e, "batch join");
         }
-        for (const Group& g : B->groups) {
-            if ((e = launch_batch_pass(g.D8, B->mixed ? MODE_UPDATE : MODE_FUSED, work + g.first, g.count, pa, t,
-                                       g.lds, s)) != hipSuccess)
+        const int np = (int)B->groups.size();
+        if ((e = fork(np)) != hipSuccess) return bhip(e, "batch fork");
+        for (int g = 0; g < np; ++g) {
+            const Group& G = B->groups[g];
+            if ((e = launch_batch_pass(G.D8, B->mixed ? MODE_UPDATE : MODE_FUSED, work + G.first, G.count, pa, t,
+                                       G.lds, lane_of(g))) != hipSuccess)
                 return bhip(e, "batch pass launch");
         }
+        if ((e = join(np)) != hipSuccess) return bhip(e, "batch join");
         if ((e = launch_batch_finalize(fwork, (int)B->fwork.size(), fa, t, s)) != hipSuccess)
             return bhip(e, "batch finalize launch");
         if (B->mixed && (e = launch_batch_objective(fa, m, t, s)) != hipSuccess)
@@ -390,6 +446,17 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
     B->inst.assign(inst, inst + count);
     B->device = dev;
     B->mixed = prec == KM_BF16;
+    for (int i = 0; i < km_batch::kSide; ++i) {
+        if ((e = hipStreamCreateWithFlags(&B->side[i], hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&B->ev_join[i], hipEventDisableTiming)) != hipSuccess) {
+            delete B;
+            return bhip(e, "side stream / event creation");
+        }
+    }
+    if ((e = hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming)) != hipSuccess) {
+        delete B;
+        return bhip(e, "event creation");
+    }
     layout(B);
     *out = B;
     return KM_OK;

@@ -239,8 +239,12 @@ struct BatchMix {
     const float* Cp;            // [k][D] padded FP32 centroids
     int32_t D, DP;
     XStats* xs;
+    float* xpart_max;           // [nxb] partials of the run-level statistics
+    double* xpart_sum;          // [nxb]
+    int32_t nxb;
 };
-hipError_t launch_batch_prep_x(const BatchMix* bm, int ninst, hipStream_t s);
+constexpr int kPrepXRows = 4096;    // rows per block of the batched run-level statistics
+hipError_t launch_batch_prep_x(const BatchWork* xwork, int nxwork, const BatchMix* bm, int ninst, hipStream_t s);
 hipError_t launch_batch_prep_c(const BatchMix* bm, int ninst, hipStream_t s);
 hipError_t launch_batch_mfma(int D16, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s);
 hipError_t launch_batch_recheck(int D8, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s);

@@ -44,6 +44,49 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 // ------------------------------------------------------------ run-level prep
+// |x|^2 of one row in FP32 (fused multiply-add in feature order) and in FP64:
+// 16 features per step, all loads of a step issued before their first use
+// (float4 when the row is 16-byte aligned, clamped scalars otherwise).
+__device__ __forceinline__ void row_norm2(const float* __restrict__ row, int d, float& s32, double& s64)
+{
+    s32 = 0.0f;
+    s64 = 0.0;
+    if ((d & 3) == 0) {
+        for (int f0 = 0; f0 < d; f0 += 16) {
+            float4 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = f0 + 4 * q;
+                v[q] = *reinterpret_cast<const float4*>(row + (f < d ? f : d - 4));
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (f0 + 4 * q < d) {
+                    const float e[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        s32 = __builtin_fmaf(e[i], e[i], s32);
+                        s64 += (double)e[i] * (double)e[i];
+                    }
+                }
+            }
+        }
+    } else {
+        for (int f0 = 0; f0 < d; f0 += 16) {
+            float v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = row[f0 + i < d ? f0 + i : d - 1];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (f0 + i < d) {
+                    s32 = __builtin_fmaf(v[i], v[i], s32);
+                    s64 += (double)v[i] * (double)v[i];
+                }
+            }
+        }
+    }
+}
+
 // Per block: max |x|^2 (FP32) and sum |x|^2 (FP64, rows in a fixed order); a
 // second one-wave kernel combines the block partials in a fixed order.
 __global__ __launch_bounds__(256) void prep_x_kernel(const float* __restrict__ X, int64_t n, int32_t d,
@@ -55,14 +98,9 @@ __global__ __launch_bounds__(256) void prep_x_kernel(const float* __restrict__ X
     float mx = 0.0f;
     double sm = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
-        const float* row = X + i * d;
-        float s32 = 0.0f;
-        double s64 = 0.0;
-        for (int f = 0; f < d; ++f) {
-            const float v = row[f];
-            s32 = __builtin_fmaf(v, v, s32);
-            s64 += (double)v * (double)v;
-        }
+        float s32;
+        double s64;
+        row_norm2(X + i * d, d, s32, s64);
         mx = fmaxf(mx, s32);
         sm += s64;
     }
@@ -309,28 +347,25 @@ __global__ __launch_bounds__(256) void batch_prep_c_kernel(const BatchMix* __res
                 const_cast<CStats*>(b.m.cs), nullptr, 0);
 }
 
-// Batched run-level statistics: one block per instance, rows in a fixed
-// order per thread, then a fixed tree.
-__global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchMix* __restrict__ bm)
+// Batched run-level statistics: row b of the work table covers rows
+// [t0, t1) of one instance (fixed order per thread, then a fixed tree) and
+// writes partial slot `slot`; a one-wave combine per instance follows.
+__global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchWork* __restrict__ work,
+                                                           const BatchMix* __restrict__ bm)
 {
     __shared__ float smax[256];
     __shared__ double ssum[256];
-    const BatchMix& b = bm[blockIdx.x];
+    const BatchWork w = work[blockIdx.x];
+    const BatchMix& b = bm[w.inst];
     const float* X = b.m.X;
-    const int64_t n = b.m.n;
     const int d = b.m.d;
     const int tid = threadIdx.x;
     float mx = 0.0f;
     double sm = 0.0;
-    for (int64_t i = tid; i < n; i += 256) {
-        const float* row = X + i * d;
-        float s32 = 0.0f;
-        double s64 = 0.0;
-        for (int f = 0; f < d; ++f) {
-            const float v = row[f];
-            s32 = __builtin_fmaf(v, v, s32);
-            s64 += (double)v * (double)v;
-        }
+    for (int64_t i = w.t0 + tid; i < w.t1; i += 256) {
+        float s32;
+        double s64;
+        row_norm2(X + i * d, d, s32, s64);
         mx = fmaxf(mx, s32);
         sm += s64;
     }
@@ -345,9 +380,27 @@ __global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchMix* __res
         __syncthreads();
     }
     if (tid == 0) {
-        b.xs->max_xn2 = smax[0];
-        b.xs->K = 2.0f * smax[0] * (1.0f + 1e-5f) + 1.0f;
-        b.xs->sum_xn2 = ssum[0];
+        b.xpart_max[w.slot] = smax[0];
+        b.xpart_sum[w.slot] = ssum[0];
+    }
+}
+
+__global__ __launch_bounds__(64) void batch_prep_x_combine_kernel(const BatchMix* __restrict__ bm)
+{
+    const BatchMix& b = bm[blockIdx.x];
+    const int lane = threadIdx.x;
+    float mx = 0.0f;
+    double sm = 0.0;
+    for (int q = lane; q < b.nxb; q += 64) { mx = fmaxf(mx, b.xpart_max[q]); sm += b.xpart_sum[q]; }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+        sm += __shfl_xor(sm, off);
+    }
+    if (lane == 0) {
+        b.xs->max_xn2 = mx;
+        b.xs->K = 2.0f * mx * (1.0f + 1e-5f) + 1.0f;
+        b.xs->sum_xn2 = sm;
     }
 }
 
@@ -626,6 +679,9 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                         for (int i = 0; i < 16; ++i) acc[nb][i] = bvv[i];
                 }
                 const unsigned char* arow = Ab_c + (tt * 32 + col) * ROWB + 8 * ES * h;
+                // raised wave priority while the MFMA chain issues keeps the
+                // matrix pipe fed while other waves run their epilogues
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int s = 0; s < D16; ++s) {
                     if constexpr (F8) {
@@ -640,6 +696,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfr[nb][s], acc[nb], 0, 0, 0);
                     }
                 }
+                __builtin_amdgcn_s_setprio(0);
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
 #pragma unroll
@@ -1036,9 +1093,12 @@ int mfma_blocks_per_cu(int fmt, int D16)
     return fmt == FMT_FP8 ? occ_mfma_fmt<FMT_FP8>(D16) : occ_mfma_fmt<FMT_BF16>(D16);
 }
 
-hipError_t launch_batch_prep_x(const BatchMix* bm, int ninst, hipStream_t s)
+hipError_t launch_batch_prep_x(const BatchWork* xwork, int nxwork, const BatchMix* bm, int ninst, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_prep_x_kernel, dim3(ninst), dim3(256), 0, s, bm);
+    hipLaunchKernelGGL(batch_prep_x_kernel, dim3(nxwork), dim3(256), 0, s, xwork, bm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_prep_x_combine_kernel, dim3(ninst), dim3(64), 0, s, bm);
     return hipGetLastError();
 }
 
