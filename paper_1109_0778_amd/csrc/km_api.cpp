@@ -345,7 +345,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(p->fmt) * sizeof(int32_t));
         if (p->fmt == FMT_FP8) {
             p->off_fsc = off; off = align256(off + 2 * (size_t)p->DP * sizeof(float));
-            p->off_pfm = off; off = align256(off + (size_t)kXStatBlocks * p->DP * sizeof(float));
+            p->off_pfm = off; off = align256(off + (size_t)kFmaxBlocks * p->DP * sizeof(float));
             p->off_xq = off;  off = align256(off + (size_t)n * p->DP);
             p->off_xst = off; off = align256(off + (size_t)n * sizeof(float2));
         }

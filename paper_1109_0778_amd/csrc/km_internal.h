@@ -154,6 +154,7 @@ constexpr int kRqHead = 4;
 __host__ __device__ constexpr int rq_ints(int fmt) { return kRqHead + (2 * cand_cap(fmt) + 7) / 8 * 8; }
 constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
 constexpr int kXStatBlocks = 256;
+constexpr int kFmaxBlocks = 1024;               // FP8 per-feature maxima
 constexpr int kRecheckSplit = 8;                // recheck blocks per MFMA block's queue region
 constexpr float kFp8Max = 448.0f;               // largest finite e4m3 (OCP "fn") value
 

@@ -156,7 +156,16 @@ __global__ __launch_bounds__(256) void prep_fmax_kernel(const float* __restrict_
     if (t < S) {
         float m = 0.0f;
         const int64_t total = n * d;
-        for (int64_t e = t; e < total; e += S) m = fmaxf(m, fabsf(X[e]));
+        for (int64_t e0 = t; e0 < total; e0 += 8 * S) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {                   // 8 loads in flight, clamped addresses
+                const int64_t e = e0 + q * S;
+                v[q] = X[e < total ? e : t];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) m = fmaxf(m, fabsf(v[q]));   // the clamped repeat of X[t] is harmless
+        }
         atomicMax(&smax[t % d], __float_as_uint(m));     // non-negative floats order like their bits
     }
     __syncthreads();
@@ -199,20 +208,23 @@ __global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ 
     if (i >= n) return;
     const float* row = X + i * d;
     const float* inv = fscale + DP;
-    uint32_t* out = reinterpret_cast<uint32_t*>(Xq + i * DP);
+    uint4* out = reinterpret_cast<uint4*>(Xq + i * DP);    // DP is a multiple of 16: one uint4 per 16 features
     float s2 = 0.0f, l1 = 0.0f;
-    for (int f0 = 0; f0 < DP; f0 += 4) {
-        uint32_t w = 0;
+    for (int f0 = 0; f0 < DP; f0 += 16) {
+        float v[16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 16; ++q) v[q] = row[f0 + q < d ? f0 + q : d - 1];   // all 16 loads in flight
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
             const int f = f0 + q;
-            const float v = f < d ? row[f] : 0.0f;
-            const float xt = v * inv[f];
-            s2 = __builtin_fmaf(v, v, s2);
+            const float x = f < d ? v[q] : 0.0f;
+            const float xt = x * inv[f];
+            s2 = __builtin_fmaf(x, x, s2);
             l1 += fabsf(xt);
-            w |= fp8_of(xt) << (8 * q);
+            w[q >> 2] |= fp8_of(xt) << (8 * (q & 3));
         }
-        out[f0 / 4] = w;
+        out[f0 / 16] = make_uint4(w[0], w[1], w[2], w[3]);
     }
     xst[i] = make_float2(sqrtf(s2) * (1.0f + 1e-6f), l1 * (1.0f + 1e-5f));
 }
@@ -984,10 +996,10 @@ hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, 
 hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, float* part_fmax, float* fscale,
                              uint8_t* Xq, float2* xst, hipStream_t s)
 {
-    hipLaunchKernelGGL(prep_fmax_kernel, dim3(kXStatBlocks), dim3(256), 0, s, X, n, d, DP, part_fmax);
+    hipLaunchKernelGGL(prep_fmax_kernel, dim3(kFmaxBlocks), dim3(256), 0, s, X, n, d, DP, part_fmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prep_fscale_kernel, dim3(1), dim3(256), 0, s, part_fmax, kXStatBlocks, d, DP, fscale);
+    hipLaunchKernelGGL(prep_fscale_kernel, dim3(1), dim3(256), 0, s, part_fmax, kFmaxBlocks, d, DP, fscale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(quant_x_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, DP, fscale, Xq, xst);
     return hipGetLastError();
