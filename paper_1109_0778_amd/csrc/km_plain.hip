@@ -57,7 +57,7 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
         if (own) {
             wl[nown + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
-                (L << 12) | (g * 64 + lane);
+                ((L * d) << 12) | (g * 64 + lane);   // record offset of the row (< 2^19), offset in the tile
             // counts are integers: any order of these adds gives the same total
             __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -78,16 +78,27 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
 #pragma unroll
             for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
         }
+        if (i0 + B <= nown) {                    // a full batch: no per-entry test
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const int ent = __builtin_amdgcn_readlane(mine, u);
-            if (ent >= 0) {
-                const int Lu = ent >> 12;
-                double* srow = S + (size_t)Lu * d;
+            for (int u = 0; u < B; ++u) {
+                double* srow = S + (__builtin_amdgcn_readlane(mine, u) >> 12);
 #pragma unroll
                 for (int m = 0; m < FPL; ++m) {
                     const int f = lane + 64 * m;
                     if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int ent = __builtin_amdgcn_readlane(mine, u);
+                if (ent >= 0) {
+                    double* srow = S + (ent >> 12);
+#pragma unroll
+                    for (int m = 0; m < FPL; ++m) {
+                        const int f = lane + 64 * m;
+                        if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
+                    }
                 }
             }
         }
