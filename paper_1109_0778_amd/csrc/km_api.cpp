@@ -55,7 +55,8 @@ struct km_plan {
     int num_cu;
     int D8, D;           // padded feature count (8-feature chunks)
     int grid;            // blocks of the assign / fused pass (one resident wave)
-    bool split;          // per-label record too large for one block: assign, then chunked update
+    bool split;          // assign and reduce as two passes (the fused pass would lose occupancy)
+    bool chunked;        // per-label record too large for one block: the reduce runs over label chunks
     int kc, nch;         // update: labels per chunk, chunks
     int grid_upd;        // update: slots (point ranges) per chunk
     size_t lds_fused;    // dynamic LDS of the fused pass (whole record)
@@ -171,6 +172,7 @@ hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
 {
     // without a split, the update walks exactly the fused pass's tiles and blocks
     if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_upd, s);
+    if (!p->chunked) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd), p->lds_upd, s);
     return launch_plain_pass(p->D8, MODE_UPDATE_WIDE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
 }
 
@@ -283,26 +285,35 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->D = 8 * p->D8;
     const int64_t ntiles = (n + plain_tile(p->D8) - 1) / plain_tile(p->D8);
 
-    // The per-label record (k x d FP64 + counts) lives in LDS.  Up to 80 KiB
-    // (two blocks per CU) it is whole and the assign and reduce run fused;
-    // beyond that the reduce runs as a separate pass over label chunks of at
-    // most 48 KiB, a 2-D grid of (point range, label chunk) blocks.
+    // The per-label record (k x d FP64 + counts) lives in LDS.  The assign and
+    // the reduce run fused as long as that costs the pass no resident blocks
+    // (a record of a few tens of KiB); beyond that they run as two passes, the
+    // reduce over the whole record up to 80 KiB and over label chunks of at
+    // most 48 KiB above it (a 2-D grid of (point range, label chunk) blocks).
     p->lds_fused = plain_lds_bytes(k, d, MODE_FUSED);
-    p->split = p->lds_fused > 80 * 1024;
-    p->kc = p->split ? std::max(1, (48 * 1024) / (8 * d)) : k;
+    p->chunked = p->lds_fused > 80 * 1024;
+    p->kc = p->chunked ? std::max(1, (48 * 1024) / (8 * d)) : k;
     p->nch = (k + p->kc - 1) / p->kc;
-    p->lds_upd = p->split ? plain_lds_bytes(p->kc, d, MODE_UPDATE_WIDE) : p->lds_fused;
+    p->lds_upd = p->chunked ? plain_lds_bytes(p->kc, d, MODE_UPDATE_WIDE) : p->lds_fused;
 
     // One resident wave of blocks for the persistent passes, at most 4 per CU.
-    int per_cu = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
-    if (!p->split) per_cu = std::min(per_cu, plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused));
-    int per_cu_upd = plain_blocks_per_cu(p->D8, p->split ? MODE_UPDATE_WIDE : MODE_UPDATE, p->lds_upd);
-    if (per_cu < 1 || per_cu_upd < 1) { delete p; return fail(KM_EHIP, "occupancy query for the per-sample pass failed"); }
-    per_cu = std::min(per_cu, 4);
+    const int per_cu_assign = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
+    const int per_cu_fused = p->chunked ? 0 : plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused);
+    int per_cu_upd = plain_blocks_per_cu(p->D8, p->chunked ? MODE_UPDATE_WIDE : MODE_UPDATE, p->lds_upd);
+    if (per_cu_assign < 1 || per_cu_upd < 1 || (!p->chunked && per_cu_fused < 1)) {
+        delete p;
+        return fail(KM_EHIP, "occupancy query for the per-sample pass failed");
+    }
+    int per_cu = std::min(per_cu_assign, 4);
+    p->split = p->chunked || per_cu_fused < per_cu;
+    if (!p->split) per_cu = std::min(per_cu, per_cu_fused);
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
-    if (p->split) {
-        const int64_t resident = (int64_t)ncu * std::min(per_cu_upd, 4);
+    per_cu_upd = std::min(per_cu_upd, 4);
+    if (p->chunked) {
+        const int64_t resident = (int64_t)ncu * per_cu_upd;
         p->grid_upd = (int)std::max<int64_t>(1, std::min<int64_t>(resident / p->nch, ntiles));
+    } else if (p->split) {
+        p->grid_upd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu_upd, ntiles));
     } else {
         p->grid_upd = p->grid;
     }
