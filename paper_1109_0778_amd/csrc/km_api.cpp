@@ -57,6 +57,8 @@ struct km_plan {
     int grid;            // blocks of the assign / fused pass (one resident wave)
     bool split;          // assign and reduce as two passes (the fused pass would lose occupancy)
     bool chunked;        // per-label record too large for one block: the reduce runs over label chunks
+    int nsub = 0;        // chunked: partition sub-ranges (kPartRows samples each)
+    size_t off_perm = 0, off_poff = 0, off_plen = 0;
     int kc, nch;         // update: labels per chunk, chunks
     int grid_upd;        // update: slots (point ranges) per chunk
     size_t lds_fused;    // dynamic LDS of the fused pass (whole record)
@@ -109,6 +111,9 @@ namespace {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// labels per chunk of a chunked reduce: 48 KiB of FP64 sums
+int chunk_labels(int k, int d) { return std::max(1, std::min(k, (48 * 1024) / (8 * d))); }
+
 km_status check_plan(const km_plan* p)
 {
     if (!p) return fail(KM_EINVAL, "plan is NULL");
@@ -148,6 +153,13 @@ PassArgs pass_args(const km_plan* p, const float* X, const float* Cp, int32_t* l
     a.X = X; a.Cp = Cp; a.labels = labels; a.mindist = nullptr;
     a.part = partials_of(p); a.ctrl = nullptr;
     a.n = p->n; a.d = p->d; a.k = p->k; a.iter = 0; a.count_changed = 0; a.kc = p->kc;
+    if (p->chunked) {
+        a.perm = reinterpret_cast<const int32_t*>(p->ws + p->off_perm);
+        a.poff = reinterpret_cast<const int32_t*>(p->ws + p->off_poff);
+        a.pcnt = reinterpret_cast<const int32_t*>(p->ws + p->off_plen);
+        a.nsub = p->nsub;
+        a.nch = p->nch;
+    }
     return a;
 }
 
@@ -173,7 +185,12 @@ hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
     // without a split, the update walks exactly the fused pass's tiles and blocks
     if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_upd, s);
     if (!p->chunked) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd), p->lds_upd, s);
-    return launch_plain_pass(p->D8, MODE_UPDATE_WIDE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
+    // label chunks: partition the samples by chunk, then reduce each chunk's samples
+    hipError_t e = launch_partition(a, reinterpret_cast<int32_t*>(p->ws + p->off_perm),
+                                    reinterpret_cast<int32_t*>(p->ws + p->off_poff),
+                                    reinterpret_cast<int32_t*>(p->ws + p->off_plen), s);
+    if (e != hipSuccess) return e;
+    return launch_part_update(p->D8, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
 }
 
 // Mixed path: the MFMA pass (timed) and the exact recheck of its queue.
@@ -270,6 +287,9 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     if (d > 8 * kMaxD8Plain) return fail(KM_ENOTSUP, "this build supports d <= %d (got %d)", 8 * kMaxD8Plain, d);
     if (prec != KM_FP32 && ((int64_t)k + kMixCK - 1) / kMixCK * kMixCK > 16384)
         return fail(KM_ENOTSUP, "BF16 and FP8 distances support k <= 16384 (got %d)", k);
+    if (plain_lds_bytes(k, d, MODE_FUSED) > 80 * 1024 &&
+        ((int64_t)k + chunk_labels(k, d) - 1) / chunk_labels(k, d) > kPartMaxChunks)
+        return fail(KM_ENOTSUP, "k = %d needs more than %d label chunks at d = %d", k, kPartMaxChunks, d);
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -288,18 +308,21 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     // The per-label record (k x d FP64 + counts) lives in LDS.  The assign and
     // the reduce run fused as long as that costs the pass no resident blocks
     // (a record of a few tens of KiB); beyond that they run as two passes, the
-    // reduce over the whole record up to 80 KiB and over label chunks of at
-    // most 48 KiB above it (a 2-D grid of (point range, label chunk) blocks).
+    // reduce over the whole record up to 80 KiB and, above it, over label
+    // chunks of at most 48 KiB: the samples are partitioned by chunk, then a
+    // 2-D grid of (point range, label chunk) blocks reduces each chunk.
     p->lds_fused = plain_lds_bytes(k, d, MODE_FUSED);
     p->chunked = p->lds_fused > 80 * 1024;
-    p->kc = p->chunked ? std::max(1, (48 * 1024) / (8 * d)) : k;
+    p->kc = p->chunked ? chunk_labels(k, d) : k;
     p->nch = (k + p->kc - 1) / p->kc;
-    p->lds_upd = p->chunked ? plain_lds_bytes(p->kc, d, MODE_UPDATE_WIDE) : p->lds_fused;
+    p->nsub = p->chunked ? (int)((n + kPartRows - 1) / kPartRows) : 0;
+    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, d) : p->lds_fused;
 
     // One resident wave of blocks for the persistent passes, at most 4 per CU.
     const int per_cu_assign = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
     const int per_cu_fused = p->chunked ? 0 : plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused);
-    int per_cu_upd = plain_blocks_per_cu(p->D8, p->chunked ? MODE_UPDATE_WIDE : MODE_UPDATE, p->lds_upd);
+    int per_cu_upd = p->chunked ? part_update_blocks_per_cu(p->D8, p->lds_upd)
+                                : plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
     if (per_cu_assign < 1 || per_cu_upd < 1 || (!p->chunked && per_cu_fused < 1)) {
         delete p;
         return fail(KM_EHIP, "occupancy query for the per-sample pass failed");
@@ -341,6 +364,11 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
     p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, p->grid_mfma + p->grid_rc) * sizeof(int32_t));
     p->off_pbad = off; off = align256(off + (size_t)std::max(p->grid, p->GS()) * sizeof(int32_t));
+    if (p->chunked) {
+        p->off_perm = off; off = align256(off + (size_t)n * sizeof(int32_t));
+        p->off_poff = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
+        p->off_plen = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
+    }
     p->off_stS = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(double));
     p->off_stC = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(int32_t));
     p->off_jt = off;   off = align256(off + (size_t)finalize_blocks(k, d) * sizeof(double));

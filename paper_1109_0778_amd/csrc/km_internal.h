@@ -19,7 +19,7 @@ constexpr int kFinSplit = 16;
 // Per-sample pass variants: assign only; update from stored labels with the
 // fused pass's tiles (so the two give bit-identical sums); fused assign +
 // update; update over label chunks with wider tiles (records beyond LDS).
-enum Mode : int { MODE_ASSIGN = 0, MODE_UPDATE = 1, MODE_FUSED = 2, MODE_UPDATE_WIDE = 3 };
+enum Mode : int { MODE_ASSIGN = 0, MODE_UPDATE = 1, MODE_FUSED = 2 };
 
 // Device control block of one plan (lives at the head of the workspace).
 struct Ctrl {
@@ -55,7 +55,16 @@ struct PassArgs {
     int32_t iter;         // Lloyd iteration index (0 outside kmeans_lloyd)
     int32_t count_changed;// assign passes: count labels that differ from the stored ones
     int32_t kc;           // update passes: labels per chunk; block y owns labels [y*kc, y*kc+kc)
+    // partitioned chunk update: sample indices grouped by label chunk within
+    // each kPartRows-sample sub-range, in sample order
+    const int32_t* perm;  // [n]
+    const int32_t* poff;  // [nsub][nch] start of (sub-range, chunk) in perm
+    const int32_t* pcnt;  // [nsub][nch] its length
+    int32_t nsub, nch;
 };
+
+constexpr int kPartRows = 4096;   // samples per partition sub-range
+constexpr int kPartMaxChunks = 16384;   // partition LDS: 2 ints per chunk
 
 // One block of a batched per-sample pass.
 struct BatchWork {
@@ -111,6 +120,12 @@ hipError_t launch_batch_objective(const FinArgs* fa, int ninst, int iter, hipStr
 hipError_t launch_batch_pad(const FinArgs* fa, const float* const* C_in, int ninst, hipStream_t s);
 // Resident blocks per CU of the plain pass (HIP occupancy query), -1 on error.
 int plain_blocks_per_cu(int D8, Mode mode, size_t lds_bytes);
+// Partitioned chunk update: partition (one wave per sub-range), then blocks
+// (point range x, label chunk y) over their samples only.
+size_t part_update_lds_bytes(int kc, int d);
+int part_update_blocks_per_cu(int D8, size_t lds_bytes);
+hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* poff, int32_t* pcnt, hipStream_t s);
+hipError_t launch_part_update(int D8, const PassArgs& a, dim3 grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStream_t s);
 
@@ -120,10 +135,6 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStrea
 // operands 13% slower than SGPR operands.
 constexpr int plain_rows_per_lane(int) { return 1; }
 inline int plain_tile(int D8) { return kBlock * plain_rows_per_lane(D8); }
-// Update-only passes read labels, not distances: 4 labels per lane per tile,
-// so each wave's list of owned samples is long enough to keep 16 rows in flight.
-constexpr int kUpdateRows = 4;
-
 // LDS bytes the plain pass needs for given k, d (activation record + label buffers).
 inline size_t plain_lds_bytes(int k, int d, Mode mode)
 {
@@ -131,8 +142,7 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
     if (mode != MODE_ASSIGN) {
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
-        const size_t tile = (size_t)kBlock * (mode == MODE_UPDATE_WIDE ? kUpdateRows : 1);
-        b += (2 + kWaves) * tile * sizeof(int32_t);          // labels of a tile (double-buffered), owned lists
+        b += (2 + kWaves) * (size_t)kBlock * sizeof(int32_t);   // labels of a tile (double-buffered), owned lists
     }
     return b;
 }

@@ -129,8 +129,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
                                           int slot, int chunk, unsigned char* smem)
 {
     constexpr int D = 8 * D8;
-    constexpr int R = (MODE == MODE_UPDATE_WIDE) ? kUpdateRows : plain_rows_per_lane(D8);
-    constexpr bool UPD = (MODE == MODE_UPDATE || MODE == MODE_UPDATE_WIDE);
+    constexpr int R = plain_rows_per_lane(D8);
+    constexpr bool UPD = (MODE == MODE_UPDATE);
     constexpr int TILE = kBlock * R;
     __shared__ double redJ[kWaves];
     __shared__ int32_t redC[kWaves];
@@ -265,6 +265,214 @@ __global__ __launch_bounds__(kBlock) void batch_pass(const BatchWork* __restrict
     pass_body<D8, MODE>(a, w.t0, w.t1, 1, w.slot, 0, smem);
 }
 
+// ------------------------------------------------------ partitioned update
+// Large records are reduced over label chunks.  Instead of every (point
+// range, chunk) block scanning all labels of its range, one pass partitions
+// each kPartRows-sample sub-range by label chunk (a stable counting sort:
+// chunk counts, their prefix, then each 64-sample group's lanes placed chunk
+// by chunk in lane order), and the chunk blocks read just their samples.
+__global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict__ labels, int64_t n, int32_t k,
+                                                       int32_t kc, int32_t nch, int32_t* perm, int32_t* poff,
+                                                       int32_t* pcnt, const Ctrl* ctrl, int32_t iter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (ctrl != nullptr && ctrl->stop_iter < iter) return;  // converged earlier
+    int32_t* cnt = reinterpret_cast<int32_t*>(smem);     // [nch]
+    int32_t* cur = cnt + nch;                             // [nch]
+    const int lane = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kPartRows;
+    const int64_t end = base + kPartRows < n ? base + kPartRows : n;
+    for (int c = lane; c < nch; c += 64) cnt[c] = 0;
+    __syncthreads();
+    for (int64_t g = base; g < end; g += 64) {
+        const int64_t i = g + lane;
+        const int L = i < end ? labels[i] : -1;
+        if (L >= 0 && L < k) __hip_atomic_fetch_add(cnt + L / kc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    int carry = 0;
+    for (int c0 = 0; c0 < nch; c0 += 64) {
+        const int c = c0 + lane;
+        const int v = c < nch ? cnt[c] : 0;
+        int incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (c < nch) {
+            const int start = (int)base + carry + incl - v;
+            cur[c] = start;
+            poff[(int64_t)blockIdx.x * nch + c] = start;
+            pcnt[(int64_t)blockIdx.x * nch + c] = v;
+        }
+        carry += __shfl(incl, 63);
+    }
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int64_t g = base; g < end; g += 64) {
+        const int64_t i = g + lane;
+        const int L = i < end ? labels[i] : -1;
+        const int c = (L >= 0 && L < k) ? L / kc : -1;
+        uint64_t rem = __ballot(c >= 0);
+        while (rem) {
+            const int cx = __builtin_amdgcn_readlane(c, (int)__builtin_ctzll(rem));
+            const uint64_t m = __ballot(c == cx);
+            const int at = cur[cx];
+            if (c == cx) perm[at + (int)__popcll(m & lt)] = (int32_t)i;
+            if (lane == (int)__builtin_ctzll(m)) cur[cx] = at + (int)__popcll(m);
+            rem &= ~m;
+        }
+    }
+}
+
+// Block (x, y): labels [y*kc, y*kc + kc') over sub-ranges [x*nsub/G, (x+1)*nsub/G);
+// wave w adds the samples whose chunk-local label is congruent to w mod 4,
+// in sample order (sub-range, then list order), by LDS atomics in program
+// order; the record goes to partial slot x like the other update passes.
+template <int D8>
+__global__ __launch_bounds__(kBlock) void part_update_kernel(PassArgs a)
+{
+    constexpr int FPL = (8 * D8 + 63) / 64;
+    constexpr int B = FPL == 1 ? 32 : 16;
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;  // converged earlier
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int k = a.k, d = a.d;
+    const int y = blockIdx.y;
+    const int j0 = y * a.kc;
+    const int kc = min(a.kc, k - j0);
+    double* S = reinterpret_cast<double*>(smem);
+    int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
+    int32_t* wrow = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [kWaves][64] owned sample indices
+    int32_t* woff = wrow + kWaves * 64;                        // [kWaves][64] their record offsets
+    for (int e = tid; e < kc * d; e += kBlock) S[e] = 0.0;
+    for (int j = tid; j < kc; j += kBlock) cnt[j] = 0;
+    __syncthreads();
+    int32_t* wr = wrow + wave * 64;
+    int32_t* wo = woff + wave * 64;
+    int fc[FPL];
+#pragma unroll
+    for (int m = 0; m < FPL; ++m) fc[m] = min(lane + 64 * m, d - 1);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int s0 = (int)((int64_t)blockIdx.x * a.nsub / gridDim.x);
+    const int s1 = (int)((int64_t)(blockIdx.x + 1) * a.nsub / gridDim.x);
+    for (int sr = s0; sr < s1; ++sr) {
+        const int start = a.poff[(int64_t)sr * a.nch + y];
+        const int num = a.pcnt[(int64_t)sr * a.nch + y];
+        for (int q0 = 0; q0 < num; q0 += 64) {
+            const int e = q0 + lane < num ? a.perm[start + q0 + lane] : -1;
+            const int L = e >= 0 ? a.labels[e] - j0 : -1;
+            const bool own = e >= 0 && (L & (kWaves - 1)) == wave;
+            const uint64_t mask = __ballot(own);
+            if (own) {
+                const int at = (int)__popcll(mask & lt);
+                wr[at] = e;
+                wo[at] = L * d;
+                __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            const int nown = (int)__popcll(mask);
+            for (int i0 = 0; i0 < nown; i0 += B) {
+                const int row_i = (lane < B && i0 + lane < nown) ? wr[i0 + lane] : -1;
+                const int off_i = (lane < B && i0 + lane < nown) ? wo[i0 + lane] : -1;
+                const int first = __builtin_amdgcn_readfirstlane(row_i);     // entry i0: always valid
+                float v[B][FPL];
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    int r = __builtin_amdgcn_readlane(row_i, u);
+                    r = r >= 0 ? r : first;
+                    const float* row = a.X + (int64_t)r * d;
+#pragma unroll
+                    for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
+                }
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int o = __builtin_amdgcn_readlane(off_i, u);
+                    if (o >= 0) {
+#pragma unroll
+                        for (int m = 0; m < FPL; ++m) {
+                            const int f = lane + 64 * m;
+                            if (f < d) lds_add_f64(S + o + f, (double)v[u][m]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int b = blockIdx.x;
+    double* dst = a.part.S + (size_t)b * k * d + (size_t)j0 * d;
+    for (int e = tid; e < kc * d; e += kBlock) dst[e] = S[e];
+    int32_t* dc = a.part.cnt + (size_t)b * k + j0;
+    for (int j = tid; j < kc; j += kBlock) dc[j] = cnt[j];
+}
+
+size_t part_update_lds_bytes(int kc, int d)
+{
+    return (size_t)kc * d * sizeof(double) + (((size_t)kc * sizeof(int32_t) + 15) & ~(size_t)15) +
+           2 * kWaves * 64 * sizeof(int32_t);
+}
+
+hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* poff, int32_t* pcnt, hipStream_t s)
+{
+    const size_t lds = 2 * (size_t)a.nch * sizeof(int32_t);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&partition_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(partition_kernel, dim3(a.nsub), dim3(64), lds, s, a.labels, a.n, a.k, a.kc, a.nch, perm,
+                       poff, pcnt, a.ctrl, a.iter);
+    return hipGetLastError();
+}
+
+template <int D8>
+static hipError_t launch_part_d8(const PassArgs& a, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&part_update_kernel<D8>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((part_update_kernel<D8>), grid, dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int D8>
+static int part_occ_d8(size_t lds)
+{
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&part_update_kernel<D8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -1;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, part_update_kernel<D8>, kBlock, lds) != hipSuccess)
+        return -1;
+    return nb;
+}
+
+hipError_t launch_part_update(int D8, const PassArgs& a, dim3 grid, size_t lds, hipStream_t s)
+{
+    switch (D8) {
+#define KM_PU(N) case N: return launch_part_d8<N>(a, grid, lds, s);
+    KM_PU(1) KM_PU(2) KM_PU(3) KM_PU(4) KM_PU(5) KM_PU(6) KM_PU(7) KM_PU(8)
+    KM_PU(9) KM_PU(10) KM_PU(11) KM_PU(12) KM_PU(13) KM_PU(14) KM_PU(15) KM_PU(16)
+#undef KM_PU
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int part_update_blocks_per_cu(int D8, size_t lds)
+{
+    switch (D8) {
+#define KM_PO(N) case N: return part_occ_d8<N>(lds);
+    KM_PO(1) KM_PO(2) KM_PO(3) KM_PO(4) KM_PO(5) KM_PO(6) KM_PO(7) KM_PO(8)
+    KM_PO(9) KM_PO(10) KM_PO(11) KM_PO(12) KM_PO(13) KM_PO(14) KM_PO(15) KM_PO(16)
+#undef KM_PO
+    default: return -1;
+    }
+}
+
 template <int D8, int MODE>
 static hipError_t allow_lds(size_t lds)
 {
@@ -281,14 +489,12 @@ static hipError_t launch_d8(Mode mode, const PassArgs& a, dim3 grid, size_t lds,
     switch (mode) {
     case MODE_ASSIGN: e = allow_lds<D8, MODE_ASSIGN>(lds); break;
     case MODE_UPDATE: e = allow_lds<D8, MODE_UPDATE>(lds); break;
-    case MODE_UPDATE_WIDE: e = allow_lds<D8, MODE_UPDATE_WIDE>(lds); break;
     case MODE_FUSED:  e = allow_lds<D8, MODE_FUSED>(lds); break;
     }
     if (e != hipSuccess) return e;
     switch (mode) {
     case MODE_ASSIGN: hipLaunchKernelGGL((plain_pass<D8, MODE_ASSIGN>), grid, dim3(kBlock), lds, s, a); break;
     case MODE_UPDATE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE>), grid, dim3(kBlock), lds, s, a); break;
-    case MODE_UPDATE_WIDE: hipLaunchKernelGGL((plain_pass<D8, MODE_UPDATE_WIDE>), grid, dim3(kBlock), lds, s, a); break;
     case MODE_FUSED:  hipLaunchKernelGGL((plain_pass<D8, MODE_FUSED>), grid, dim3(kBlock), lds, s, a); break;
     }
     return hipGetLastError();
@@ -302,7 +508,6 @@ static int occupancy_d8(Mode mode, size_t lds)
     switch (mode) {
     case MODE_ASSIGN: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_ASSIGN>, kBlock, lds); break;
     case MODE_UPDATE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_UPDATE>, kBlock, lds); break;
-    case MODE_UPDATE_WIDE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_UPDATE_WIDE>, kBlock, lds); break;
     case MODE_FUSED:  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plain_pass<D8, MODE_FUSED>, kBlock, lds); break;
     }
     return e == hipSuccess ? nb : -1;
