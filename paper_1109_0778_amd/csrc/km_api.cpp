@@ -67,12 +67,15 @@ struct km_plan {
     // mixed precision (BF16 or FP8 MFMA + FP32 recheck)
     bool mixed = false;
     int fmt = FMT_BF16;
+    bool cascade = false;   // screen + refine (longer centroid sweeps, and FP8); else one BF16 sweep
     int D16 = 0, DP = 0, kpad = 0, IB = 0;
     int grid_mfma = 0, grid_rc = 0;
     int64_t rq_per_block = 0;
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
     size_t off_fsc = 0, off_pfm = 0, off_xq = 0, off_xst = 0;   // FP8 only
+    size_t off_ab16 = 0, off_bias16 = 0, off_cs16 = 0;           // FP8: BF16 operands of the refining pass
+    size_t off_amb = 0, off_ambc = 0;                            // samples the screen left open
     size_t off_pcn = 0;                                          // BF16: per-block max |c|^2
     // workspace
     unsigned char* ws;
@@ -174,7 +177,7 @@ FinArgs fin_args(const km_plan* p)
     f.jmode = p->mixed ? 1 : 0;
     f.Jterm = reinterpret_cast<double*>(p->ws + p->off_jt);
     f.sum_xn2 = p->mixed ? &reinterpret_cast<const XStats*>(p->ws + p->off_xs)->sum_xn2 : nullptr;
-    f.GC = p->mixed ? p->grid_mfma + p->grid_rc : p->grid;
+    f.GC = p->mixed ? (p->cascade ? 2 : 1) * p->grid_mfma + p->grid_rc : p->grid;
     return f;
 }
 
@@ -193,19 +196,29 @@ hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
     return launch_part_update(p->D8, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
 }
 
-// Mixed path: the MFMA pass (timed) and the exact recheck of its queue.
+// Mixed path: the screening MFMA pass (the plan's format), the BF16 refining
+// pass over the samples it left open (both timed, as one), and the exact
+// recheck of the refining pass's queue.  Short sweeps (k <= 128, BF16) run
+// one pass that keeps candidate lists for every sample instead.
 hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, const Ctrl* ctrl, int iter,
                                 int count_changed, hipStream_t s)
 {
     unsigned char* ws = p->ws;
     int32_t* changed = reinterpret_cast<int32_t*>(ws + p->off_pch);
     const bool f8 = p->fmt == FMT_FP8;
-    hipError_t e = launch_prep_c(p->fmt, reinterpret_cast<const float*>(ws + p->off_cp), p->k, p->d, p->D, p->kpad,
-                                 p->DP, reinterpret_cast<const XStats*>(ws + p->off_xs),
+    const int G = p->grid_mfma;
+    const float* Cp = reinterpret_cast<const float*>(ws + p->off_cp);
+    const XStats* xs = reinterpret_cast<const XStats*>(ws + p->off_xs);
+    hipError_t e = launch_prep_c(p->fmt, Cp, p->k, p->d, p->D, p->kpad, p->DP, xs,
                                  f8 ? reinterpret_cast<const float*>(ws + p->off_fsc) : nullptr, ws + p->off_ab,
                                  reinterpret_cast<float*>(ws + p->off_bias), reinterpret_cast<CStats*>(ws + p->off_cs),
                                  f8 ? nullptr : reinterpret_cast<float*>(ws + p->off_pcn), ctrl, iter, s);
     if (e != hipSuccess) return e;
+    if (f8 && (e = launch_prep_c(FMT_BF16, Cp, p->k, p->d, p->D, p->kpad, p->DP, xs, nullptr, ws + p->off_ab16,
+                                 reinterpret_cast<float*>(ws + p->off_bias16),
+                                 reinterpret_cast<CStats*>(ws + p->off_cs16),
+                                 reinterpret_cast<float*>(ws + p->off_pcn), ctrl, iter, s)) != hipSuccess)
+        return e;
     MixArgs m{};
     m.X = X; m.n = p->n; m.d = p->d; m.k = p->k; m.kpad = p->kpad;
     m.Ab = ws + p->off_ab;
@@ -221,23 +234,45 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.rq = reinterpret_cast<int32_t*>(ws + p->off_rq);
     m.rq_count = reinterpret_cast<int32_t*>(ws + p->off_rqc);
     m.rq_per_block = p->rq_per_block;
-    m.nreg = p->grid_mfma;
+    m.nreg = G;
     m.changed_part = changed;
+    m.amb = reinterpret_cast<int32_t*>(ws + p->off_amb);
+    m.amb_count = reinterpret_cast<int32_t*>(ws + p->off_ambc);
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
+    // the refining pass: BF16 operands (the FP8 plan's own copy), FP32 rows
+    MixArgs m2 = m;
+    if (f8) {
+        m2.Ab = ws + p->off_ab16;
+        m2.bias = reinterpret_cast<const float*>(ws + p->off_bias16);
+        m2.cs = reinterpret_cast<const CStats*>(ws + p->off_cs16);
+        m2.Xq = nullptr;
+        m2.xst = nullptr;
+        m2.u = 0.00390625f;
+    }
+    m2.amb = nullptr;
+    m2.amb_count = nullptr;
+    m2.amb_in = m.amb;
+    m2.amb_in_count = m.amb_count;
+    m2.changed_part = changed + G;
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
-    if ((e = launch_mfma_assign(p->fmt, p->D16, m, p->grid_mfma, s)) != hipSuccess) return e;
+    if (p->cascade) {
+        if ((e = launch_mfma_assign(p->fmt, 1, p->D16, m, G, s)) != hipSuccess) return e;
+        if ((e = launch_mfma_assign(FMT_BF16, 2, p->D16, m2, G, s)) != hipSuccess) return e;
+    } else if ((e = launch_mfma_assign(FMT_BF16, 0, p->D16, m, G, s)) != hipSuccess) {
+        return e;
+    }
     if (timed) {
         if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
         ++p->ev_used;
     }
     RecheckArgs r{};
-    r.X = X; r.Cp = reinterpret_cast<const float*>(ws + p->off_cp); r.n = p->n; r.d = p->d; r.k = p->k;
-    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = rq_ints(p->fmt);
-    r.nreg = p->grid_mfma;
-    r.labels = labels; r.changed_part = changed + p->grid_mfma;
+    r.X = X; r.Cp = Cp; r.n = p->n; r.d = p->d; r.k = p->k;
+    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = rq_ints(FMT_BF16);
+    r.nreg = G;
+    r.labels = labels; r.changed_part = changed + (p->cascade ? 2 : 1) * G;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
-    return launch_recheck(p->D8, r, p->grid_mfma, s);
+    return launch_recheck(p->D8, r, G, s);
 }
 
 // Run-level prep of the mixed path (once per call, amortised over its
@@ -348,11 +383,16 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->kpad = (k + kMixCK - 1) / kMixCK * kMixCK;
         p->IB = 1;
         while ((1 << p->IB) < p->kpad) ++p->IB;
-        const int occ = mfma_blocks_per_cu(p->fmt, p->D16);
+        p->cascade = p->fmt == FMT_FP8 || p->kpad > 2 * kMixCK;
+        const int occ = p->cascade ? mfma_blocks_per_cu(p->fmt, 1, p->D16) : mfma_blocks_per_cu(FMT_BF16, 0, p->D16);
         if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
         p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
+        if (p->cascade && mfma_blocks_per_cu(FMT_BF16, 2, p->D16) < 1) {
+            delete p;
+            return fail(KM_EHIP, "occupancy query for the refining MFMA pass failed");
+        }
         p->rq_per_block = ((mt + p->grid_mfma - 1) / p->grid_mfma) * kMixTile;
     }
 
@@ -362,7 +402,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->off_pS = off;   off = align256(off + (size_t)p->GS() * k * d * sizeof(double));
     p->off_pcnt = off; off = align256(off + (size_t)p->GS() * k * sizeof(int32_t));
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
-    p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, p->grid_mfma + p->grid_rc) * sizeof(int32_t));
+    p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, 2 * p->grid_mfma + p->grid_rc) * sizeof(int32_t));
     p->off_pbad = off; off = align256(off + (size_t)std::max(p->grid, p->GS()) * sizeof(int32_t));
     if (p->chunked) {
         p->off_perm = off; off = align256(off + (size_t)n * sizeof(int32_t));
@@ -381,12 +421,17 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_cs = off;   off = align256(off + sizeof(CStats));
         p->off_pcn = off;  off = align256(off + (size_t)prep_c_blocks(p->kpad) * sizeof(float));
         p->off_rqc = off;  off = align256(off + 2 * (size_t)p->grid_mfma * sizeof(int32_t));
-        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(p->fmt) * sizeof(int32_t));
+        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(FMT_BF16) * sizeof(int32_t));
+        p->off_amb = off;  off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(int32_t));
+        p->off_ambc = off; off = align256(off + (size_t)p->grid_mfma * sizeof(int32_t));
         if (p->fmt == FMT_FP8) {
             p->off_fsc = off; off = align256(off + 2 * (size_t)p->DP * sizeof(float));
             p->off_pfm = off; off = align256(off + (size_t)kFmaxBlocks * p->DP * sizeof(float));
             p->off_xq = off;  off = align256(off + (size_t)n * p->DP);
             p->off_xst = off; off = align256(off + (size_t)n * sizeof(float2));
+            p->off_ab16 = off;   off = align256(off + (size_t)p->kpad * p->DP * 2);
+            p->off_bias16 = off; off = align256(off + (size_t)p->kpad * sizeof(float));
+            p->off_cs16 = off;   off = align256(off + sizeof(CStats));
         }
     }
     p->total = off;

@@ -241,7 +241,7 @@ void layout(km_batch* B)
         }
         emit_groups(by_m, c_m, B->order, B->mwork, B->mgroups);
         emit_groups(by_r, c_r, B->order, B->rwork, B->rgroups);
-        for (Group& g : B->mgroups) g.lds = mfma_lds_bytes(FMT_BF16, g.D8);
+        for (Group& g : B->mgroups) g.lds = mfma_lds_bytes(FMT_BF16, g.D8, 0);
         B->off_bm = off;    off = al256(off + (size_t)m * sizeof(BatchMix));
         B->off_mwork = off; off = al256(off + B->mwork.size() * sizeof(BatchWork));
         B->off_rwork = off; off = al256(off + B->rwork.size() * sizeof(BatchWork));

@@ -200,6 +200,10 @@ struct MixArgs {
     int64_t rq_per_block;       // region capacity (tiles per block x samples per tile)
     int32_t nreg;               // queue regions (one per MFMA block or work row)
     int32_t* changed_part;      // [nreg]
+    int32_t* amb;               // stage 1: [nreg][rq_per_block] samples left for stage 2
+    int32_t* amb_count;         // stage 1: [nreg]
+    const int32_t* amb_in;      // stage 2: stage 1's amb and amb_count
+    const int32_t* amb_in_count;
     const Ctrl* ctrl;
     int32_t iter;
     int32_t count_changed;
@@ -234,9 +238,12 @@ int prep_c_blocks(int kpad);
 hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t D, int32_t kpad, int32_t DP,
                          const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, float* part_cn2,
                          const Ctrl* ctrl, int32_t iter, hipStream_t s);
-hipError_t launch_mfma_assign(int fmt, int D16, const MixArgs& a, int grid, hipStream_t s);
-size_t mfma_lds_bytes(int fmt, int D16);
-int mfma_blocks_per_cu(int fmt, int D16);
+// MFMA passes: stage 1 screens every sample (two smallest keys), stage 2
+// (BF16) refines the samples stage 1 listed (candidate lists, recheck queue);
+// stage 0 (the one-pass sweep) serves the batched path.
+hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s);
+size_t mfma_lds_bytes(int fmt, int D16, int stage);
+int mfma_blocks_per_cu(int fmt, int stage, int D16);
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
 
 // Batched mixed path: one record per instance.  The per-iteration prep and

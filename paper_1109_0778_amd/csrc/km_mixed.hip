@@ -519,7 +519,12 @@ __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
 // the two halves of a sample's rows.
 // One block's share of the MFMA pass: 128-sample tiles t_first, t_first +
 // t_step, ... below t_end; its recheck entries go to queue region `region`.
-template <int D16, int FMT>
+// STAGE 0: keys, running minimum and candidate lists over consecutive
+// samples.  STAGE 1 (screen): only the two smallest keys of each sample; a
+// sample whose second key lies outside its band takes the smallest, the
+// others are listed in region `region` of a.amb.  STAGE 2 (refine): the
+// stage-0 sweep over the samples listed in region `region` of a.amb_in.
+template <int D16, int FMT, int STAGE>
 __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
                                           int region, unsigned char* smem)
 {
@@ -562,7 +567,9 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     const float P = (float)a.D8;
     const float gcan = (10.0f + (a.D8 > 1 ? ceilf(log2f(P)) : 0.0f)) * 5.9604645e-8f;
     const int nchunks = a.kpad / kMixCK;
-    const int64_t ntiles = (n + kMixTile - 1) / kMixTile;
+    const int amb_n = STAGE == 2 ? a.amb_in_count[region] : 0;        // samples listed for this block
+    const int32_t* amb_list = STAGE == 2 ? a.amb_in + (size_t)region * a.rq_per_block : nullptr;
+    const int64_t ntiles = STAGE == 2 ? (amb_n + kMixTile - 1) / kMixTile : (n + kMixTile - 1) / kMixTile;
     const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     uint32_t* mycand = cand + (size_t)wave * NB * SLOTS * 64;
     int32_t changed = 0;
@@ -606,7 +613,8 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         int64_t pidx[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int64_t p = t * kMixTile + (int64_t)wave * (NB * 32) + nb * 32 + col;
+            int64_t p = t * kMixTile + (int64_t)wave * (NB * 32) + nb * 32 + col;
+            if constexpr (STAGE == 2) p = p < amb_n ? (int64_t)amb_list[p] : n;   // a listed sample, or none
             pidx[nb] = p;
             const bool valid = p < n;
             if constexpr (F8) {
@@ -661,11 +669,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         // m: running minimum key; cnt: list length; cut: smallest key dropped
         // from a full list (every kept entry is below it); ovf: a full list
         // that could not be split (equal values), i.e. rescan the sample
-        uint32_t m[NB], thr[NB], cut[NB];
+        uint32_t m[NB], m2[NB], thr[NB], cut[NB];
         int cnt[NB], ovf[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            m[nb] = 0xffffffffu; thr[nb] = 0xffffffffu; cut[nb] = 0xffffffffu; cnt[nb] = 0; ovf[nb] = 0;
+            m[nb] = 0xffffffffu; m2[nb] = 0xffffffffu; thr[nb] = 0xffffffffu; cut[nb] = 0xffffffffu; cnt[nb] = 0; ovf[nb] = 0;
         }
 
         // --- sweep over the centroids; the next chunk (possibly chunk 0 of the
@@ -711,6 +719,22 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 __builtin_amdgcn_s_setprio(0);
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
+                if constexpr (STAGE == 1) {
+                    // the two smallest keys so far (m <= m2)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        uint32_t mm = m[nb], mm2 = m2[nb];
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const uint32_t key = (__float_as_uint(acc[nb][i]) & ~ibm) | (j0 + 8 * (i >> 2) + (i & 3));
+                            mm2 = min(mm2, max(mm, key));
+                            mm = min(mm, key);
+                        }
+                        m[nb] = mm;
+                        m2[nb] = mm2;
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     uint32_t key[16];
@@ -768,6 +792,36 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
             }
         }
 
+        if constexpr (STAGE == 1) {
+            // decide per sample: the second key outside the band leaves one
+            // candidate; otherwise list the sample for the refining sweep
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const uint32_t mo = (uint32_t)__shfl_xor((int)m[nb], 32);
+                const uint32_t mo2 = (uint32_t)__shfl_xor((int)m2[nb], 32);
+                const uint32_t mp = min(m[nb], mo);
+                const uint32_t mp2 = min(max(m[nb], mo), min(m2[nb], mo2));
+                const uint32_t tf = thr_key(mp, W[nb], ibm);
+                const int64_t p = pidx[nb];
+                const bool valid = p < n;
+                const bool unique = mp2 > tf && (int)(mp & ibm) < a.k;
+                if (valid && unique && h == 0) {
+                    const int lab = (int)(mp & ibm);
+                    if (a.count_changed) changed += (a.iter == 0) ? 1 : (a.labels[p] != lab);
+                    a.labels[p] = lab;
+                }
+                const uint64_t need = __ballot(valid && !unique && h == 0);
+                if (need) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&blk_count, (int)__popcll(need));
+                    base = __shfl(base, 0);
+                    if (valid && !unique && h == 0)
+                        a.amb[(size_t)region * a.rq_per_block + base + (int)__popcll(need & ((1ull << col) - 1ull))] =
+                            (int32_t)p;
+                }
+            }
+            continue;
+        }
         // --- decide per sample: unique candidate, or queue an exact recheck
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -830,16 +884,23 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         int32_t c = 0;
         for (int w = 0; w < kMixWaves; ++w) c += sred[w];
         a.changed_part[region] = c;
-        a.rq_count[region] = blk_count;
-        a.rq_count[a.nreg + region] = blk_full;
+        if constexpr (STAGE == 1) {
+            a.amb_count[region] = blk_count;
+        } else {
+            a.rq_count[region] = blk_count;
+            a.rq_count[a.nreg + region] = blk_full;
+        }
     }
 }
 
-template <int D16, int FMT>
+template <int D16, int FMT, int STAGE>
 __global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    mfma_body<D16, FMT>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
+    if constexpr (STAGE == 2)
+        mfma_body<D16, FMT, STAGE>(a, 0, INT64_MAX, 1, blockIdx.x, smem);   // block b refines region b
+    else
+        mfma_body<D16, FMT, STAGE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
 }
 
 // Batched instances (BF16): row b of the work table runs tiles [t0, t1) of
@@ -852,7 +913,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void batch_mfma(const BatchWork* __
     const BatchWork w = work[blockIdx.x];
     MixArgs a = bm[w.inst].m;
     a.iter = iter;
-    mfma_body<D16, FMT_BF16>(a, w.t0, w.t1, 1, w.slot, smem);
+    mfma_body<D16, FMT_BF16, 0>(a, w.t0, w.t1, 1, w.slot, smem);
 }
 
 // ------------------------------------------------------------ exact recheck
@@ -1029,80 +1090,90 @@ hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t
     return hipGetLastError();
 }
 
-size_t mfma_lds_bytes(int fmt, int D16)
+size_t mfma_lds_bytes(int fmt, int D16, int stage)
 {
     const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
     return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
-           (size_t)kMixWaves * kMixNB * cand_slots(fmt) * 64 * sizeof(uint32_t);
+           (stage == 1 ? 0 : (size_t)kMixWaves * kMixNB * cand_slots(fmt) * 64 * sizeof(uint32_t));
 }
 
-template <int D16, int FMT>
+template <int D16, int FMT, int STAGE>
 static hipError_t launch_mfma_d16(const MixArgs& a, int grid, hipStream_t s)
 {
-    const size_t lds = mfma_lds_bytes(FMT, D16);
+    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((mfma_assign<D16, FMT>), dim3(grid), dim3(64 * kMixWaves), lds, s, a);
+    hipLaunchKernelGGL((mfma_assign<D16, FMT, STAGE>), dim3(grid), dim3(64 * kMixWaves), lds, s, a);
     return hipGetLastError();
 }
 
-template <int FMT>
-static hipError_t launch_mfma_fmt(int D16, const MixArgs& a, int grid, hipStream_t s)
+template <int FMT, int STAGE>
+static hipError_t launch_mfma_fs(int D16, const MixArgs& a, int grid, hipStream_t s)
 {
     switch (D16) {
-    case 1: return launch_mfma_d16<1, FMT>(a, grid, s);
-    case 2: return launch_mfma_d16<2, FMT>(a, grid, s);
-    case 3: return launch_mfma_d16<3, FMT>(a, grid, s);
-    case 4: return launch_mfma_d16<4, FMT>(a, grid, s);
-    case 5: return launch_mfma_d16<5, FMT>(a, grid, s);
-    case 6: return launch_mfma_d16<6, FMT>(a, grid, s);
-    case 7: return launch_mfma_d16<7, FMT>(a, grid, s);
-    case 8: return launch_mfma_d16<8, FMT>(a, grid, s);
+    case 1: return launch_mfma_d16<1, FMT, STAGE>(a, grid, s);
+    case 2: return launch_mfma_d16<2, FMT, STAGE>(a, grid, s);
+    case 3: return launch_mfma_d16<3, FMT, STAGE>(a, grid, s);
+    case 4: return launch_mfma_d16<4, FMT, STAGE>(a, grid, s);
+    case 5: return launch_mfma_d16<5, FMT, STAGE>(a, grid, s);
+    case 6: return launch_mfma_d16<6, FMT, STAGE>(a, grid, s);
+    case 7: return launch_mfma_d16<7, FMT, STAGE>(a, grid, s);
+    case 8: return launch_mfma_d16<8, FMT, STAGE>(a, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_mfma_assign(int fmt, int D16, const MixArgs& a, int grid, hipStream_t s)
+// The single-instance passes: BF16 and FP8 screens (stage 1), the BF16 refine
+// (stage 2), the BF16 one-pass sweep (stage 0).
+hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s)
 {
-    return fmt == FMT_FP8 ? launch_mfma_fmt<FMT_FP8>(D16, a, grid, s) : launch_mfma_fmt<FMT_BF16>(D16, a, grid, s);
+    if (stage == 1) return fmt == FMT_FP8 ? launch_mfma_fs<FMT_FP8, 1>(D16, a, grid, s)
+                                          : launch_mfma_fs<FMT_BF16, 1>(D16, a, grid, s);
+    if (stage == 2 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 2>(D16, a, grid, s);
+    if (stage == 0 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 0>(D16, a, grid, s);
+    return hipErrorInvalidValue;
 }
 
-template <int D16, int FMT>
+template <int D16, int FMT, int STAGE>
 static int occ_mfma()
 {
-    const size_t lds = mfma_lds_bytes(FMT, D16);
+    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE);
     if (lds > 64 * 1024 &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return -1;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_assign<D16, FMT>, 64 * kMixWaves, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_assign<D16, FMT, STAGE>, 64 * kMixWaves, lds) !=
+        hipSuccess)
         return -1;
     return nb;
 }
 
-template <int FMT>
-static int occ_mfma_fmt(int D16)
+template <int FMT, int STAGE>
+static int occ_mfma_fs(int D16)
 {
     switch (D16) {
-    case 1: return occ_mfma<1, FMT>();
-    case 2: return occ_mfma<2, FMT>();
-    case 3: return occ_mfma<3, FMT>();
-    case 4: return occ_mfma<4, FMT>();
-    case 5: return occ_mfma<5, FMT>();
-    case 6: return occ_mfma<6, FMT>();
-    case 7: return occ_mfma<7, FMT>();
-    case 8: return occ_mfma<8, FMT>();
+    case 1: return occ_mfma<1, FMT, STAGE>();
+    case 2: return occ_mfma<2, FMT, STAGE>();
+    case 3: return occ_mfma<3, FMT, STAGE>();
+    case 4: return occ_mfma<4, FMT, STAGE>();
+    case 5: return occ_mfma<5, FMT, STAGE>();
+    case 6: return occ_mfma<6, FMT, STAGE>();
+    case 7: return occ_mfma<7, FMT, STAGE>();
+    case 8: return occ_mfma<8, FMT, STAGE>();
     default: return -1;
     }
 }
 
-int mfma_blocks_per_cu(int fmt, int D16)
+int mfma_blocks_per_cu(int fmt, int stage, int D16)
 {
-    return fmt == FMT_FP8 ? occ_mfma_fmt<FMT_FP8>(D16) : occ_mfma_fmt<FMT_BF16>(D16);
+    if (stage == 1) return fmt == FMT_FP8 ? occ_mfma_fs<FMT_FP8, 1>(D16) : occ_mfma_fs<FMT_BF16, 1>(D16);
+    if (stage == 2 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 2>(D16);
+    if (stage == 0 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 0>(D16);
+    return -1;
 }
 
 hipError_t launch_batch_prep_x(const BatchWork* xwork, int nxwork, const BatchMix* bm, int ninst, hipStream_t s)
@@ -1123,7 +1194,7 @@ hipError_t launch_batch_prep_c(const BatchMix* bm, int ninst, hipStream_t s)
 template <int D16>
 static hipError_t launch_batch_mfma_d16(const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s)
 {
-    const size_t lds = mfma_lds_bytes(FMT_BF16, D16);
+    const size_t lds = mfma_lds_bytes(FMT_BF16, D16, 0);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_mfma<D16>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

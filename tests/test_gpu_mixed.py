@@ -97,12 +97,15 @@ def test_mixed_stepwise_against_oracle(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_mixed_tolerance_mode_matches_fp32(prec):
+@pytest.mark.parametrize("n,d,k", [(8000, 8, 6), (20000, 16, 300)])   # one-pass sweep; screen + refine
+def test_mixed_tolerance_mode_matches_fp32(prec, n, d, k):
+    """Tolerance mode stops where the FP32 path stops: the changed-label counts
+    of every pass (screen, refine, recheck) add up to the FP32 pass's."""
     torch, B = _torch(), _bind()
-    X, C = datagen.blobs(8000, 8, 6, 6, 1.0, seed=5)
+    X, C = datagen.blobs(n, d, k, k, 1.0, seed=5)
     for tol in (0.0, 1e-3):
-        m = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(8000, 8, 6, prec))
-        p = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(8000, 8, 6, "fp32"))
+        m = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(n, d, k, prec))
+        p = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(n, d, k, "fp32"))
         assert m["iters"] == p["iters"]
         assert np.array_equal(m["C"], p["C"]) and np.array_equal(m["labels"], p["labels"])
 
