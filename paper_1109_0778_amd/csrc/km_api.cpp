@@ -393,7 +393,10 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
             delete p;
             return fail(KM_EHIP, "occupancy query for the refining MFMA pass failed");
         }
-        p->rq_per_block = ((mt + p->grid_mfma - 1) / p->grid_mfma) * kMixTile;
+        // a block's share of samples, under the screen's tile and the others'
+        const int64_t mt1 = (n + mix_tile(1) - 1) / mix_tile(1);
+        p->rq_per_block = std::max(((mt + p->grid_mfma - 1) / p->grid_mfma) * kMixTile,
+                                   ((mt1 + p->grid_mfma - 1) / p->grid_mfma) * mix_tile(1));
     }
 
     size_t off = 0;

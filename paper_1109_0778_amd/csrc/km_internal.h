@@ -153,6 +153,11 @@ enum MixFmt { FMT_BF16 = 0, FMT_FP8 = 1 };
 constexpr int kMixWaves = 4;                    // waves per block
 constexpr int kMixNB = 1;                       // 32-sample column blocks per wave
 constexpr int kMixTile = kMixWaves * kMixNB * 32;
+// The screen (two smallest keys, no candidate lists) holds two column blocks
+// per wave: each centroid fragment read from LDS feeds two MFMAs.
+constexpr int kMixNBScreen = 2;
+__host__ __device__ constexpr int mix_nb(int stage) { return stage == 1 ? kMixNBScreen : kMixNB; }
+__host__ __device__ constexpr int mix_tile(int stage) { return kMixWaves * mix_nb(stage) * 32; }
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
 // Candidates kept per lane (half a sample's rows); the FP8 band is about 16
 // times wider than the BF16 one, so it keeps more.

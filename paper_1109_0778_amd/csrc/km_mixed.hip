@@ -504,6 +504,14 @@ __global__ __launch_bounds__(256) void prep_c_fp8_kernel(const float* __restrict
 }
 
 // ------------------------------------------------------------- the MFMA pass
+// median of three: with a <= b, the second smallest of {a, b, c}
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
 {
     const float v = __uint_as_float(m & ~ibm);
@@ -532,7 +540,8 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     constexpr int ES = F8 ? 1 : 2;         // operand bytes per feature
     constexpr int DP = 16 * D16;
     constexpr int ROWB = DP * ES + 16;     // padded LDS row: conflict-free reads
-    constexpr int NB = kMixNB;
+    constexpr int NB = mix_nb(STAGE);
+    constexpr int TILE = mix_tile(STAGE);   // samples per block per tile
     constexpr int CHB = kMixCK * ROWB;     // bytes of one chunk buffer
     constexpr int V = DP * ES / 16;        // uint4 per centroid row
     constexpr int CAP = cand_cap(FMT);
@@ -569,7 +578,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     const int nchunks = a.kpad / kMixCK;
     const int amb_n = STAGE == 2 ? a.amb_in_count[region] : 0;        // samples listed for this block
     const int32_t* amb_list = STAGE == 2 ? a.amb_in + (size_t)region * a.rq_per_block : nullptr;
-    const int64_t ntiles = STAGE == 2 ? (amb_n + kMixTile - 1) / kMixTile : (n + kMixTile - 1) / kMixTile;
+    const int64_t ntiles = STAGE == 2 ? (amb_n + TILE - 1) / TILE : (n + TILE - 1) / TILE;
     const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     uint32_t* mycand = cand + (size_t)wave * NB * SLOTS * 64;
     int32_t changed = 0;
@@ -613,7 +622,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         int64_t pidx[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            int64_t p = t * kMixTile + (int64_t)wave * (NB * 32) + nb * 32 + col;
+            int64_t p = t * TILE + (int64_t)wave * (NB * 32) + nb * 32 + col;
             if constexpr (STAGE == 2) p = p < amb_n ? (int64_t)amb_list[p] : n;   // a listed sample, or none
             pidx[nb] = p;
             const bool valid = p < n;
@@ -683,6 +692,12 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
             if (pref) KM_LOAD_CHUNK(c + 1 < nchunks ? c + 1 : 0)
             const unsigned char* Ab_c = Abuf + cur * CHB;
             const float* bb_c = bbuf + cur * kMixCK;
+            // screen: the two smallest keys of this chunk, indexed within the
+            // chunk (compile-time constants); chunk base and lane offset are
+            // added when the pair joins the running one
+            uint32_t lm[NB], lm2[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) { lm[nb] = 0xffffffffu; lm2[nb] = 0xffffffffu; }
 #pragma unroll
             for (int tt = 0; tt < kMixCK / 32; ++tt) {
                 f32x16 acc[NB];
@@ -720,18 +735,18 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
                 if constexpr (STAGE == 1) {
-                    // the two smallest keys so far (m <= m2)
+                    // the two smallest keys of the chunk so far (lm <= lm2)
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
-                        uint32_t mm = m[nb], mm2 = m2[nb];
+                        uint32_t mm = lm[nb], mm2 = lm2[nb];
 #pragma unroll
                         for (int i = 0; i < 16; ++i) {
-                            const uint32_t key = (__float_as_uint(acc[nb][i]) & ~ibm) | (j0 + 8 * (i >> 2) + (i & 3));
-                            mm2 = min(mm2, max(mm, key));
+                            const uint32_t key = (__float_as_uint(acc[nb][i]) & ~ibm) | (uint32_t)(tt * 32 + 8 * (i >> 2) + (i & 3));
+                            mm2 = med3_u32(mm, mm2, key);
                             mm = min(mm, key);
                         }
-                        m[nb] = mm;
-                        m2[nb] = mm2;
+                        lm[nb] = mm;
+                        lm2[nb] = mm2;
                     }
                     continue;
                 }
@@ -783,6 +798,17 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                             cnt[nb] = w;
                         }
                     }
+                }
+            }
+            if constexpr (STAGE == 1) {
+                // index bits of the chunk (c * 64) and of the lane's rows (4h)
+                // are clear in the chunk-local keys (kpad >= 64)
+                const uint32_t J = (uint32_t)(c * kMixCK) | (4u * (uint32_t)h);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const uint32_t a1 = lm[nb] | J, a2 = lm2[nb] | J;
+                    m2[nb] = min(min(m2[nb], a2), max(m[nb], a1));
+                    m[nb] = min(m[nb], a1);
                 }
             }
             if (pref) {
