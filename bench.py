@@ -41,9 +41,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 FP32 lanes at 2.4 GHz, one non-packed FP32
-# VALU operation per lane per clock (packed FP32 is not used by this build).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X published FP32 vector peak: 256 CUs x 128 FP32 FMA lanes per clock x
+# 2 FLOP x 2.4 GHz = 157.3 TFLOP/s (reached only with packed FP32 operations,
+# which this library does not emit).
+VALU_PEAK_TFLOPS = 256 * 128 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plain_pass_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1109_0778_amd", "csrc", "km_plain.hip")
@@ -343,7 +344,7 @@ def main():
     fp = timed_lloyd(B, torch, X, C0, "fp32", steps, args.warmup)
     el, kt, J = fp["el"], fp["kt"], fp["J"]
     kmean_ms = float(np.mean(kt)) if kt else float("nan")
-    ops = 2.0 * w.n * w.k * w.d                # one subtract + one FMA per (sample, centroid, feature)
+    ops = 3.0 * w.n * w.k * w.d                # FLOP: one subtract (1) + one FMA (2) per (sample, centroid, feature)
     achieved = ops / (kmean_ms * 1e-3) / 1e12
     algo_bytes = w.n * w.d * 4 + 2 * w.n * 4   # X once, labels read + written
     traffic = measured_traffic(f"{w.name}:{w.n}x{w.d}x{w.k}")
@@ -384,11 +385,11 @@ def main():
             "kernel": "plain_pass (fused assign + per-label reduce)",
             "bound": "alu",
             "achieved": achieved,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS,
+            "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS,
             "traffic": traffic,
-            "ops_per_launch": ops,
+            "flops_per_launch": ops,
             "mean_launch_ms": kmean_ms,
             "launches": len(kt),
             "hbm_gbps_algorithmic_kernel": algo_bytes / (kmean_ms * 1e-3) / 1e9,

@@ -135,6 +135,11 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStrea
 // operands 13% slower than SGPR operands.
 constexpr int plain_rows_per_lane(int) { return 1; }
 inline int plain_tile(int D8) { return kBlock * plain_rows_per_lane(D8); }
+// Lanes that carry one sample row in the per-label adds: a row of at most 16
+// (32) features takes a quarter (half) wave, so one load and one LDS atomic
+// instruction serve four (two) samples.
+__host__ __device__ constexpr int row_lanes(int D8) { return D8 <= 2 ? 16 : D8 <= 4 ? 32 : 64; }
+__host__ __device__ constexpr int row_groups(int D8) { return 64 / row_lanes(D8); }
 // LDS bytes the plain pass needs for given k, d (activation record + label buffers).
 inline size_t plain_lds_bytes(int k, int d, Mode mode)
 {
@@ -142,7 +147,9 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode)
     if (mode != MODE_ASSIGN) {
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
-        b += (2 + kWaves) * (size_t)kBlock * sizeof(int32_t);   // labels of a tile (double-buffered), owned lists
+        // labels of a tile, double-buffered (fused), and each wave's owned
+        // samples, one list per row group; one size serves both modes
+        b += (2 + (size_t)kWaves * row_groups((d + 7) / 8)) * kBlock * sizeof(int32_t);
     }
     return b;
 }

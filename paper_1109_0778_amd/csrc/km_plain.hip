@@ -33,74 +33,111 @@ __device__ __forceinline__ void lds_add_f64(double* p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// "process": add the tile's samples that this wave owns (label L with
-// L % 4 == wave) to the block's activation record, in increasing sample
-// order.  The owned samples are listed (and counted) in LDS first; then B
-// rows at a time are loaded (lane f carries feature f: coalesced) with every
-// load issued before the first is used -- addresses are clamped to a valid row and
-// feature instead of branching, so no load waits on another -- and added
-// with LDS atomics without return, which the wave issues, and the LDS
-// executes, in program order: every sum has a fixed order and nothing waits
-// on their results.
+// "process": add the tile's samples that this wave owns to the block's
+// activation record, in increasing sample order.  lab[g] is the label of
+// sample g * 64 + lane of the tile (-1: none, or another chunk's).  A row
+// takes LPR lanes (lane f carries feature f: coalesced), so a wave holds NG =
+// 64 / LPR row groups; label class c = L mod (4 NG) belongs to wave c / NG,
+// row group c % NG.  Each group lists (and counts) its samples in its own LDS
+// list; then BG rows per group at a time are loaded, the next batch's loads
+// issued before this batch's adds, rows past a list's end clamped to the
+// tile's first row instead of branching, so no load waits on another.  The
+// adds are LDS atomics without return, which the wave issues, and the LDS
+// executes, in program order; the groups of one instruction hold different
+// labels, so every sum has a fixed order and nothing waits on the results.
 template <int D8, int TILE>
-__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, const int32_t* lb, int32_t* wl,
-                                                double* S, int32_t* cnt, int lane, int wave)
+__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, const int (&lab)[TILE / 64],
+                                                int32_t* wl, double* S, int32_t* cnt, int lane, int wave)
 {
-    constexpr int FPL = (8 * D8 + 63) / 64;  // features per lane
-    constexpr int B = FPL == 1 ? 32 : 16;
-    int nown = 0;
+    constexpr int LPR = row_lanes(D8);                          // lanes per row
+    constexpr int NG = 64 / LPR;                                // row groups per wave
+    constexpr int FPL = (8 * D8 + LPR - 1) / LPR;               // features per lane
+    constexpr int BG = NG > 1 ? LPR : (FPL == 1 ? 32 : 16);     // rows per group per batch
+    static_assert(NG * BG <= 64, "one entry per lane");
+    int nown[NG];
+#pragma unroll
+    for (int s = 0; s < NG; ++s) nown[s] = 0;
 #pragma unroll
     for (int g = 0; g < TILE / 64; ++g) {
-        const int L = lb[g * 64 + lane];
-        const bool own = L >= 0 && (L & (kWaves - 1)) == wave;
-        const uint64_t mask = __ballot(own);
-        if (own) {
-            wl[nown + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
-                ((L * d) << 12) | (g * 64 + lane);   // record offset of the row (< 2^19), offset in the tile
-            // counts are integers: any order of these adds gives the same total
-            __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int L = lab[g];
+        const int c = L & (kWaves * NG - 1);
+        const bool own = L >= 0 && c / NG == wave;
+#pragma unroll
+        for (int s = 0; s < NG; ++s) {
+            const bool mine = own && c % NG == s;
+            const uint64_t mask = __ballot(mine);
+            if (mine) {
+                wl[s * TILE + nown[s] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
+                    ((L * d) << 12) | (g * 64 + lane);   // record offset of the row (< 2^19), offset in the tile
+                // counts are integers: any order of these adds gives the same total
+                __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            nown[s] += (int)__popcll(mask);
         }
-        nown += (int)__popcll(mask);
     }
+    const int h = lane / LPR;       // this lane's row group
+    const int fl = lane % LPR;      // its first feature
     int fc[FPL];
 #pragma unroll
-    for (int m = 0; m < FPL; ++m) fc[m] = min(lane + 64 * m, d - 1);
-    for (int i0 = 0; i0 < nown; i0 += B) {
-        const int mine = (lane < B && i0 + lane < nown) ? wl[i0 + lane] : -1;
-        const int first = __builtin_amdgcn_readfirstlane(mine);     // entry i0: always valid
-        float v[B][FPL];
+    for (int m = 0; m < FPL; ++m) fc[m] = min(fl + LPR * m, d - 1);
+    int nmax = nown[0], nmin = nown[0];
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            int ent = __builtin_amdgcn_readlane(mine, u);
-            ent = ent >= 0 ? ent : first;
-            const float* row = Xt + (int64_t)(ent & 4095) * d;
+    for (int s = 1; s < NG; ++s) { nmax = max(nmax, nown[s]); nmin = min(nmin, nown[s]); }
+    // lane s * BG + u holds row u of group s's batch (-1: past the list)
+    const int qs = lane / BG, qu = lane % BG;
+    int qn = nown[0];
+#pragma unroll
+    for (int s = 1; s < NG; ++s) qn = qs == s ? nown[s] : qn;
+    auto entries = [&](int b) {
+        const int i = b * BG + qu;
+        return (qs < NG && i < qn) ? wl[qs * TILE + i] : -1;
+    };
+    // this lane's group's entry of row u
+    auto row_entry = [&](int q, int u) {
+        int e = __builtin_amdgcn_readlane(q, u);
+#pragma unroll
+        for (int s = 1; s < NG; ++s) {
+            const int es = __builtin_amdgcn_readlane(q, s * BG + u);
+            e = h == s ? es : e;
+        }
+        return e;
+    };
+    const int nbat = (nmax + BG - 1) / BG;
+    float v0[BG][FPL], v1[BG][FPL];
+    int q0 = -1, q1 = -1;
+    auto load = [&](int b, float (&v)[BG][FPL], int& q) {
+        q = entries(b);
+#pragma unroll
+        for (int u = 0; u < BG; ++u) {
+            const int e = row_entry(q, u);
+            const float* row = Xt + (int64_t)(e >= 0 ? (e & 4095) : 0) * d;
 #pragma unroll
             for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
         }
-        if (i0 + B <= nown) {                    // a full batch: no per-entry test
+    };
+    auto add = [&](int b, const float (&v)[BG][FPL], int q) {
+        const bool full = b * BG + BG <= nmin;   // every group has all BG rows: no per-row test
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                double* srow = S + (__builtin_amdgcn_readlane(mine, u) >> 12);
+        for (int u = 0; u < BG; ++u) {
+            const int e = row_entry(q, u);
+            if (full || e >= 0) {
+                double* srow = S + (e >> 12);
 #pragma unroll
                 for (int m = 0; m < FPL; ++m) {
-                    const int f = lane + 64 * m;
+                    const int f = fl + LPR * m;
                     if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
                 }
             }
-        } else {
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int ent = __builtin_amdgcn_readlane(mine, u);
-                if (ent >= 0) {
-                    double* srow = S + (ent >> 12);
-#pragma unroll
-                    for (int m = 0; m < FPL; ++m) {
-                        const int f = lane + 64 * m;
-                        if (f < d) lds_add_f64(srow + f, (double)v[u][m]);
-                    }
-                }
-            }
+        }
+    };
+    if (nbat > 0) load(0, v0, q0);
+    for (int b = 0; b < nbat; b += 2) {
+        if (b + 1 < nbat) load(b + 1, v1, q1);
+        add(b, v0, q0);
+        if (b + 1 < nbat) {
+            if (b + 2 < nbat) load(b + 2, v0, q0);
+            add(b + 1, v1, q1);
         }
     }
 }
@@ -131,6 +168,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     constexpr int D = 8 * D8;
     constexpr int R = plain_rows_per_lane(D8);
     constexpr bool UPD = (MODE == MODE_UPDATE);
+    constexpr bool FUSED = (MODE == MODE_FUSED);
     constexpr int TILE = kBlock * R;
     __shared__ double redJ[kWaves];
     __shared__ int32_t redC[kWaves];
@@ -149,8 +187,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
 
     double* S = reinterpret_cast<double*>(smem);
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
-    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [2][TILE] labels of a tile
-    int32_t* wlist = lbl + 2 * TILE;                           // [kWaves][TILE] owned samples per wave
+    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [2][TILE] labels of a tile (fused)
+    int32_t* wlist = lbl + 2 * TILE;                           // [kWaves][row groups][TILE] owned samples
 
     // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
@@ -163,53 +201,88 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     int32_t changed = 0, bad = 0;
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t t_last = t_end < ntiles ? t_end : ntiles;
-    int buf = 0;
-    for (int64_t t = t_first; t < t_last; t += t_step) {
-        // lane holds samples t*TILE + r*256 + tid, r < R
-        int lab[R];
-        if (UPD) {
+    const int64_t nmine = t_first < t_last ? (t_last - t_first + t_step - 1) / t_step : 0;
+
+    // the map over one tile: nearest centroid, labels, objective, changed count
+    auto assign_tile = [&](int64_t t, int (&lab)[R]) {
+        float x[R][D];
+        int old[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t gp = t * TILE + r * kBlock + tid;
-                lab[r] = -1;
-                if (gp < n) {
-                    const int L = a.labels[gp];
-                    if (L < 0 || L >= k) ++bad;
-                    else if (L >= j0 && L < j0 + kc) lab[r] = L - j0;   // chunk-local label
-                }
-            }
-        } else {
-            float x[R][D];
+        for (int r = 0; r < R; ++r) {
+            const int64_t gp = t * TILE + r * kBlock + tid;
+            const bool valid = gp < n;
+            // the previous label is fetched with the row, not after the sweep
+            old[r] = (valid && a.count_changed && a.iter != 0) ? a.labels[gp] : -1;
+            load_row<D8>(a.X + (valid ? gp : 0) * d, d, valid, x[r]);
+        }
+        float best[R];
+        int bj[R];
+        nearest<D8, R>(x, (cfloat*)a.Cp, k, best, bj);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t gp = t * TILE + r * kBlock + tid;
-                const bool valid = gp < n;
-                load_row<D8>(a.X + (valid ? gp : 0) * d, d, valid, x[r]);
-            }
-            float best[R];
-            int bj[R];
-            nearest<D8, R>(x, (cfloat*)a.Cp, k, best, bj);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t gp = t * TILE + r * kBlock + tid;
-                lab[r] = -1;
-                if (gp < n) {
-                    if (a.count_changed) changed += (a.iter == 0) ? 1 : (a.labels[gp] != bj[r]);
-                    a.labels[gp] = bj[r];
-                    if (a.mindist) a.mindist[gp] = best[r];
-                    Jl += (double)best[r];
-                    lab[r] = bj[r];
-                }
+        for (int r = 0; r < R; ++r) {
+            const int64_t gp = t * TILE + r * kBlock + tid;
+            lab[r] = -1;
+            if (gp < n) {
+                if (a.count_changed) changed += (a.iter == 0) ? 1 : (old[r] != bj[r]);
+                a.labels[gp] = bj[r];
+                if (a.mindist) a.mindist[gp] = best[r];
+                Jl += (double)best[r];
+                lab[r] = bj[r];
             }
         }
-        if (MODE != MODE_ASSIGN) {
-            // "process": every sample of the tile into the activation record
-            int32_t* lb = lbl + buf * TILE;
+    };
+
+    if constexpr (FUSED) {
+        for (int64_t i = 0; i < nmine; ++i) {
+            const int64_t t = t_first + i * t_step;
+            int lab[R];
+            assign_tile(t, lab);
+            // "process": the tile's labels go through LDS to the waves that own them
+            int32_t* lb = lbl + (i & 1) * TILE;
 #pragma unroll
             for (int r = 0; r < R; ++r) lb[r * kBlock + tid] = lab[r];
-            __syncthreads();
-            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lb, wlist + wave * TILE, S, cnt, lane, wave);
-            buf ^= 1;
+            __syncthreads();    // labels of the tile complete
+            int lt[TILE / 64];
+#pragma unroll
+            for (int g = 0; g < TILE / 64; ++g) lt[g] = lb[g * 64 + lane];
+            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lt, wlist + wave * row_groups(D8) * TILE, S, cnt, lane, wave);
+        }
+    } else {
+        // labels of a tile for the update pass (INT_MIN: past the last sample)
+        int Ln[TILE / 64];
+        auto load_labels = [&](int64_t t, int (&Lv)[TILE / 64]) {
+#pragma unroll
+            for (int g = 0; g < TILE / 64; ++g) {
+                const int64_t gp = t * TILE + g * 64 + lane;
+                Lv[g] = gp < n ? a.labels[gp] : INT_MIN;
+            }
+        };
+        if (UPD && nmine > 0) load_labels(t_first, Ln);
+        for (int64_t i = 0; i < nmine; ++i) {
+            const int64_t t = t_first + i * t_step;
+            // lane holds samples t*TILE + r*256 + tid, r < R
+            if (UPD) {
+                // every wave reads the whole tile's labels (the next tile's
+                // are in flight while this one is added); wave g counts the
+                // invalid labels of row group g
+                int L[TILE / 64];
+#pragma unroll
+                for (int g = 0; g < TILE / 64; ++g) L[g] = Ln[g];
+                if (i + 1 < nmine) load_labels(t + t_step, Ln);
+                int lab[TILE / 64];
+#pragma unroll
+                for (int g = 0; g < TILE / 64; ++g) {
+                    lab[g] = -1;
+                    if (L[g] != INT_MIN) {
+                        if (L[g] < 0 || L[g] >= k) bad += (g == wave);
+                        else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
+                    }
+                }
+                accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lab, wlist + wave * row_groups(D8) * TILE, S, cnt, lane, wave);
+            } else {
+                int lab[R];
+                assign_tile(t, lab);
+            }
         }
     }
 
@@ -245,8 +318,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     }
 }
 
+// The update pass holds two batches of rows in flight; it is built for four
+// resident waves per SIMD (at most 128 VGPRs).
+__host__ __device__ constexpr int pass_min_waves(int mode) { return mode == MODE_UPDATE ? 4 : 1; }
+
 template <int D8, int MODE>
-__global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_min_waves(MODE))))
+void plain_pass(PassArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     pass_body<D8, MODE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, blockIdx.y, smem);
@@ -255,7 +333,8 @@ __global__ __launch_bounds__(kBlock) void plain_pass(PassArgs a)
 // Batched instances: block b runs tiles [t0, t1) of instance work[b].inst into
 // that instance's partial slot work[b].slot.
 template <int D8, int MODE>
-__global__ __launch_bounds__(kBlock) void batch_pass(const BatchWork* __restrict__ work,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_min_waves(MODE))))
+void batch_pass(const BatchWork* __restrict__ work,
                                                      const PassArgs* __restrict__ insts, int32_t iter)
 {
     extern __shared__ __align__(16) unsigned char smem[];
