@@ -31,7 +31,7 @@
  *   - Shape limits: 1 <= k <= n < 2^31, 1 <= d <= 1024 (the FP32 path
  *     currently supports d <= 128 and returns KM_ENOTSUP above that; a
  *     per-label record k * d * 8 bytes above 80 KiB is reduced over label
- *     chunks of 48 KiB, at most 16384 of them, KM_ENOTSUP beyond).
+ *     chunks of 44 KiB, at most 16384 of them, KM_ENOTSUP beyond).
  *   - Inputs must be finite; NaN/Inf are not checked on the hot path.
  *   - A plan is not thread-safe; distinct plans are independent.  Calls that
  *     share one plan (one workspace) must be ordered on one stream.

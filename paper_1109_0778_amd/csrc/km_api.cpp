@@ -58,7 +58,7 @@ struct km_plan {
     bool split;          // assign and reduce as two passes (the fused pass would lose occupancy)
     bool chunked;        // per-label record too large for one block: the reduce runs over label chunks
     int nsub = 0;        // chunked: partition sub-ranges (kPartRows samples each)
-    size_t off_perm = 0, off_poff = 0, off_plen = 0;
+    size_t off_perm = 0, off_plab = 0, off_poff = 0, off_plen = 0;
     int kc, nch;         // update: labels per chunk, chunks
     int grid_upd;        // update: slots (point ranges) per chunk
     size_t lds_fused;    // dynamic LDS of the fused pass (whole record)
@@ -69,6 +69,7 @@ struct km_plan {
     int fmt = FMT_BF16;
     bool cascade = false;   // screen + refine (longer centroid sweeps, and FP8); else one BF16 sweep
     int D16 = 0, DP = 0, kpad = 0, IB = 0;
+    int upd_tiles = 1;   // update pass: tiles listed per step
     int grid_mfma = 0, grid_rc = 0;
     int64_t rq_per_block = 0;
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
@@ -114,8 +115,9 @@ namespace {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// labels per chunk of a chunked reduce: 48 KiB of FP64 sums
-int chunk_labels(int k, int d) { return std::max(1, std::min(k, (48 * 1024) / (8 * d))); }
+// Labels per chunk of a chunked reduce: sums and count of a chunk within 44 KiB, so with the
+// update pass's entry lists three blocks fit in a CU's 160 KiB of LDS.
+int chunk_labels(int k, int d) { return std::max(1, std::min(k, (44 * 1024) / (8 * d + 4))); }
 
 km_status check_plan(const km_plan* p)
 {
@@ -155,9 +157,10 @@ PassArgs pass_args(const km_plan* p, const float* X, const float* Cp, int32_t* l
     PassArgs a{};
     a.X = X; a.Cp = Cp; a.labels = labels; a.mindist = nullptr;
     a.part = partials_of(p); a.ctrl = nullptr;
-    a.n = p->n; a.d = p->d; a.k = p->k; a.iter = 0; a.count_changed = 0; a.kc = p->kc;
+    a.n = p->n; a.d = p->d; a.k = p->k; a.iter = 0; a.count_changed = 0; a.kc = p->kc; a.upd_tiles = p->upd_tiles;
     if (p->chunked) {
         a.perm = reinterpret_cast<const int32_t*>(p->ws + p->off_perm);
+        a.plab = reinterpret_cast<const int32_t*>(p->ws + p->off_plab);
         a.poff = reinterpret_cast<const int32_t*>(p->ws + p->off_poff);
         a.pcnt = reinterpret_cast<const int32_t*>(p->ws + p->off_plen);
         a.nsub = p->nsub;
@@ -190,6 +193,7 @@ hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
     if (!p->chunked) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd), p->lds_upd, s);
     // label chunks: partition the samples by chunk, then reduce each chunk's samples
     hipError_t e = launch_partition(a, reinterpret_cast<int32_t*>(p->ws + p->off_perm),
+                                    reinterpret_cast<int32_t*>(p->ws + p->off_plab),
                                     reinterpret_cast<int32_t*>(p->ws + p->off_poff),
                                     reinterpret_cast<int32_t*>(p->ws + p->off_plen), s);
     if (e != hipSuccess) return e;
@@ -344,26 +348,33 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     // the reduce run fused as long as that costs the pass no resident blocks
     // (a record of a few tens of KiB); beyond that they run as two passes, the
     // reduce over the whole record up to 80 KiB and, above it, over label
-    // chunks of at most 48 KiB: the samples are partitioned by chunk, then a
+    // chunks of at most 44 KiB: the samples are partitioned by chunk, then a
     // 2-D grid of (point range, label chunk) blocks reduces each chunk.
     p->lds_fused = plain_lds_bytes(k, d, MODE_FUSED);
     p->chunked = p->lds_fused > 80 * 1024;
     p->kc = p->chunked ? chunk_labels(k, d) : k;
     p->nch = (k + p->kc - 1) / p->kc;
     p->nsub = p->chunked ? (int)((n + kPartRows - 1) / kPartRows) : 0;
-    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, d) : p->lds_fused;
 
     // One resident wave of blocks for the persistent passes, at most 4 per CU.
     const int per_cu_assign = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
     const int per_cu_fused = p->chunked ? 0 : plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused);
-    int per_cu_upd = p->chunked ? part_update_blocks_per_cu(p->D8, p->lds_upd)
-                                : plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
-    if (per_cu_assign < 1 || per_cu_upd < 1 || (!p->chunked && per_cu_fused < 1)) {
+    if (per_cu_assign < 1 || (!p->chunked && per_cu_fused < 1)) {
         delete p;
         return fail(KM_EHIP, "occupancy query for the per-sample pass failed");
     }
     int per_cu = std::min(per_cu_assign, 4);
     p->split = p->chunked || per_cu_fused < per_cu;
+    // A stand-alone update lists kUpdTiles tiles per step; the update that
+    // must walk the fused pass's blocks (no split) keeps its LDS and lists one.
+    p->upd_tiles = p->split ? kUpdTiles : 1;
+    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, d) : plain_lds_bytes(k, d, MODE_UPDATE, p->upd_tiles);
+    int per_cu_upd = p->chunked ? part_update_blocks_per_cu(p->D8, p->lds_upd)
+                                : plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
+    if (per_cu_upd < 1) {
+        delete p;
+        return fail(KM_EHIP, "occupancy query for the update pass failed");
+    }
     if (!p->split) per_cu = std::min(per_cu, per_cu_fused);
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
     per_cu_upd = std::min(per_cu_upd, 4);
@@ -409,6 +420,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->off_pbad = off; off = align256(off + (size_t)std::max(p->grid, p->GS()) * sizeof(int32_t));
     if (p->chunked) {
         p->off_perm = off; off = align256(off + (size_t)n * sizeof(int32_t));
+        p->off_plab = off; off = align256(off + (size_t)n * sizeof(int32_t));
         p->off_poff = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
         p->off_plen = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
     }

@@ -168,7 +168,7 @@ void layout(km_batch* B)
         const int64_t tiles = (x.n + kBlock - 1) / kBlock;
         const int nb = (int)((tiles + B->tpb - 1) / B->tpb);
         B->nslots[i] = nb;
-        const size_t lds = lds_bucket(plain_lds_bytes(x.k, x.d, MODE_FUSED));
+        const size_t lds = lds_bucket(plain_lds_bytes(x.k, x.d, B->mixed ? MODE_UPDATE : MODE_FUSED));
         auto key = std::make_pair(D8, lds);
         for (int b = 0; b < nb; ++b) {
             BatchWork w;
@@ -274,7 +274,7 @@ km_status upload(km_batch* B)
         PassArgs& a = pa[i];
         std::memset(&a, 0, sizeof a);
         a.X = x.X; a.Cp = Cp; a.labels = x.labels; a.mindist = nullptr; a.part = pt; a.ctrl = nullptr;
-        a.n = x.n; a.d = x.d; a.k = x.k; a.iter = 0; a.count_changed = 0; a.kc = x.k;
+        a.n = x.n; a.d = x.d; a.k = x.k; a.iter = 0; a.count_changed = 0; a.kc = x.k; a.upd_tiles = kUpdTiles;
         FinArgs& f = fa[i];
         std::memset(&f, 0, sizeof f);
         f.part = pt; f.G = B->nslots[i]; f.GJ = B->nslots[i]; f.GC = B->nslots[i];

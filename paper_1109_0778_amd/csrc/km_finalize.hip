@@ -96,12 +96,17 @@ __global__ __launch_bounds__(64) void finalize_objective_kernel(FinArgs a)
     const int lane = threadIdx.x;
     double J = 0.0;
     int64_t ch = 0;
+    // unrolled: the loads of several strides are in flight together (the
+    // adds keep their order)
     if (a.jmode == 0) {
+#pragma unroll 8
         for (int b = lane; b < a.GJ; b += 64) J += a.part.J[b];
     } else {
         const int nb = finalize_blocks(a.k, a.d);
+#pragma unroll 8
         for (int b = lane; b < nb; b += 64) J += a.Jterm[b];
     }
+#pragma unroll 8
     for (int b = lane; b < a.GC; b += 64) ch += a.part.changed[b];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -146,6 +151,7 @@ __global__ __launch_bounds__(128) void batch_finalize_kernel(const BatchFinWork*
             const int f = (int)(e - (int64_t)j * a.d);
             double S = 0.0;
             int64_t c = 0;
+#pragma unroll 8
             for (int b = 0; b < a.G; ++b) {
                 S += a.part.S[(size_t)b * kd + e];
                 c += a.part.cnt[(size_t)b * a.k + j];

@@ -55,9 +55,11 @@ struct PassArgs {
     int32_t iter;         // Lloyd iteration index (0 outside kmeans_lloyd)
     int32_t count_changed;// assign passes: count labels that differ from the stored ones
     int32_t kc;           // update passes: labels per chunk; block y owns labels [y*kc, y*kc+kc)
+    int32_t upd_tiles;    // update pass: tiles listed and added per step (1 .. kUpdTiles)
     // partitioned chunk update: sample indices grouped by label chunk within
     // each kPartRows-sample sub-range, in sample order
     const int32_t* perm;  // [n]
+    const int32_t* plab;  // [n] label of sample perm[i]
     const int32_t* poff;  // [nsub][nch] start of (sub-range, chunk) in perm
     const int32_t* pcnt;  // [nsub][nch] its length
     int32_t nsub, nch;
@@ -124,7 +126,8 @@ int plain_blocks_per_cu(int D8, Mode mode, size_t lds_bytes);
 // (point range x, label chunk y) over their samples only.
 size_t part_update_lds_bytes(int kc, int d);
 int part_update_blocks_per_cu(int D8, size_t lds_bytes);
-hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* poff, int32_t* pcnt, hipStream_t s);
+hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* plab, int32_t* poff, int32_t* pcnt,
+                            hipStream_t s);
 hipError_t launch_part_update(int D8, const PassArgs& a, dim3 grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStream_t s);
@@ -140,16 +143,22 @@ inline int plain_tile(int D8) { return kBlock * plain_rows_per_lane(D8); }
 // instruction serve four (two) samples.
 __host__ __device__ constexpr int row_lanes(int D8) { return D8 <= 2 ? 16 : D8 <= 4 ? 32 : 64; }
 __host__ __device__ constexpr int row_groups(int D8) { return 64 / row_lanes(D8); }
+// Each wave's owned-sample lists: two row groups share a buffer, one filling
+// it from the front, the other from the back.
+__host__ __device__ constexpr int list_bufs(int D8) { return (row_groups(D8) + 1) / 2; }
+// Tiles the update pass lists and adds per step (the fused pass: one).
+constexpr int kUpdTiles = 3;
 // LDS bytes the plain pass needs for given k, d (activation record + label buffers).
-inline size_t plain_lds_bytes(int k, int d, Mode mode)
+inline size_t plain_lds_bytes(int k, int d, Mode mode, int upd_tiles = kUpdTiles)
 {
     size_t b = 0;
     if (mode != MODE_ASSIGN) {
         b += (size_t)k * (size_t)d * sizeof(double);
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
-        // labels of a tile, double-buffered (fused), and each wave's owned
-        // samples, one list per row group; one size serves both modes
-        b += (2 + (size_t)kWaves * row_groups((d + 7) / 8)) * kBlock * sizeof(int32_t);
+        // fused: labels of a tile, double-buffered, and each wave's owned
+        // samples of a tile; update: each wave's owned samples of a step
+        const size_t lists = (size_t)kWaves * list_bufs((d + 7) / 8) * kBlock;
+        b += (mode == MODE_FUSED ? 2 * (size_t)kBlock + lists : (size_t)upd_tiles * lists) * sizeof(int32_t);
     }
     return b;
 }

@@ -33,20 +33,23 @@ __device__ __forceinline__ void lds_add_f64(double* p, double v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// "process": add the tile's samples that this wave owns to the block's
-// activation record, in increasing sample order.  lab[g] is the label of
-// sample g * 64 + lane of the tile (-1: none, or another chunk's).  A row
-// takes LPR lanes (lane f carries feature f: coalesced), so a wave holds NG =
-// 64 / LPR row groups; label class c = L mod (4 NG) belongs to wave c / NG,
-// row group c % NG.  Each group lists (and counts) its samples in its own LDS
-// list; then BG rows per group at a time are loaded, the next batch's loads
-// issued before this batch's adds, rows past a list's end clamped to the
-// tile's first row instead of branching, so no load waits on another.  The
-// adds are LDS atomics without return, which the wave issues, and the LDS
-// executes, in program order; the groups of one instruction hold different
-// labels, so every sum has a fixed order and nothing waits on the results.
-template <int D8, int TILE>
-__device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, int d, const int (&lab)[TILE / 64],
+// "process": add the samples of a step (at most STEP of them: one or more
+// tiles) that this wave owns to the block's activation record, in increasing
+// sample order.  lab[g] is the label of sample g * 64 + lane of the step (-1:
+// none, or another chunk's); row_of(pos) is the row of sample pos; the lists
+// hold cap entries per buffer (the step's samples).  A row takes LPR
+// lanes (lane f carries feature f: coalesced), so a wave holds NG = 64 / LPR
+// row groups; label class c = L mod (4 NG) belongs to wave c / NG, row group
+// c % NG.  Each group lists (and counts) its samples in LDS, two groups
+// sharing a buffer from its two ends; then BG rows per group at a time are
+// loaded, the next batch's loads issued before this batch's adds, rows past
+// a list's end clamped to the step's first row instead of branching, so no
+// load waits on another.  The adds are LDS atomics without return, which the
+// wave issues, and the LDS executes, in program order; the groups of one
+// instruction hold different labels, so every sum has a fixed order and
+// nothing waits on the results.
+template <int D8, int STEP, typename RowOf>
+__device__ __forceinline__ void accumulate_step(RowOf row_of, int d, const int (&lab)[STEP / 64], int cap,
                                                 int32_t* wl, double* S, int32_t* cnt, int lane, int wave)
 {
     constexpr int LPR = row_lanes(D8);                          // lanes per row
@@ -54,11 +57,14 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
     constexpr int FPL = (8 * D8 + LPR - 1) / LPR;               // features per lane
     constexpr int BG = NG > 1 ? LPR : (FPL == 1 ? 32 : 16);     // rows per group per batch
     static_assert(NG * BG <= 64, "one entry per lane");
+    static_assert(STEP <= 4096, "12-bit step offsets");
+    // slot i of group s's list (buffers of cap entries: the samples a step can hold)
+    auto slot = [cap](int s, int i) { return (s >> 1) * cap + ((s & 1) ? cap - 1 - i : i); };
     int nown[NG];
 #pragma unroll
     for (int s = 0; s < NG; ++s) nown[s] = 0;
 #pragma unroll
-    for (int g = 0; g < TILE / 64; ++g) {
+    for (int g = 0; g < STEP / 64; ++g) {
         const int L = lab[g];
         const int c = L & (kWaves * NG - 1);
         const bool own = L >= 0 && c / NG == wave;
@@ -67,9 +73,9 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
             const bool mine = own && c % NG == s;
             const uint64_t mask = __ballot(mine);
             if (mine) {
-                wl[s * TILE + nown[s] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
-                    ((L * d) << 12) | (g * 64 + lane);   // record offset of the row (< 2^19), offset in the tile
+                wl[slot(s, nown[s] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u)))] =
+                    ((L * d) << 12) | (g * 64 + lane);   // record offset of the row (< 2^19), offset in the step
                 // counts are integers: any order of these adds gives the same total
                 __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
@@ -91,7 +97,7 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
     for (int s = 1; s < NG; ++s) qn = qs == s ? nown[s] : qn;
     auto entries = [&](int b) {
         const int i = b * BG + qu;
-        return (qs < NG && i < qn) ? wl[qs * TILE + i] : -1;
+        return (qs < NG && i < qn) ? wl[slot(qs, i)] : -1;
     };
     // this lane's group's entry of row u
     auto row_entry = [&](int q, int u) {
@@ -111,7 +117,7 @@ __device__ __forceinline__ void accumulate_tile(const float* __restrict__ Xt, in
 #pragma unroll
         for (int u = 0; u < BG; ++u) {
             const int e = row_entry(q, u);
-            const float* row = Xt + (int64_t)(e >= 0 ? (e & 4095) : 0) * d;
+            const float* row = row_of(e >= 0 ? (e & 4095) : 0);
 #pragma unroll
             for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
         }
@@ -187,8 +193,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
 
     double* S = reinterpret_cast<double*>(smem);
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
-    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [2][TILE] labels of a tile (fused)
-    int32_t* wlist = lbl + 2 * TILE;                           // [kWaves][row groups][TILE] owned samples
+    int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // fused: [2][TILE] labels of a tile
+    int32_t* wlist = FUSED ? lbl + 2 * TILE : lbl;             // [kWaves][list buffers][step] owned samples
 
     // "alloc": zero the block's activation record
     if (MODE != MODE_ASSIGN) {
@@ -245,44 +251,57 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
             int lt[TILE / 64];
 #pragma unroll
             for (int g = 0; g < TILE / 64; ++g) lt[g] = lb[g * 64 + lane];
-            accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lt, wlist + wave * row_groups(D8) * TILE, S, cnt, lane, wave);
+            const float* Xt = a.X + t * TILE * (int64_t)d;
+            accumulate_step<D8, TILE>([&](int pos) { return Xt + pos * d; }, d, lt, TILE,
+                                      wlist + wave * list_bufs(D8) * TILE, S, cnt, lane, wave);
         }
-    } else {
-        // labels of a tile for the update pass (INT_MIN: past the last sample)
-        int Ln[TILE / 64];
-        auto load_labels = [&](int64_t t, int (&Lv)[TILE / 64]) {
+    } else if constexpr (UPD) {
+        // steps of ut of the block's tiles: every wave reads the whole
+        // step's labels (INT_MIN: past the last sample), the next step's in
+        // flight while this one is added; wave w counts the invalid labels of
+        // row group w of each tile
+        constexpr int NL = kUpdTiles * TILE / 64;
+        const int ut = a.upd_tiles;
+        const int64_t nsteps = (nmine + ut - 1) / ut;
+        auto tile_of = [&](int64_t st, int j) { return t_first + (st * ut + j) * t_step; };
+        auto load_labels = [&](int64_t st, int (&Lv)[NL]) {
 #pragma unroll
-            for (int g = 0; g < TILE / 64; ++g) {
-                const int64_t gp = t * TILE + g * 64 + lane;
-                Lv[g] = gp < n ? a.labels[gp] : INT_MIN;
-            }
-        };
-        if (UPD && nmine > 0) load_labels(t_first, Ln);
-        for (int64_t i = 0; i < nmine; ++i) {
-            const int64_t t = t_first + i * t_step;
-            // lane holds samples t*TILE + r*256 + tid, r < R
-            if (UPD) {
-                // every wave reads the whole tile's labels (the next tile's
-                // are in flight while this one is added); wave g counts the
-                // invalid labels of row group g
-                int L[TILE / 64];
-#pragma unroll
-                for (int g = 0; g < TILE / 64; ++g) L[g] = Ln[g];
-                if (i + 1 < nmine) load_labels(t + t_step, Ln);
-                int lab[TILE / 64];
+            for (int j = 0; j < kUpdTiles; ++j) {
+                const bool in = j < ut && st * ut + j < nmine;
 #pragma unroll
                 for (int g = 0; g < TILE / 64; ++g) {
-                    lab[g] = -1;
-                    if (L[g] != INT_MIN) {
-                        if (L[g] < 0 || L[g] >= k) bad += (g == wave);
-                        else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
-                    }
+                    const int64_t gp = tile_of(st, j) * TILE + g * 64 + lane;
+                    Lv[j * (TILE / 64) + g] = (in && gp < n) ? a.labels[gp] : INT_MIN;
                 }
-                accumulate_tile<D8, TILE>(a.X + t * TILE * (int64_t)d, d, lab, wlist + wave * row_groups(D8) * TILE, S, cnt, lane, wave);
-            } else {
-                int lab[R];
-                assign_tile(t, lab);
             }
+        };
+        int Ln[NL];
+        if (nsteps > 0) load_labels(0, Ln);
+        for (int64_t st = 0; st < nsteps; ++st) {
+            int L[NL];
+#pragma unroll
+            for (int g = 0; g < NL; ++g) L[g] = Ln[g];
+            if (st + 1 < nsteps) load_labels(st + 1, Ln);
+            int lab[NL];
+#pragma unroll
+            for (int g = 0; g < NL; ++g) {
+                lab[g] = -1;
+                if (L[g] != INT_MIN) {
+                    if (L[g] < 0 || L[g] >= k) bad += ((g % (TILE / 64)) == wave);
+                    else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
+                }
+            }
+            // tile j of the step starts j * t_step tiles after its first
+            const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)d;
+            const int64_t tstride = t_step * TILE * (int64_t)d;
+            auto row_of = [&](int pos) { return Xs + ((pos / TILE) * tstride + (pos % TILE) * d); };
+            accumulate_step<D8, kUpdTiles * TILE>(row_of, d, lab, ut * TILE,
+                                                  wlist + wave * list_bufs(D8) * ut * TILE, S, cnt, lane, wave);
+        }
+    } else {
+        for (int64_t i = 0; i < nmine; ++i) {
+            int lab[R];
+            assign_tile(t_first + i * t_step, lab);
         }
     }
 
@@ -351,9 +370,10 @@ void batch_pass(const BatchWork* __restrict__ work,
 // chunk counts, their prefix, then each 64-sample group's lanes placed chunk
 // by chunk in lane order), and the chunk blocks read just their samples.
 __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict__ labels, int64_t n, int32_t k,
-                                                       int32_t kc, int32_t nch, int32_t* perm, int32_t* poff,
-                                                       int32_t* pcnt, const Ctrl* ctrl, int32_t iter)
+                                                       int32_t kc, int32_t nch, int32_t* perm, int32_t* plab,
+                                                       int32_t* poff, int32_t* pcnt, const Ctrl* ctrl, int32_t iter)
 {
+    constexpr int G = kPartRows / 64;                     // 64-sample groups of a sub-range
     extern __shared__ __align__(16) unsigned char smem[];
     if (ctrl != nullptr && ctrl->stop_iter < iter) return;  // converged earlier
     int32_t* cnt = reinterpret_cast<int32_t*>(smem);     // [nch]
@@ -362,12 +382,19 @@ __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict
     const int64_t base = (int64_t)blockIdx.x * kPartRows;
     const int64_t end = base + kPartRows < n ? base + kPartRows : n;
     for (int c = lane; c < nch; c += 64) cnt[c] = 0;
-    __syncthreads();
-    for (int64_t g = base; g < end; g += 64) {
-        const int64_t i = g + lane;
-        const int L = i < end ? labels[i] : -1;
-        if (L >= 0 && L < k) __hip_atomic_fetch_add(cnt + L / kc, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // every label of the sub-range in registers (all loads in flight at once)
+    int lb[G], ch[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t i = base + g * 64 + lane;
+        lb[g] = i < end ? labels[i] : -1;
     }
+#pragma unroll
+    for (int g = 0; g < G; ++g) ch[g] = (lb[g] >= 0 && lb[g] < k) ? lb[g] / kc : -1;
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (ch[g] >= 0) __hip_atomic_fetch_add(cnt + ch[g], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
     int carry = 0;
     for (int c0 = 0; c0 < nch; c0 += 64) {
@@ -388,19 +415,25 @@ __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict
         carry += __shfl(incl, 63);
     }
     __syncthreads();
+    // scatter in sample order: a lane's slot is its chunk's cursor plus the
+    // number of lower lanes of the group in the same chunk
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (int64_t g = base; g < end; g += 64) {
-        const int64_t i = g + lane;
-        const int L = i < end ? labels[i] : -1;
-        const int c = (L >= 0 && L < k) ? L / kc : -1;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int c = ch[g];
+        const int at = c >= 0 ? cur[c] : 0;
+        int rank = 0, num = 0;
         uint64_t rem = __ballot(c >= 0);
         while (rem) {
             const int cx = __builtin_amdgcn_readlane(c, (int)__builtin_ctzll(rem));
             const uint64_t m = __ballot(c == cx);
-            const int at = cur[cx];
-            if (c == cx) perm[at + (int)__popcll(m & lt)] = (int32_t)i;
-            if (lane == (int)__builtin_ctzll(m)) cur[cx] = at + (int)__popcll(m);
+            if (c == cx) { rank = (int)__popcll(m & lt); num = (int)__popcll(m); }
             rem &= ~m;
+        }
+        if (c >= 0) {
+            perm[at + rank] = (int32_t)(base + g * 64 + lane);
+            plab[at + rank] = lb[g];
+            if (rank == 0) cur[c] = at + num;    // the chunk's first lane advances its cursor
         }
     }
 }
@@ -409,11 +442,16 @@ __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict
 // wave w adds the samples whose chunk-local label is congruent to w mod 4,
 // in sample order (sub-range, then list order), by LDS atomics in program
 // order; the record goes to partial slot x like the other update passes.
+// The block's entries (sample, label) are walked kPartStep at a time, the
+// next step's entries in flight while this step's rows are added, and the
+// rows in batches of B with the next batch's loads issued first.
+constexpr int kPartStep = 256;
 template <int D8>
 __global__ __launch_bounds__(kBlock) void part_update_kernel(PassArgs a)
 {
     constexpr int FPL = (8 * D8 + 63) / 64;
     constexpr int B = FPL == 1 ? 32 : 16;
+    constexpr int Q = kPartStep / 64;
     extern __shared__ __align__(16) unsigned char smem[];
     if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;  // converged earlier
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -423,60 +461,100 @@ __global__ __launch_bounds__(kBlock) void part_update_kernel(PassArgs a)
     const int kc = min(a.kc, k - j0);
     double* S = reinterpret_cast<double*>(smem);
     int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
-    int32_t* wrow = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [kWaves][64] owned sample indices
-    int32_t* woff = wrow + kWaves * 64;                        // [kWaves][64] their record offsets
+    int32_t* wrow = cnt + (((size_t)kc + 3) & ~(size_t)3);     // [kWaves][kPartStep] owned sample indices
+    int32_t* woff = wrow + kWaves * kPartStep;                 // [kWaves][kPartStep] their record offsets
     for (int e = tid; e < kc * d; e += kBlock) S[e] = 0.0;
     for (int j = tid; j < kc; j += kBlock) cnt[j] = 0;
     __syncthreads();
-    int32_t* wr = wrow + wave * 64;
-    int32_t* wo = woff + wave * 64;
+    int32_t* wr = wrow + wave * kPartStep;
+    int32_t* wo = woff + wave * kPartStep;
     int fc[FPL];
 #pragma unroll
     for (int m = 0; m < FPL; ++m) fc[m] = min(lane + 64 * m, d - 1);
     const uint64_t lt = (1ull << lane) - 1ull;
-    const int s0 = (int)((int64_t)blockIdx.x * a.nsub / gridDim.x);
     const int s1 = (int)((int64_t)(blockIdx.x + 1) * a.nsub / gridDim.x);
-    for (int sr = s0; sr < s1; ++sr) {
-        const int start = a.poff[(int64_t)sr * a.nch + y];
-        const int num = a.pcnt[(int64_t)sr * a.nch + y];
-        for (int q0 = 0; q0 < num; q0 += 64) {
-            const int e = q0 + lane < num ? a.perm[start + q0 + lane] : -1;
-            const int L = e >= 0 ? a.labels[e] - j0 : -1;
-            const bool own = e >= 0 && (L & (kWaves - 1)) == wave;
+    // step cursor: sub-range sr, entries [q0, q0 + kPartStep) of its run of this chunk
+    int sr = (int)((int64_t)blockIdx.x * a.nsub / gridDim.x);
+    int q0 = 0, start = 0, num = 0;
+    if (sr < s1) { start = a.poff[(int64_t)sr * a.nch + y]; num = a.pcnt[(int64_t)sr * a.nch + y]; }
+    auto fetch = [&](int st, int nm, int q, int (&E)[Q], int (&L)[Q]) {
+#pragma unroll
+        for (int g = 0; g < Q; ++g) {
+            const int i = q + g * 64 + lane;
+            E[g] = i < nm ? a.perm[st + i] : -1;
+            L[g] = i < nm ? a.plab[st + i] - j0 : -1;
+        }
+    };
+    int E[Q], L[Q];
+    fetch(start, num, 0, E, L);
+    float v0[B][FPL], v1[B][FPL];
+    while (sr < s1) {
+        // the next step: the rest of this run, else the next non-empty sub-range
+        int nsr = sr, nq0 = q0 + kPartStep, nstart = start, nnum = num;
+        if (nq0 >= num) {
+            nq0 = 0;
+            nnum = 0;
+            while (nnum == 0 && ++nsr < s1) {
+                nstart = a.poff[(int64_t)nsr * a.nch + y];
+                nnum = a.pcnt[(int64_t)nsr * a.nch + y];
+            }
+        }
+        int En[Q], Ln[Q];
+        fetch(nstart, nnum, nq0, En, Ln);
+        // this step's owned entries, in order
+        int nown = 0;
+#pragma unroll
+        for (int g = 0; g < Q; ++g) {
+            const bool own = E[g] >= 0 && (L[g] & (kWaves - 1)) == wave;
             const uint64_t mask = __ballot(own);
             if (own) {
-                const int at = (int)__popcll(mask & lt);
-                wr[at] = e;
-                wo[at] = L * d;
-                __hip_atomic_fetch_add(cnt + L, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int at = nown + (int)__popcll(mask & lt);
+                wr[at] = E[g];
+                wo[at] = L[g] * d;
+                __hip_atomic_fetch_add(cnt + L[g], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            const int nown = (int)__popcll(mask);
-            for (int i0 = 0; i0 < nown; i0 += B) {
-                const int row_i = (lane < B && i0 + lane < nown) ? wr[i0 + lane] : -1;
-                const int off_i = (lane < B && i0 + lane < nown) ? wo[i0 + lane] : -1;
-                const int first = __builtin_amdgcn_readfirstlane(row_i);     // entry i0: always valid
-                float v[B][FPL];
+            nown += (int)__popcll(mask);
+        }
+        int r0 = -1, o0 = -1, r1 = -1, o1 = -1;
+        auto load = [&](int b, float (&v)[B][FPL], int& ri, int& oi) {
+            ri = (lane < B && b * B + lane < nown) ? wr[b * B + lane] : -1;
+            oi = (lane < B && b * B + lane < nown) ? wo[b * B + lane] : -1;
+            const int first = __builtin_amdgcn_readfirstlane(ri);   // entry b*B: always valid
 #pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    int r = __builtin_amdgcn_readlane(row_i, u);
-                    r = r >= 0 ? r : first;
-                    const float* row = a.X + (int64_t)r * d;
+            for (int u = 0; u < B; ++u) {
+                int r = __builtin_amdgcn_readlane(ri, u);
+                r = r >= 0 ? r : first;
+                const float* row = a.X + (int64_t)r * d;
 #pragma unroll
-                    for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
-                }
+                for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
+            }
+        };
+        auto add = [&](const float (&v)[B][FPL], int oi) {
 #pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    const int o = __builtin_amdgcn_readlane(off_i, u);
-                    if (o >= 0) {
+            for (int u = 0; u < B; ++u) {
+                const int o = __builtin_amdgcn_readlane(oi, u);
+                if (o >= 0) {
 #pragma unroll
-                        for (int m = 0; m < FPL; ++m) {
-                            const int f = lane + 64 * m;
-                            if (f < d) lds_add_f64(S + o + f, (double)v[u][m]);
-                        }
+                    for (int m = 0; m < FPL; ++m) {
+                        const int f = lane + 64 * m;
+                        if (f < d) lds_add_f64(S + o + f, (double)v[u][m]);
                     }
                 }
             }
+        };
+        const int nbat = (nown + B - 1) / B;
+        if (nbat > 0) load(0, v0, r0, o0);
+        for (int b = 0; b < nbat; b += 2) {
+            if (b + 1 < nbat) load(b + 1, v1, r1, o1);
+            add(v0, o0);
+            if (b + 1 < nbat) {
+                if (b + 2 < nbat) load(b + 2, v0, r0, o0);
+                add(v1, o1);
+            }
         }
+#pragma unroll
+        for (int g = 0; g < Q; ++g) { E[g] = En[g]; L[g] = Ln[g]; }
+        sr = nsr; q0 = nq0; start = nstart; num = nnum;
     }
     __syncthreads();
     const int b = blockIdx.x;
@@ -489,10 +567,11 @@ __global__ __launch_bounds__(kBlock) void part_update_kernel(PassArgs a)
 size_t part_update_lds_bytes(int kc, int d)
 {
     return (size_t)kc * d * sizeof(double) + (((size_t)kc * sizeof(int32_t) + 15) & ~(size_t)15) +
-           2 * kWaves * 64 * sizeof(int32_t);
+           2 * kWaves * kPartStep * sizeof(int32_t);
 }
 
-hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* poff, int32_t* pcnt, hipStream_t s)
+hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* plab, int32_t* poff, int32_t* pcnt,
+                            hipStream_t s)
 {
     const size_t lds = 2 * (size_t)a.nch * sizeof(int32_t);
     if (lds > 64 * 1024) {
@@ -501,7 +580,7 @@ hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* poff, int
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(partition_kernel, dim3(a.nsub), dim3(64), lds, s, a.labels, a.n, a.k, a.kc, a.nch, perm,
-                       poff, pcnt, a.ctrl, a.iter);
+                       plab, poff, pcnt, a.ctrl, a.iter);
     return hipGetLastError();
 }
 
