@@ -24,6 +24,7 @@
 #include "km_dist.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace km {
 
@@ -256,48 +257,54 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
                                       wlist + wave * list_bufs(D8) * TILE, S, cnt, lane, wave);
         }
     } else if constexpr (UPD) {
-        // steps of ut of the block's tiles: every wave reads the whole
-        // step's labels (INT_MIN: past the last sample), the next step's in
-        // flight while this one is added; wave w counts the invalid labels of
-        // row group w of each tile
-        constexpr int NL = kUpdTiles * TILE / 64;
-        const int ut = a.upd_tiles;
-        const int64_t nsteps = (nmine + ut - 1) / ut;
-        auto tile_of = [&](int64_t st, int j) { return t_first + (st * ut + j) * t_step; };
-        auto load_labels = [&](int64_t st, int (&Lv)[NL]) {
+        // steps of UT of the block's tiles: every wave reads the whole step's
+        // labels (INT_MIN: past the last sample), the next step's in flight
+        // while this one is added; wave w counts the invalid labels of row
+        // group w of each tile
+        auto steps = [&](auto ut_c) {
+            constexpr int UT = decltype(ut_c)::value;
+            constexpr int NL = UT * TILE / 64;
+            const int64_t nsteps = (nmine + UT - 1) / UT;
+            auto tile_of = [&](int64_t st, int j) { return t_first + (st * UT + j) * t_step; };
+            auto load_labels = [&](int64_t st, int (&Lv)[NL]) {
 #pragma unroll
-            for (int j = 0; j < kUpdTiles; ++j) {
-                const bool in = j < ut && st * ut + j < nmine;
+                for (int j = 0; j < UT; ++j) {
+                    const bool in = st * UT + j < nmine;
 #pragma unroll
-                for (int g = 0; g < TILE / 64; ++g) {
-                    const int64_t gp = tile_of(st, j) * TILE + g * 64 + lane;
-                    Lv[j * (TILE / 64) + g] = (in && gp < n) ? a.labels[gp] : INT_MIN;
+                    for (int g = 0; g < TILE / 64; ++g) {
+                        const int64_t gp = tile_of(st, j) * TILE + g * 64 + lane;
+                        Lv[j * (TILE / 64) + g] = (in && gp < n) ? a.labels[gp] : INT_MIN;
+                    }
                 }
+            };
+            int Ln[NL];
+            if (nsteps > 0) load_labels(0, Ln);
+            for (int64_t st = 0; st < nsteps; ++st) {
+                int L[NL];
+#pragma unroll
+                for (int g = 0; g < NL; ++g) L[g] = Ln[g];
+                if (st + 1 < nsteps) load_labels(st + 1, Ln);
+                int lab[NL];
+#pragma unroll
+                for (int g = 0; g < NL; ++g) {
+                    lab[g] = -1;
+                    if (L[g] != INT_MIN) {
+                        if (L[g] < 0 || L[g] >= k) bad += ((g % (TILE / 64)) == wave);
+                        else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
+                    }
+                }
+                // tile j of the step starts j * t_step tiles after its first
+                const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)d;
+                const int64_t tstride = t_step * TILE * (int64_t)d;
+                auto row_of = [&](int pos) {
+                    return UT == 1 ? Xs + pos * d : Xs + ((pos / TILE) * tstride + (pos % TILE) * d);
+                };
+                accumulate_step<D8, UT * TILE>(row_of, d, lab, UT * TILE, wlist + wave * list_bufs(D8) * UT * TILE,
+                                               S, cnt, lane, wave);
             }
         };
-        int Ln[NL];
-        if (nsteps > 0) load_labels(0, Ln);
-        for (int64_t st = 0; st < nsteps; ++st) {
-            int L[NL];
-#pragma unroll
-            for (int g = 0; g < NL; ++g) L[g] = Ln[g];
-            if (st + 1 < nsteps) load_labels(st + 1, Ln);
-            int lab[NL];
-#pragma unroll
-            for (int g = 0; g < NL; ++g) {
-                lab[g] = -1;
-                if (L[g] != INT_MIN) {
-                    if (L[g] < 0 || L[g] >= k) bad += ((g % (TILE / 64)) == wave);
-                    else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
-                }
-            }
-            // tile j of the step starts j * t_step tiles after its first
-            const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)d;
-            const int64_t tstride = t_step * TILE * (int64_t)d;
-            auto row_of = [&](int pos) { return Xs + ((pos / TILE) * tstride + (pos % TILE) * d); };
-            accumulate_step<D8, kUpdTiles * TILE>(row_of, d, lab, ut * TILE,
-                                                  wlist + wave * list_bufs(D8) * ut * TILE, S, cnt, lane, wave);
-        }
+        if (a.upd_tiles == kUpdTiles) steps(std::integral_constant<int, kUpdTiles>());
+        else steps(std::integral_constant<int, 1>());
     } else {
         for (int64_t i = 0; i < nmine; ++i) {
             int lab[R];
