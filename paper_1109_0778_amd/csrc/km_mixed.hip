@@ -919,8 +919,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     }
 }
 
+// The screen is built for three resident waves per SIMD (its 64 samples per
+// wave hold 64 VGPRs of operands for the whole sweep).
 template <int D16, int FMT, int STAGE>
-__global__ __launch_bounds__(64 * kMixWaves) void mfma_assign(MixArgs a)
+__global__ __launch_bounds__(64 * kMixWaves) __attribute__((amdgpu_waves_per_eu(STAGE == 1 ? 3 : 1)))
+void mfma_assign(MixArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     if constexpr (STAGE == 2)
