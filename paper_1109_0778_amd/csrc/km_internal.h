@@ -55,7 +55,8 @@ struct PassArgs {
     int32_t iter;         // Lloyd iteration index (0 outside kmeans_lloyd)
     int32_t count_changed;// assign passes: count labels that differ from the stored ones
     int32_t kc;           // update passes: labels per chunk; block y owns labels [y*kc, y*kc+kc)
-    int32_t upd_tiles;    // update pass: tiles listed and added per step (1 .. kUpdTiles)
+    int32_t upd_tiles;    // update pass: tiles listed and added per step (1 .. kUpdTiles); above 1 each
+                          // block walks a contiguous range of tiles
     // partitioned chunk update: sample indices grouped by label chunk within
     // each kPartRows-sample sub-range, in sample order
     const int32_t* perm;  // [n]
@@ -153,7 +154,7 @@ inline size_t plain_lds_bytes(int k, int d, Mode mode, int upd_tiles = kUpdTiles
 {
     size_t b = 0;
     if (mode != MODE_ASSIGN) {
-        b += (size_t)k * (size_t)d * sizeof(double);
+        b += ((size_t)k * (size_t)d + 1) / 2 * 2 * sizeof(double);   // the lists start 16-byte aligned
         b += ((size_t)k * sizeof(int32_t) + 15) & ~(size_t)15;
         // fused: labels of a tile, double-buffered, and each wave's owned
         // samples of a tile; update: each wave's owned samples of a step

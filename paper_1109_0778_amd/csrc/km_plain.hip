@@ -56,7 +56,7 @@ __device__ __forceinline__ void accumulate_step(RowOf row_of, int d, const int (
     constexpr int LPR = row_lanes(D8);                          // lanes per row
     constexpr int NG = 64 / LPR;                                // row groups per wave
     constexpr int FPL = (8 * D8 + LPR - 1) / LPR;               // features per lane
-    constexpr int BG = NG > 1 ? LPR : (FPL == 1 ? 32 : 16);     // rows per group per batch
+    constexpr int BG = NG > 1 ? 16 : (FPL == 1 ? 32 : 16);      // rows per group per batch
     static_assert(NG * BG <= 64, "one entry per lane");
     static_assert(STEP <= 4096, "12-bit step offsets");
     // slot i of group s's list (buffers of cap entries: the samples a step can hold)
@@ -91,45 +91,66 @@ __device__ __forceinline__ void accumulate_step(RowOf row_of, int d, const int (
     int nmax = nown[0], nmin = nown[0];
 #pragma unroll
     for (int s = 1; s < NG; ++s) { nmax = max(nmax, nown[s]); nmin = min(nmin, nown[s]); }
-    // lane s * BG + u holds row u of group s's batch (-1: past the list)
-    const int qs = lane / BG, qu = lane % BG;
-    int qn = nown[0];
-#pragma unroll
-    for (int s = 1; s < NG; ++s) qn = qs == s ? nown[s] : qn;
-    auto entries = [&](int b) {
-        const int i = b * BG + qu;
-        return (qs < NG && i < qn) ? wl[slot(qs, i)] : -1;
-    };
-    // this lane's group's entry of row u
-    auto row_entry = [&](int q, int u) {
-        int e = __builtin_amdgcn_readlane(q, u);
-#pragma unroll
-        for (int s = 1; s < NG; ++s) {
-            const int es = __builtin_amdgcn_readlane(q, s * BG + u);
-            e = h == s ? es : e;
-        }
-        return e;
-    };
     const int nbat = (nmax + BG - 1) / BG;
     float v0[BG][FPL], v1[BG][FPL];
     int q0 = -1, q1 = -1;
+    // The entry of row u of batch b for this lane's group.  One group: lane
+    // u holds it and a readlane broadcasts it.  Several groups: each lane
+    // reads its group's entries from the list, four per LDS read (an odd
+    // group's list runs backwards from the end of its buffer); entries past
+    // the group's list read as -1.
+    int nh = nown[0];
+#pragma unroll
+    for (int s = 1; s < NG; ++s) nh = h == s ? nown[s] : nh;
+    auto entries = [&](int b) {
+        if constexpr (NG == 1) {
+            const int i = b * BG + lane;
+            return (lane < BG && i < nown[0]) ? wl[i] : -1;
+        } else {
+            return 0;
+        }
+    };
+    auto batch_entries = [&](int b, int q, int (&e)[BG]) {
+        if constexpr (NG == 1) {
+#pragma unroll
+            for (int u = 0; u < BG; ++u) e[u] = __builtin_amdgcn_readlane(q, u);
+        } else {
+            const int i0 = b * BG;
+#pragma unroll
+            for (int u = 0; u < BG; u += 4) {
+                const int4 v = *reinterpret_cast<const int4*>(wl + ((h & 1) ? slot(h, i0 + u + 3) : slot(h, i0 + u)));
+                const bool rev = h & 1;
+                e[u + 0] = rev ? v.w : v.x;
+                e[u + 1] = rev ? v.z : v.y;
+                e[u + 2] = rev ? v.y : v.z;
+                e[u + 3] = rev ? v.x : v.w;
+            }
+            if (i0 + BG > nh) {
+#pragma unroll
+                for (int u = 0; u < BG; ++u) e[u] = i0 + u < nh ? e[u] : -1;
+            }
+        }
+    };
     auto load = [&](int b, float (&v)[BG][FPL], int& q) {
         q = entries(b);
+        int e[BG];
+        batch_entries(b, q, e);
+        const int first = NG == 1 ? e[0] : 0;     // entry 0 of a one-group batch is valid
 #pragma unroll
         for (int u = 0; u < BG; ++u) {
-            const int e = row_entry(q, u);
-            const float* row = row_of(e >= 0 ? (e & 4095) : 0);
+            const float* row = row_of(e[u] >= 0 ? (e[u] & 4095) : (NG == 1 ? (first & 4095) : 0));
 #pragma unroll
             for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
         }
     };
     auto add = [&](int b, const float (&v)[BG][FPL], int q) {
         const bool full = b * BG + BG <= nmin;   // every group has all BG rows: no per-row test
+        int e[BG];
+        batch_entries(b, q, e);
 #pragma unroll
         for (int u = 0; u < BG; ++u) {
-            const int e = row_entry(q, u);
-            if (full || e >= 0) {
-                double* srow = S + (e >> 12);
+            if (full || e[u] >= 0) {
+                double* srow = S + (e[u] >> 12);
 #pragma unroll
                 for (int m = 0; m < FPL; ++m) {
                     const int f = fl + LPR * m;
@@ -193,7 +214,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     const int kc = UPD ? min(a.kc, k - j0) : k;
 
     double* S = reinterpret_cast<double*>(smem);
-    int32_t* cnt = reinterpret_cast<int32_t*>(S + (size_t)kc * d);
+    int32_t* cnt = reinterpret_cast<int32_t*>(S + ((size_t)kc * d + 1) / 2 * 2);   // 16-byte aligned
     int32_t* lbl = cnt + (((size_t)kc + 3) & ~(size_t)3);     // fused: [2][TILE] labels of a tile
     int32_t* wlist = FUSED ? lbl + 2 * TILE : lbl;             // [kWaves][list buffers][step] owned samples
 
@@ -293,17 +314,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
                         else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
                     }
                 }
-                // tile j of the step starts j * t_step tiles after its first
+                // the step's samples are consecutive (one tile, or contiguous tiles)
                 const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)d;
-                const int64_t tstride = t_step * TILE * (int64_t)d;
-                auto row_of = [&](int pos) {
-                    return UT == 1 ? Xs + pos * d : Xs + ((pos / TILE) * tstride + (pos % TILE) * d);
-                };
+                auto row_of = [&](int pos) { return Xs + pos * d; };
                 accumulate_step<D8, UT * TILE>(row_of, d, lab, UT * TILE, wlist + wave * list_bufs(D8) * UT * TILE,
                                                S, cnt, lane, wave);
             }
         };
-        if (a.upd_tiles == kUpdTiles) steps(std::integral_constant<int, kUpdTiles>());
+        if (a.upd_tiles == kUpdTiles && t_step == 1) steps(std::integral_constant<int, kUpdTiles>());
         else steps(std::integral_constant<int, 1>());
     } else {
         for (int64_t i = 0; i < nmine; ++i) {
@@ -353,7 +371,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_min
 void plain_pass(PassArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    pass_body<D8, MODE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, blockIdx.y, smem);
+    if (MODE == MODE_UPDATE && a.upd_tiles > 1) {
+        // a stand-alone update: block b walks tiles [b T / G, (b + 1) T / G)
+        const int64_t nt = (a.n + kBlock - 1) / kBlock;
+        pass_body<D8, MODE>(a, (int64_t)blockIdx.x * nt / gridDim.x, (int64_t)(blockIdx.x + 1) * nt / gridDim.x, 1,
+                            blockIdx.x, blockIdx.y, smem);
+    } else {
+        pass_body<D8, MODE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, blockIdx.y, smem);
+    }
 }
 
 // Batched instances: block b runs tiles [t0, t1) of instance work[b].inst into
