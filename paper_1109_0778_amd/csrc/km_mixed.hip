@@ -955,6 +955,19 @@ __global__ __launch_bounds__(64 * kMixWaves) void batch_mfma(const BatchWork* __
 // distance is bit-identical to the FP32 path's.  The winner is the
 // lexicographic (distance, index) minimum over the candidates; entries
 // flagged -1 scan all k centroids in index order.
+// One level of the canonical pairwise tree over the lanes of a sample (lane
+// q holds chunk q's partial): lanes q with q % 2S == 0 and q + S < D8 add the
+// partial of lane q + S, fetched with a DPP row shift.
+template <int S, int D8>
+__device__ __forceinline__ void tree_level(float& part, int q)
+{
+    if constexpr (S < D8) {
+        const float other = __builtin_bit_cast(
+            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, part), 0x100 + S, 0xf, 0xf, false));
+        if ((q % (2 * S)) == 0 && q + S < D8) part = part + other;
+    }
+}
+
 template <int D8>
 __device__ __forceinline__ void recheck_body(const RecheckArgs& a, int region, int y, int ny)
 {
@@ -967,7 +980,6 @@ __device__ __forceinline__ void recheck_body(const RecheckArgs& a, int region, i
     const int lane = tid & 63;
     const int q = lane % GS;
     const int grp = lane / GS;
-    const int leader = lane - q;
     // ny blocks re-check the entries of one queue region, block y taking
     // every ny-th group of waves
     const int count = a.rq_count[region];
@@ -988,11 +1000,20 @@ __device__ __forceinline__ void recheck_body(const RecheckArgs& a, int region, i
         float x[8];
         {
             const float* xr = a.X + p * a.d;
+            if ((a.d & 7) == 0) {
+                // every lane's eight features lie inside the row: two vector loads
+                const float4 v0 = *reinterpret_cast<const float4*>(xr + 8 * qc);
+                const float4 v1 = *reinterpret_cast<const float4*>(xr + 8 * qc + 4);
+                const bool in = q < D8;
+                x[0] = in ? v0.x : 0.0f; x[1] = in ? v0.y : 0.0f; x[2] = in ? v0.z : 0.0f; x[3] = in ? v0.w : 0.0f;
+                x[4] = in ? v1.x : 0.0f; x[5] = in ? v1.y : 0.0f; x[6] = in ? v1.z : 0.0f; x[7] = in ? v1.w : 0.0f;
+            } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int f = 8 * qc + i;
-                const float v = xr[f < a.d ? f : a.d - 1];
-                x[i] = (q < D8 && f < a.d) ? v : 0.0f;
+                for (int i = 0; i < 8; ++i) {
+                    const int f = 8 * qc + i;
+                    const float v = xr[f < a.d ? f : a.d - 1];
+                    x[i] = (q < D8 && f < a.d) ? v : 0.0f;
+                }
             }
         }
         // trip count: the longest candidate list of the wave
@@ -1032,12 +1053,15 @@ __device__ __forceinline__ void recheck_body(const RecheckArgs& a, int region, i
                     const float df = x[i] - (q < D8 ? cv[u][i] : 0.0f);
                     part = __builtin_fmaf(df, df, part);
                 }
-#pragma unroll
-                for (int s = 1; s < D8; s *= 2) {
-                    const float other = __shfl(part, lane + s < 64 ? lane + s : lane);
-                    if ((q % (2 * s)) == 0 && q + s < D8) part = part + other;
-                }
-                const float dist = __shfl(part, leader);
+                // the chunk partials' pairwise tree across the sample's lanes
+                // (lane q adds lane q + s; DPP row shifts stay inside a
+                // 16-lane row, which holds whole samples); the distance is
+                // complete in the sample's first lane, the only one that uses it
+                tree_level<1, D8>(part, q);
+                tree_level<2, D8>(part, q);
+                tree_level<4, D8>(part, q);
+                tree_level<8, D8>(part, q);
+                const float dist = part;
                 const int j = jj[u];
                 if (j >= 0 && (dist < best || (dist == best && j < bj))) { best = dist; bj = j; }
             }
