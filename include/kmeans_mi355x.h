@@ -53,7 +53,8 @@
  * centroids; the objective comes from the FP64 per-label sums through
  * J = sum_i |x_i|^2 + sum_j (cnt_j |c_j|^2 - 2 c_j . S_j).  FP8 scales each
  * feature by a power of two s_f >= max_i |x_if| / 448 (exact) and keeps an
- * e4m3 copy of X in the workspace, made once per call; d <= 128 and
+ * e4m3 copy of X in the workspace, made once per call; both keep a BF16 copy
+ * of X (n x 16 ceil(d/16) x 2 bytes) made once per call; d <= 128 and
  * k <= 16384 for both (KM_ENOTSUP otherwise).
  */
 #ifndef KMEANS_MI355X_H

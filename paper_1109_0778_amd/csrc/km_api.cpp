@@ -75,6 +75,7 @@ struct km_plan {
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
     size_t off_fsc = 0, off_pfm = 0, off_xq = 0, off_xst = 0;   // FP8 only
+    size_t off_xb = 0, off_xn = 0;                              // BF16 copy of X and |x| bounds
     size_t off_ab16 = 0, off_bias16 = 0, off_cs16 = 0;           // FP8: BF16 operands of the refining pass
     size_t off_amb = 0, off_ambc = 0;                            // samples the screen left open
     size_t off_pcn = 0;                                          // BF16: per-block max |c|^2
@@ -228,6 +229,8 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.Ab = ws + p->off_ab;
     m.Xq = f8 ? ws + p->off_xq : nullptr;
     m.xst = f8 ? reinterpret_cast<const float2*>(ws + p->off_xst) : nullptr;
+    m.Xb = f8 ? nullptr : reinterpret_cast<const __bf16*>(ws + p->off_xb);
+    m.xn = f8 ? nullptr : reinterpret_cast<const float*>(ws + p->off_xn);
     m.bias = reinterpret_cast<const float*>(ws + p->off_bias);
     m.cs = reinterpret_cast<const CStats*>(ws + p->off_cs);
     m.u = f8 ? 0.0625f : 0.00390625f;        // unit roundoff: e4m3 2^-4, BF16 2^-8
@@ -251,6 +254,8 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
         m2.cs = reinterpret_cast<const CStats*>(ws + p->off_cs16);
         m2.Xq = nullptr;
         m2.xst = nullptr;
+        m2.Xb = reinterpret_cast<const __bf16*>(ws + p->off_xb);
+        m2.xn = reinterpret_cast<const float*>(ws + p->off_xn);
         m2.u = 0.00390625f;
     }
     m2.amb = nullptr;
@@ -280,12 +285,16 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
 }
 
 // Run-level prep of the mixed path (once per call, amortised over its
-// iterations): |x| statistics, and for FP8 the scaled e4m3 copy of X.
+// iterations): |x| statistics, the BF16 copy of X with |x| bounds, and for
+// FP8 the scaled e4m3 copy of X.
 hipError_t enqueue_prep_x(km_plan* p, const float* X, hipStream_t s)
 {
     hipError_t e = launch_prep_x(X, p->n, p->d, reinterpret_cast<float*>(p->ws + p->off_pxm),
                                  reinterpret_cast<double*>(p->ws + p->off_pxs),
                                  reinterpret_cast<XStats*>(p->ws + p->off_xs), s);
+    if (e != hipSuccess) return e;
+    e = launch_prep_x_bf16(X, p->n, p->d, p->DP, reinterpret_cast<__bf16*>(p->ws + p->off_xb),
+                           reinterpret_cast<float*>(p->ws + p->off_xn), s);
     if (e != hipSuccess || p->fmt != FMT_FP8) return e;
     return launch_prep_x_fp8(X, p->n, p->d, p->DP, reinterpret_cast<float*>(p->ws + p->off_pfm),
                              reinterpret_cast<float*>(p->ws + p->off_fsc), p->ws + p->off_xq,
@@ -439,6 +448,8 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(FMT_BF16) * sizeof(int32_t));
         p->off_amb = off;  off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(int32_t));
         p->off_ambc = off; off = align256(off + (size_t)p->grid_mfma * sizeof(int32_t));
+        p->off_xb = off;   off = align256(off + (size_t)n * p->DP * 2);
+        p->off_xn = off;   off = align256(off + (size_t)n * sizeof(float));
         if (p->fmt == FMT_FP8) {
             p->off_fsc = off; off = align256(off + 2 * (size_t)p->DP * sizeof(float));
             p->off_pfm = off; off = align256(off + (size_t)kFmaxBlocks * p->DP * sizeof(float));

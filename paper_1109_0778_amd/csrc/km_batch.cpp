@@ -301,6 +301,7 @@ km_status upload(km_batch* B)
         mm.bias = reinterpret_cast<const float*>(ws + B->off_bias[i]);
         mm.cs = reinterpret_cast<const CStats*>(ws + B->off_cs[i]);
         mm.Xq = nullptr; mm.xst = nullptr;
+        mm.Xb = nullptr; mm.xn = nullptr;    // converts X in the pass (no run-level copy)
         mm.u = 0.00390625f;                  // BF16 unit roundoff 2^-8
         mm.IB = ib_of(kpad);
         mm.gamma_terms = 2 * 16 * D16 + 8;

@@ -211,6 +211,8 @@ struct MixArgs {
     const float* bias;          // [kpad] (K + |c_j|^2) / (2r), padded rows huge
     const uint8_t* Xq;          // FP8: [n][16*D16] e4m3(x / s_f), zero padded
     const float2* xst;          // FP8: per sample (|x| upper bound, sum_f |x_f / s_f| upper bound)
+    const __bf16* Xb;           // BF16 passes: [n][16*D16] bf16(x), zero padded, or nullptr (convert X)
+    const float* xn;            // with Xb: per sample |x| upper bound
     const CStats* cs;
     float u;                    // unit roundoff of the quantised format
     int32_t IB;                 // index bits in a key
@@ -252,6 +254,7 @@ hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, 
                          XStats* xs, hipStream_t s);
 // FP8 run-level prep: per-feature scales s_f (powers of two), the e4m3 copy
 // of X and the per-sample band inputs.
+hipError_t launch_prep_x_bf16(const float* X, int64_t n, int32_t d, int32_t DP, __bf16* Xb, float* xn, hipStream_t s);
 hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, float* part_fmax, float* fscale,
                              uint8_t* Xq, float2* xst, hipStream_t s);
 // Per-iteration centroid prep.  BF16 with part_cn2 (prep_c_blocks(kpad)

@@ -188,7 +188,8 @@ __global__ __launch_bounds__(256) void prep_fscale_kernel(const float* __restric
 {
     for (int f = threadIdx.x; f < DP; f += 256) {
         float m = 0.0f;
-        for (int b = 0; b < nb; ++b) m = fmaxf(m, part_fmax[(size_t)b * DP + f]);
+#pragma unroll 16
+        for (int b = 0; b < nb; ++b) m = fmaxf(m, part_fmax[(size_t)b * DP + f]);   // 16 loads in flight
         const float sc = f < d ? pow2_scale(m, kFp8Max) : 1.0f;
         fscale[f] = sc;
         fscale[DP + f] = 1.0f / sc;         // exact: a power of two
@@ -201,32 +202,97 @@ __device__ __forceinline__ uint32_t fp8_of(float v)
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
 }
 
+// Eight features of one row per thread: a row takes G adjacent lanes (G =
+// DP / 8 rounded up to a power of two, at most 16; lanes past DP / 8 idle), so
+// the row is read and written coalesced and its sums are completed by an xor
+// tree across those lanes.  f0: the thread's first feature; x[8]: its
+// features (zero past d); the result: the thread holds a chunk of a row.
+__host__ __device__ constexpr int row_lanes_q(int DP)
+{
+    return DP / 8 <= 2 ? 2 : DP / 8 <= 4 ? 4 : DP / 8 <= 8 ? 8 : 16;
+}
+
+__device__ __forceinline__ bool row_chunk(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
+                                          int64_t& i, int& f0, float (&x)[8])
+{
+    const int G = row_lanes_q(DP);
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    i = t / G;
+    f0 = 8 * (int)(t - i * G);
+    const bool live = i < n && f0 < DP;
+    const float* row = X + (live ? i : 0) * d;
+    if ((d & 7) == 0) {
+        // the chunk lies inside the row (DP = d rounded up to 16, chunks of 8
+        // past d only when d % 16 == 8: clamp those to the row's last chunk)
+        const int fc = f0 < d ? f0 : d - 8;                 // idle lanes and the chunk past d: in the row
+        const float4 v0 = *reinterpret_cast<const float4*>(row + fc);
+        const float4 v1 = *reinterpret_cast<const float4*>(row + fc + 4);
+        const bool in = live && f0 < d;   // (f0 < d also keeps idle lanes' loads in the row)
+        x[0] = in ? v0.x : 0.0f; x[1] = in ? v0.y : 0.0f; x[2] = in ? v0.z : 0.0f; x[3] = in ? v0.w : 0.0f;
+        x[4] = in ? v1.x : 0.0f; x[5] = in ? v1.y : 0.0f; x[6] = in ? v1.z : 0.0f; x[7] = in ? v1.w : 0.0f;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int f = f0 + q;
+            const float v = row[f < d ? f : d - 1];
+            x[q] = (live && f < d) ? v : 0.0f;
+        }
+    }
+    return live;
+}
+
+template <typename T>
+__device__ __forceinline__ T row_sum(T v, int cpr)
+{
+    for (int off = 1; off < cpr; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 __global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
                                                       const float* __restrict__ fscale, uint8_t* Xq, float2* xst)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const float* row = X + i * d;
+    int64_t i;
+    int f0;
+    float x[8];
+    const bool live = row_chunk(X, n, d, DP, i, f0, x);
     const float* inv = fscale + DP;
-    uint4* out = reinterpret_cast<uint4*>(Xq + i * DP);    // DP is a multiple of 16: one uint4 per 16 features
     float s2 = 0.0f, l1 = 0.0f;
-    for (int f0 = 0; f0 < DP; f0 += 16) {
-        float v[16];
+    uint32_t w[2] = {0u, 0u};
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = row[f0 + q < d ? f0 + q : d - 1];   // all 16 loads in flight
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int f = f0 + q;
-            const float x = f < d ? v[q] : 0.0f;
-            const float xt = x * inv[f];
-            s2 = __builtin_fmaf(x, x, s2);
-            l1 += fabsf(xt);
-            w[q >> 2] |= fp8_of(xt) << (8 * (q & 3));
-        }
-        out[f0 / 16] = make_uint4(w[0], w[1], w[2], w[3]);
+    for (int q = 0; q < 8; ++q) {
+        const float xt = x[q] * inv[f0 + q < DP ? f0 + q : DP - 1];   // idle lanes: a valid index
+        s2 = __builtin_fmaf(x[q], x[q], s2);
+        l1 += fabsf(xt);
+        w[q >> 2] |= fp8_of(xt) << (8 * (q & 3));
     }
-    xst[i] = make_float2(sqrtf(s2) * (1.0f + 1e-6f), l1 * (1.0f + 1e-5f));
+    s2 = row_sum(s2, row_lanes_q(DP));
+    l1 = row_sum(l1, row_lanes_q(DP));
+    if (!live) return;
+    *reinterpret_cast<uint2*>(Xq + i * DP + f0) = make_uint2(w[0], w[1]);
+    if (f0 == 0) xst[i] = make_float2(sqrtf(s2) * (1.0f + 1e-6f), l1 * (1.0f + 1e-5f));
+}
+
+// Once per call: the BF16 copy of X the BF16 MFMA passes read (rounded to
+// nearest even, zero padded to DP features) and an upper bound of |x| per
+// sample.  One thread per sample.
+__global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                           int32_t DP, __bf16* Xb, float* xn)
+{
+    int64_t i;
+    int f0;
+    float x[8];
+    const bool live = row_chunk(X, n, d, DP, i, f0, x);
+    float s2 = 0.0f;
+    bf16x8 w;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        s2 = __builtin_fmaf(x[q], x[q], s2);
+        w[q] = (__bf16)x[q];
+    }
+    s2 = row_sum(s2, row_lanes_q(DP));
+    if (!live) return;
+    *reinterpret_cast<bf16x8*>(Xb + i * DP + f0) = w;
+    if (f0 == 0) xn[i] = sqrtf(s2) * (1.0f + 1e-6f);
 }
 
 // ------------------------------------------------------ per-iteration prep
@@ -643,29 +709,38 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 const float r = xn + cmax;
                 W[nb] = (2.0f * B + 2.01f * gcan * r * r * inv2r) * 1.001f;
             } else {
-                const float* row = a.X + (valid ? p : 0) * d;
-                float s2 = 0.0f;
+                float xn;
+                if (a.Xb != nullptr) {
+                    // the run's BF16 copy: one 16-byte load per 16 features
+                    const bf16x8* xr = reinterpret_cast<const bf16x8*>(a.Xb + (valid ? p : 0) * DP + 8 * h);
 #pragma unroll
-                for (int s = 0; s < D16; ++s) {
-                    const int f0 = 16 * s + 8 * h;
-                    float v[8];
-                    if (valid && (d & 3) == 0 && f0 + 8 <= d) {
-                        const float4 v0 = *reinterpret_cast<const float4*>(row + f0);
-                        const float4 v1 = *reinterpret_cast<const float4*>(row + f0 + 4);
-                        v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
-                        v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
-                    } else {
+                    for (int s = 0; s < D16; ++s) bfr[nb][s] = xr[2 * s];
+                    xn = valid ? a.xn[p] : 0.0f;
+                } else {
+                    const float* row = a.X + (valid ? p : 0) * d;
+                    float s2 = 0.0f;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) v[i] = (valid && f0 + i < d) ? row[f0 + i] : 0.0f;
+                    for (int s = 0; s < D16; ++s) {
+                        const int f0 = 16 * s + 8 * h;
+                        float v[8];
+                        if (valid && (d & 3) == 0 && f0 + 8 <= d) {
+                            const float4 v0 = *reinterpret_cast<const float4*>(row + f0);
+                            const float4 v1 = *reinterpret_cast<const float4*>(row + f0 + 4);
+                            v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+                            v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 8; ++i) v[i] = (valid && f0 + i < d) ? row[f0 + i] : 0.0f;
+                        }
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            s2 = __builtin_fmaf(v[i], v[i], s2);
+                            bfr[nb][s][i] = (__bf16)v[i];
+                        }
                     }
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        s2 = __builtin_fmaf(v[i], v[i], s2);
-                        bfr[nb][s][i] = (__bf16)v[i];
-                    }
+                    s2 += __shfl_xor(s2, 32);
+                    xn = sqrtf(s2) * (1.0f + 1e-6f);
                 }
-                s2 += __shfl_xor(s2, 32);
-                const float xn = sqrtf(s2) * (1.0f + 1e-6f);
                 const float u = a.u;
                 const float q = 2.0f * (2.0f * u + u * u);
                 const float emax = K + cn2max + 2.0f * (1.0f + u) * (1.0f + u) * xn * cmax;
@@ -1107,6 +1182,14 @@ hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, 
     return hipGetLastError();
 }
 
+hipError_t launch_prep_x_bf16(const float* X, int64_t n, int32_t d, int32_t DP, __bf16* Xb, float* xn, hipStream_t s)
+{
+    const int64_t threads = n * row_lanes_q(DP);
+    hipLaunchKernelGGL(quant_x_bf16_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, X, n, d, DP, Xb,
+                       xn);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, float* part_fmax, float* fscale,
                              uint8_t* Xq, float2* xst, hipStream_t s)
 {
@@ -1115,7 +1198,9 @@ hipError_t launch_prep_x_fp8(const float* X, int64_t n, int32_t d, int32_t DP, f
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_fscale_kernel, dim3(1), dim3(256), 0, s, part_fmax, kFmaxBlocks, d, DP, fscale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(quant_x_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, DP, fscale, Xq, xst);
+    const int64_t threads = n * row_lanes_q(DP);
+    hipLaunchKernelGGL(quant_x_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, X, n, d, DP, fscale,
+                       Xq, xst);
     return hipGetLastError();
 }
 
