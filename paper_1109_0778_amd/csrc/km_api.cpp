@@ -191,7 +191,7 @@ hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
 {
     // without a split, the update walks exactly the fused pass's tiles and blocks
     if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_upd, s);
-    if (!p->chunked) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd), p->lds_upd, s);
+    if (!p->chunked) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
     // label chunks: partition the samples by chunk, then reduce each chunk's samples
     hipError_t e = launch_partition(a, reinterpret_cast<int32_t*>(p->ws + p->off_perm),
                                     reinterpret_cast<int32_t*>(p->ws + p->off_plab),
@@ -377,7 +377,16 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     // A stand-alone update lists kUpdTiles tiles per step; the update that
     // must walk the fused pass's blocks (no split) keeps its LDS and lists one.
     p->upd_tiles = p->split ? kUpdTiles : 1;
-    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, d) : plain_lds_bytes(k, d, MODE_UPDATE, p->upd_tiles);
+    // A stand-alone update whose record would leave fewer than three blocks
+    // per CU adds label chunks instead (each block reads its range's labels
+    // and adds its chunk's samples; every row is still read once).
+    if (p->split && !p->chunked) {
+        int c = 1;
+        while (c < 4 && plain_lds_bytes((k + c - 1) / c, d, MODE_UPDATE, p->upd_tiles) > 53 * 1024) ++c;
+        p->kc = (k + c - 1) / c;
+        p->nch = (k + p->kc - 1) / p->kc;
+    }
+    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, d) : plain_lds_bytes(p->kc, d, MODE_UPDATE, p->upd_tiles);
     int per_cu_upd = p->chunked ? part_update_blocks_per_cu(p->D8, p->lds_upd)
                                 : plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
     if (per_cu_upd < 1) {
@@ -387,11 +396,9 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     if (!p->split) per_cu = std::min(per_cu, per_cu_fused);
     p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, ntiles));
     per_cu_upd = std::min(per_cu_upd, 4);
-    if (p->chunked) {
+    if (p->split) {
         const int64_t resident = (int64_t)ncu * per_cu_upd;
         p->grid_upd = (int)std::max<int64_t>(1, std::min<int64_t>(resident / p->nch, ntiles));
-    } else if (p->split) {
-        p->grid_upd = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu_upd, ntiles));
     } else {
         p->grid_upd = p->grid;
     }
