@@ -77,7 +77,7 @@ struct km_plan {
     size_t off_fsc = 0, off_pfm = 0, off_xq = 0, off_xst = 0;   // FP8 only
     size_t off_xb = 0, off_xn = 0;                              // BF16 copy of X and |x| bounds
     size_t off_ab16 = 0, off_bias16 = 0, off_cs16 = 0;           // FP8: BF16 operands of the refining pass
-    size_t off_amb = 0, off_ambc = 0;                            // samples the screen left open
+    size_t off_amb = 0, off_ambc = 0, off_ambk = 0;              // samples the screen left open, their keys
     size_t off_pcn = 0;                                          // BF16: per-block max |c|^2
     // workspace
     unsigned char* ws;
@@ -245,6 +245,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.changed_part = changed;
     m.amb = reinterpret_cast<int32_t*>(ws + p->off_amb);
     m.amb_count = reinterpret_cast<int32_t*>(ws + p->off_ambc);
+    m.amb_key = f8 ? nullptr : reinterpret_cast<uint32_t*>(ws + p->off_ambk);
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
     // the refining pass: BF16 operands (the FP8 plan's own copy), FP32 rows
     MixArgs m2 = m;
@@ -262,12 +263,15 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m2.amb_count = nullptr;
     m2.amb_in = m.amb;
     m2.amb_in_count = m.amb_count;
+    m2.amb_key = nullptr;
+    m2.amb_key_in = m.amb_key;
     m2.changed_part = changed + G;
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
     if (p->cascade) {
         if ((e = launch_mfma_assign(p->fmt, 1, p->D16, m, G, s)) != hipSuccess) return e;
-        if ((e = launch_mfma_assign(FMT_BF16, 2, p->D16, m2, G, s)) != hipSuccess) return e;
+        // after a BF16 screen the refine's keys are the screen's: its band is known
+        if ((e = launch_mfma_assign(FMT_BF16, f8 ? 2 : 3, p->D16, m2, G, s)) != hipSuccess) return e;
     } else if ((e = launch_mfma_assign(FMT_BF16, 0, p->D16, m, G, s)) != hipSuccess) {
         return e;
     }
@@ -416,7 +420,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
         p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
-        if (p->cascade && mfma_blocks_per_cu(FMT_BF16, 2, p->D16) < 1) {
+        if (p->cascade && mfma_blocks_per_cu(FMT_BF16, p->fmt == FMT_FP8 ? 2 : 3, p->D16) < 1) {
             delete p;
             return fail(KM_EHIP, "occupancy query for the refining MFMA pass failed");
         }
@@ -455,6 +459,9 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(FMT_BF16) * sizeof(int32_t));
         p->off_amb = off;  off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(int32_t));
         p->off_ambc = off; off = align256(off + (size_t)p->grid_mfma * sizeof(int32_t));
+        if (p->fmt == FMT_BF16) {
+            p->off_ambk = off; off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(uint32_t));
+        }
         p->off_xb = off;   off = align256(off + (size_t)n * p->DP * 2);
         p->off_xn = off;   off = align256(off + (size_t)n * sizeof(float));
         if (p->fmt == FMT_FP8) {

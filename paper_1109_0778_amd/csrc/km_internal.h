@@ -226,8 +226,10 @@ struct MixArgs {
     int32_t* changed_part;      // [nreg]
     int32_t* amb;               // stage 1: [nreg][rq_per_block] samples left for stage 2
     int32_t* amb_count;         // stage 1: [nreg]
-    const int32_t* amb_in;      // stage 2: stage 1's amb and amb_count
+    const int32_t* amb_in;      // stages 2, 3: stage 1's amb and amb_count
     const int32_t* amb_in_count;
+    uint32_t* amb_key;          // stage 1: [nreg][rq_per_block] smallest key of each listed sample
+    const uint32_t* amb_key_in; // stage 3: stage 1's amb_key (same operands, so the same keys)
     const Ctrl* ctrl;
     int32_t iter;
     int32_t count_changed;

@@ -596,8 +596,11 @@ __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
 // STAGE 0: keys, running minimum and candidate lists over consecutive
 // samples.  STAGE 1 (screen): only the two smallest keys of each sample; a
 // sample whose second key lies outside its band takes the smallest, the
-// others are listed in region `region` of a.amb.  STAGE 2 (refine): the
-// stage-0 sweep over the samples listed in region `region` of a.amb_in.
+// others are listed in region `region` of a.amb (with their smallest key in
+// a.amb_key when given).  STAGE 2 (refine): the stage-0 sweep over the
+// samples listed in region `region` of a.amb_in.  STAGE 3 (refine after a
+// screen with the same operands): the smallest key, and so the band, is the
+// screen's; the sweep lists the keys inside it and nothing more.
 template <int D16, int FMT, int STAGE>
 __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
                                           int region, unsigned char* smem)
@@ -642,9 +645,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     const float P = (float)a.D8;
     const float gcan = (10.0f + (a.D8 > 1 ? ceilf(log2f(P)) : 0.0f)) * 5.9604645e-8f;
     const int nchunks = a.kpad / kMixCK;
-    const int amb_n = STAGE == 2 ? a.amb_in_count[region] : 0;        // samples listed for this block
-    const int32_t* amb_list = STAGE == 2 ? a.amb_in + (size_t)region * a.rq_per_block : nullptr;
-    const int64_t ntiles = STAGE == 2 ? (amb_n + TILE - 1) / TILE : (n + TILE - 1) / TILE;
+    constexpr bool REF = STAGE >= 2;       // a refining sweep over the screen's open samples
+    const int amb_n = REF ? a.amb_in_count[region] : 0;        // samples listed for this block
+    const int32_t* amb_list = REF ? a.amb_in + (size_t)region * a.rq_per_block : nullptr;
+    const uint32_t* amb_key = STAGE == 3 ? a.amb_key_in + (size_t)region * a.rq_per_block : nullptr;
+    const int64_t ntiles = REF ? (amb_n + TILE - 1) / TILE : (n + TILE - 1) / TILE;
     const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     uint32_t* mycand = cand + (size_t)wave * NB * SLOTS * 64;
     int32_t changed = 0;
@@ -686,10 +691,12 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         long bq[NB][F8 ? D16 : 1];
         float W[NB];
         int64_t pidx[NB];
+        uint32_t mfix[NB];   // stage 3: the screen's smallest key of the sample
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             int64_t p = t * TILE + (int64_t)wave * (NB * 32) + nb * 32 + col;
-            if constexpr (STAGE == 2) p = p < amb_n ? (int64_t)amb_list[p] : n;   // a listed sample, or none
+            if constexpr (STAGE == 3) mfix[nb] = p < amb_n ? amb_key[p] : 0u;
+            if constexpr (REF) p = p < amb_n ? (int64_t)amb_list[p] : n;   // a listed sample, or none
             pidx[nb] = p;
             const bool valid = p < n;
             if constexpr (F8) {
@@ -749,6 +756,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 W[nb] = (2.0f * B + 2.01f * gcan * r * r) * 1.001f;
             }
         }
+
+        // stage 3: the final band is known before the sweep
+        uint32_t tfix[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) tfix[nb] = STAGE == 3 ? thr_key(mfix[nb], W[nb], ibm) : 0u;
 
         // m: running minimum key; cnt: list length; cut: smallest key dropped
         // from a full list (every kept entry is below it); ovf: a full list
@@ -822,6 +834,24 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                         }
                         lm[nb] = mm;
                         lm2[nb] = mm2;
+                    }
+                    continue;
+                }
+                if constexpr (STAGE == 3) {
+                    // list every key inside the known band; more than CAP of
+                    // them leaves the sample to a full rescan
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        uint32_t* lst = mycand + nb * SLOTS * 64 + lane;
+#pragma unroll
+                        for (int half = 0; half < 2; ++half) {
+#pragma unroll
+                            for (int i = 8 * half; i < 8 * half + 8; ++i) {
+                                const uint32_t key = (__float_as_uint(acc[nb][i]) & ~ibm) | (j0 + 8 * (i >> 2) + (i & 3));
+                                if (key <= tfix[nb]) { lst[cnt[nb] * 64] = key; ++cnt[nb]; }
+                            }
+                            if (cnt[nb] > CAP) { ovf[nb] = 1; cnt[nb] = CAP; }
+                        }
                     }
                     continue;
                 }
@@ -916,9 +946,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                     int base = 0;
                     if (lane == 0) base = atomicAdd(&blk_count, (int)__popcll(need));
                     base = __shfl(base, 0);
-                    if (valid && !unique && h == 0)
-                        a.amb[(size_t)region * a.rq_per_block + base + (int)__popcll(need & ((1ull << col) - 1ull))] =
-                            (int32_t)p;
+                    if (valid && !unique && h == 0) {
+                        const size_t at = (size_t)region * a.rq_per_block + base + (int)__popcll(need & ((1ull << col) - 1ull));
+                        a.amb[at] = (int32_t)p;
+                        if (a.amb_key != nullptr) a.amb_key[at] = mp;
+                    }
                 }
             }
             continue;
@@ -926,14 +958,22 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         // --- decide per sample: unique candidate, or queue an exact recheck
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const uint32_t mp = min(m[nb], (uint32_t)__shfl_xor((int)m[nb], 32));
-            const uint32_t tf = thr_key(mp, W[nb], ibm);
+            const uint32_t mp = STAGE == 3 ? mfix[nb] : min(m[nb], (uint32_t)__shfl_xor((int)m[nb], 32));
+            const uint32_t tf = STAGE == 3 ? tfix[nb] : thr_key(mp, W[nb], ibm);
             int vc = 0;
+            uint32_t lmin = 0xffffffffu;
             const int stored = cnt[nb];
-            for (int q = 0; q < stored; ++q) vc += (mycand[(nb * SLOTS + q) * 64 + lane] <= tf);
+            for (int q = 0; q < stored; ++q) {
+                const uint32_t v = mycand[(nb * SLOTS + q) * 64 + lane];
+                vc += (v <= tf);
+                lmin = min(lmin, v);
+            }
             const int vc_other = __shfl_xor(vc, 32);
             // a dropped key inside the final band: the list is incomplete
-            const int ovf_h = ovf[nb] | (cut[nb] <= tf ? 1 : 0);
+            int ovf_h = ovf[nb] | (cut[nb] <= tf ? 1 : 0);
+            // stage 3 takes its band from the screen: the listed minimum must be
+            // the screen's key exactly, else the sample is rescanned in full
+            if constexpr (STAGE == 3) ovf_h |= min(lmin, (uint32_t)__shfl_xor((int)lmin, 32)) != mp ? 1 : 0;
             const int ovf_any = ovf_h | __shfl_xor(ovf_h, 32);
             const int64_t p = pidx[nb];
             const bool valid = p < n;
@@ -995,13 +1035,14 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
 }
 
 // The screen is built for three resident waves per SIMD (its 64 samples per
-// wave hold 64 VGPRs of operands for the whole sweep).
+// wave hold 64 VGPRs of operands for the whole sweep); the refine after a
+// BF16 screen fits four (128 VGPRs at 128 features).
 template <int D16, int FMT, int STAGE>
-__global__ __launch_bounds__(64 * kMixWaves) __attribute__((amdgpu_waves_per_eu(STAGE == 1 ? 3 : 1)))
+__global__ __launch_bounds__(64 * kMixWaves) __attribute__((amdgpu_waves_per_eu(STAGE == 1 ? 3 : STAGE == 3 ? 4 : 1)))
 void mfma_assign(MixArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    if constexpr (STAGE == 2)
+    if constexpr (STAGE >= 2)
         mfma_body<D16, FMT, STAGE>(a, 0, INT64_MAX, 1, blockIdx.x, smem);   // block b refines region b
     else
         mfma_body<D16, FMT, STAGE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
@@ -1232,7 +1273,7 @@ size_t mfma_lds_bytes(int fmt, int D16, int stage)
 {
     const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
     return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
-           (stage == 1 ? 0 : (size_t)kMixWaves * kMixNB * cand_slots(fmt) * 64 * sizeof(uint32_t));
+           (stage == 1 ? 0 : (size_t)kMixWaves * mix_nb(stage) * cand_slots(fmt) * 64 * sizeof(uint32_t));
 }
 
 template <int D16, int FMT, int STAGE>
@@ -1265,12 +1306,14 @@ static hipError_t launch_mfma_fs(int D16, const MixArgs& a, int grid, hipStream_
 }
 
 // The single-instance passes: BF16 and FP8 screens (stage 1), the BF16 refine
-// (stage 2), the BF16 one-pass sweep (stage 0).
+// after the FP8 screen (stage 2) and after the BF16 screen (stage 3), the BF16
+// one-pass sweep (stage 0).
 hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s)
 {
     if (stage == 1) return fmt == FMT_FP8 ? launch_mfma_fs<FMT_FP8, 1>(D16, a, grid, s)
                                           : launch_mfma_fs<FMT_BF16, 1>(D16, a, grid, s);
     if (stage == 2 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 2>(D16, a, grid, s);
+    if (stage == 3 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 3>(D16, a, grid, s);
     if (stage == 0 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 0>(D16, a, grid, s);
     return hipErrorInvalidValue;
 }
@@ -1310,6 +1353,7 @@ int mfma_blocks_per_cu(int fmt, int stage, int D16)
 {
     if (stage == 1) return fmt == FMT_FP8 ? occ_mfma_fs<FMT_FP8, 1>(D16) : occ_mfma_fs<FMT_BF16, 1>(D16);
     if (stage == 2 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 2>(D16);
+    if (stage == 3 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 3>(D16);
     if (stage == 0 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 0>(D16);
     return -1;
 }
