@@ -401,6 +401,10 @@ void batch_pass(const BatchWork* __restrict__ work,
 // each kPartRows-sample sub-range by label chunk (a stable counting sort:
 // chunk counts, their prefix, then each 64-sample group's lanes placed chunk
 // by chunk in lane order), and the chunk blocks read just their samples.
+// Within a group, the lanes of a lane's chunk are found bit by bit: one
+// ballot per bit of the chunk index, kept or complemented as the lane's own
+// bit is set or clear, so the cost is log2(chunks) ballots, not one round
+// per distinct chunk.
 __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict__ labels, int64_t n, int32_t k,
                                                        int32_t kc, int32_t nch, int32_t* perm, int32_t* plab,
                                                        int32_t* poff, int32_t* pcnt, const Ctrl* ctrl, int32_t iter)
@@ -424,9 +428,26 @@ __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict
 #pragma unroll
     for (int g = 0; g < G; ++g) ch[g] = (lb[g] >= 0 && lb[g] < k) ? lb[g] / kc : -1;
     __syncthreads();
+    // per group: a lane's rank among the lanes of its chunk and their number,
+    // packed beside the chunk (chunk < 2^16, rank < 64, number <= 64); the
+    // first lane of each chunk adds the number (distinct addresses)
+    const int nbits = nch > 1 ? 32 - __builtin_clz((unsigned)(nch - 1)) : 0;
+    const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-        if (ch[g] >= 0) __hip_atomic_fetch_add(cnt + ch[g], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int g = 0; g < G; ++g) {
+        const int c = ch[g];
+        uint64_t same = __ballot(c >= 0);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (c >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            same &= bit ? m : ~m;
+        }
+        const int rank = (int)__popcll(same & lt), num = (int)__popcll(same);
+        if (c >= 0) {
+            if (rank == 0) __hip_atomic_fetch_add(cnt + c, num, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            ch[g] = c | (rank << 16) | (num << 23);
+        }
+    }
     __syncthreads();
     int carry = 0;
     for (int c0 = 0; c0 < nch; c0 += 64) {
@@ -449,19 +470,11 @@ __global__ __launch_bounds__(64) void partition_kernel(const int32_t* __restrict
     __syncthreads();
     // scatter in sample order: a lane's slot is its chunk's cursor plus the
     // number of lower lanes of the group in the same chunk
-    const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int c = ch[g];
+        const int c = ch[g] >= 0 ? (ch[g] & 0xffff) : -1;
+        const int rank = (ch[g] >> 16) & 127, num = ch[g] >> 23;
         const int at = c >= 0 ? cur[c] : 0;
-        int rank = 0, num = 0;
-        uint64_t rem = __ballot(c >= 0);
-        while (rem) {
-            const int cx = __builtin_amdgcn_readlane(c, (int)__builtin_ctzll(rem));
-            const uint64_t m = __ballot(c == cx);
-            if (c == cx) { rank = (int)__popcll(m & lt); num = (int)__popcll(m); }
-            rem &= ~m;
-        }
         if (c >= 0) {
             perm[at + rank] = (int32_t)(base + g * 64 + lane);
             plab[at + rank] = lb[g];

@@ -114,7 +114,7 @@ SHAPES = [  # (n, d, k): several tiles, ragged tails, odd d, d not a multiple of
     (3000, 8, 8), (5000, 3, 5), (4099, 17, 13), (2500, 64, 64), (1200, 128, 9),
     (257, 33, 40), (700, 1, 4), (20000, 24, 100), (999, 96, 3), (64, 5, 64),
     # per-label record beyond one block's LDS: assign + label-chunked update
-    (20000, 128, 200), (9001, 96, 150), (5000, 24, 600),
+    (20000, 128, 200), (9001, 96, 150), (5000, 24, 600), (12001, 128, 2000),
     # record too large for the fused pass but within one update block: update over 2 label chunks
     (30000, 64, 120), (20000, 32, 256),
 ]
