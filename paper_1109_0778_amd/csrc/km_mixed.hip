@@ -821,8 +821,10 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 __builtin_amdgcn_s_setprio(0);
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
-                if constexpr (STAGE == 1) {
-                    // the two smallest keys of the chunk so far (lm <= lm2)
+                if constexpr (STAGE == 1 && D16 > 5) {
+                    // the two smallest keys of the chunk so far (lm <= lm2),
+                    // one key at a time (3 VALU operations per key): at 96 or
+                    // more features the MFMA chain outlasts the epilogue
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
                         uint32_t mm = lm[nb], mm2 = lm2[nb];
@@ -831,6 +833,31 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                             const uint32_t key = (__float_as_uint(acc[nb][i]) & ~ibm) | (uint32_t)(tt * 32 + 8 * (i >> 2) + (i & 3));
                             mm2 = med3_u32(mm, mm2, key);
                             mm = min(mm, key);
+                        }
+                        lm[nb] = mm;
+                        lm2[nb] = mm2;
+                    }
+                    continue;
+                } else if constexpr (STAGE == 1) {
+                    // shorter chains leave the epilogue as the longer part:
+                    // keys two at a time; with a <= b <= c the sorted lm, k0,
+                    // k1, the new pair is (a, min(lm2, b)), where
+                    // b = med3(lm, k0, k1) and a = min3(lm, k0, k1) (every
+                    // other key seen is >= lm2); 9 VALU operations per 4 keys
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        uint32_t mm = lm[nb], mm2 = lm2[nb];
+#pragma unroll
+                        for (int i = 0; i < 16; i += 4) {
+                            uint32_t key[4];
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                key[q] = (__float_as_uint(acc[nb][i + q]) & ~ibm) | (uint32_t)(tt * 32 + 8 * (i >> 2) + q);
+                            const uint32_t t1 = med3_u32(mm, key[0], key[1]);
+                            const uint32_t l1 = min(min(mm, key[0]), key[1]);
+                            const uint32_t t2 = med3_u32(l1, key[2], key[3]);
+                            mm = min(min(l1, key[2]), key[3]);
+                            mm2 = min(min(mm2, t1), t2);
                         }
                         lm[nb] = mm;
                         lm2[nb] = mm2;
