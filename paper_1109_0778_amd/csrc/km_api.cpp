@@ -68,6 +68,8 @@ struct km_plan {
     bool mixed = false;
     int fmt = FMT_BF16;
     bool cascade = false;   // screen + refine (longer centroid sweeps, and FP8); else one BF16 sweep
+    // MFMA passes per iteration: one sweep; BF16 screen + refine; FP8 screen + BF16 screen + refine
+    int mfma_passes() const { return !cascade ? 1 : fmt == FMT_FP8 ? 3 : 2; }
     int D16 = 0, DP = 0, kpad = 0, IB = 0;
     int upd_tiles = 1;   // update pass: tiles listed per step
     int grid_mfma = 0, grid_rc = 0;
@@ -78,6 +80,7 @@ struct km_plan {
     size_t off_xb = 0, off_xn = 0;                              // BF16 copy of X and |x| bounds
     size_t off_ab16 = 0, off_bias16 = 0, off_cs16 = 0;           // FP8: BF16 operands of the refining pass
     size_t off_amb = 0, off_ambc = 0, off_ambk = 0;              // samples the screen left open, their keys
+    size_t off_amb2 = 0, off_ambc2 = 0;                          // FP8: those the BF16 screen left open
     size_t off_pcn = 0;                                          // BF16: per-block max |c|^2
     // workspace
     unsigned char* ws;
@@ -181,7 +184,7 @@ FinArgs fin_args(const km_plan* p)
     f.jmode = p->mixed ? 1 : 0;
     f.Jterm = reinterpret_cast<double*>(p->ws + p->off_jt);
     f.sum_xn2 = p->mixed ? &reinterpret_cast<const XStats*>(p->ws + p->off_xs)->sum_xn2 : nullptr;
-    f.GC = p->mixed ? (p->cascade ? 2 : 1) * p->grid_mfma + p->grid_rc : p->grid;
+    f.GC = p->mixed ? p->mfma_passes() * p->grid_mfma + p->grid_rc : p->grid;
     return f;
 }
 
@@ -246,32 +249,44 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.amb = reinterpret_cast<int32_t*>(ws + p->off_amb);
     m.amb_count = reinterpret_cast<int32_t*>(ws + p->off_ambc);
     m.amb_key = f8 ? nullptr : reinterpret_cast<uint32_t*>(ws + p->off_ambk);
+    m.amb_key_in = nullptr;
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
-    // the refining pass: BF16 operands (the FP8 plan's own copy), FP32 rows
-    MixArgs m2 = m;
+    // BF16 operands (the FP8 plan's own copy); an FP8 screen's open samples
+    // get a BF16 screen of their own (mb), whose keys the refine then shares
+    MixArgs mb = m;
     if (f8) {
-        m2.Ab = ws + p->off_ab16;
-        m2.bias = reinterpret_cast<const float*>(ws + p->off_bias16);
-        m2.cs = reinterpret_cast<const CStats*>(ws + p->off_cs16);
-        m2.Xq = nullptr;
-        m2.xst = nullptr;
-        m2.Xb = reinterpret_cast<const __bf16*>(ws + p->off_xb);
-        m2.xn = reinterpret_cast<const float*>(ws + p->off_xn);
-        m2.u = 0.00390625f;
+        mb.Ab = ws + p->off_ab16;
+        mb.bias = reinterpret_cast<const float*>(ws + p->off_bias16);
+        mb.cs = reinterpret_cast<const CStats*>(ws + p->off_cs16);
+        mb.Xq = nullptr;
+        mb.xst = nullptr;
+        mb.Xb = reinterpret_cast<const __bf16*>(ws + p->off_xb);
+        mb.xn = reinterpret_cast<const float*>(ws + p->off_xn);
+        mb.u = 0.00390625f;
+        mb.amb_in = m.amb;
+        mb.amb_in_count = m.amb_count;
+        mb.amb = reinterpret_cast<int32_t*>(ws + p->off_amb2);
+        mb.amb_count = reinterpret_cast<int32_t*>(ws + p->off_ambc2);
+        mb.amb_key = reinterpret_cast<uint32_t*>(ws + p->off_ambk);
+        mb.changed_part = changed + G;
     }
+    const MixArgs& last_screen = f8 ? mb : m;
+    // the refining pass: the last screen's open samples and keys
+    MixArgs m2 = mb;
     m2.amb = nullptr;
     m2.amb_count = nullptr;
-    m2.amb_in = m.amb;
-    m2.amb_in_count = m.amb_count;
+    m2.amb_in = last_screen.amb;
+    m2.amb_in_count = last_screen.amb_count;
     m2.amb_key = nullptr;
-    m2.amb_key_in = m.amb_key;
-    m2.changed_part = changed + G;
+    m2.amb_key_in = last_screen.amb_key;
+    m2.changed_part = changed + (p->mfma_passes() - 1) * G;
     const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
     if (p->cascade) {
         if ((e = launch_mfma_assign(p->fmt, 1, p->D16, m, G, s)) != hipSuccess) return e;
+        if (f8 && (e = launch_mfma_assign(FMT_BF16, 2, p->D16, mb, G, s)) != hipSuccess) return e;
         // after a BF16 screen the refine's keys are the screen's: its band is known
-        if ((e = launch_mfma_assign(FMT_BF16, f8 ? 2 : 3, p->D16, m2, G, s)) != hipSuccess) return e;
+        if ((e = launch_mfma_assign(FMT_BF16, 3, p->D16, m2, G, s)) != hipSuccess) return e;
     } else if ((e = launch_mfma_assign(FMT_BF16, 0, p->D16, m, G, s)) != hipSuccess) {
         return e;
     }
@@ -283,7 +298,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     r.X = X; r.Cp = Cp; r.n = p->n; r.d = p->d; r.k = p->k;
     r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = rq_ints(FMT_BF16);
     r.nreg = G;
-    r.labels = labels; r.changed_part = changed + (p->cascade ? 2 : 1) * G;
+    r.labels = labels; r.changed_part = changed + p->mfma_passes() * G;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
     return launch_recheck(p->D8, r, G, s);
 }
@@ -420,7 +435,8 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
         p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
-        if (p->cascade && mfma_blocks_per_cu(FMT_BF16, p->fmt == FMT_FP8 ? 2 : 3, p->D16) < 1) {
+        if (p->cascade && (mfma_blocks_per_cu(FMT_BF16, 3, p->D16) < 1 ||
+                           (p->fmt == FMT_FP8 && mfma_blocks_per_cu(FMT_BF16, 2, p->D16) < 1))) {
             delete p;
             return fail(KM_EHIP, "occupancy query for the refining MFMA pass failed");
         }
@@ -436,7 +452,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->off_pS = off;   off = align256(off + (size_t)p->GS() * k * d * sizeof(double));
     p->off_pcnt = off; off = align256(off + (size_t)p->GS() * k * sizeof(int32_t));
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
-    p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, 2 * p->grid_mfma + p->grid_rc) * sizeof(int32_t));
+    p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, 3 * p->grid_mfma + p->grid_rc) * sizeof(int32_t));
     p->off_pbad = off; off = align256(off + (size_t)std::max(p->grid, p->GS()) * sizeof(int32_t));
     if (p->chunked) {
         p->off_perm = off; off = align256(off + (size_t)n * sizeof(int32_t));
@@ -459,8 +475,10 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(FMT_BF16) * sizeof(int32_t));
         p->off_amb = off;  off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(int32_t));
         p->off_ambc = off; off = align256(off + (size_t)p->grid_mfma * sizeof(int32_t));
-        if (p->fmt == FMT_BF16) {
-            p->off_ambk = off; off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(uint32_t));
+        p->off_ambk = off; off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(uint32_t));
+        if (p->fmt == FMT_FP8) {
+            p->off_amb2 = off;  off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(int32_t));
+            p->off_ambc2 = off; off = align256(off + (size_t)p->grid_mfma * sizeof(int32_t));
         }
         p->off_xb = off;   off = align256(off + (size_t)n * p->DP * 2);
         p->off_xn = off;   off = align256(off + (size_t)n * sizeof(float));

@@ -173,7 +173,7 @@ constexpr int kMixTile = kMixWaves * kMixNB * 32;
 // The screen (two smallest keys, no candidate lists) holds two column blocks
 // per wave: each centroid fragment read from LDS feeds two MFMAs.
 constexpr int kMixNBScreen = 2;
-__host__ __device__ constexpr int mix_nb(int stage) { return stage == 1 ? kMixNBScreen : kMixNB; }
+__host__ __device__ constexpr int mix_nb(int stage) { return stage == 1 || stage == 2 ? kMixNBScreen : kMixNB; }
 __host__ __device__ constexpr int mix_tile(int stage) { return kMixWaves * mix_nb(stage) * 32; }
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
 // Candidates kept per lane (half a sample's rows); the FP8 band is about 16
@@ -224,12 +224,12 @@ struct MixArgs {
     int64_t rq_per_block;       // region capacity (tiles per block x samples per tile)
     int32_t nreg;               // queue regions (one per MFMA block or work row)
     int32_t* changed_part;      // [nreg]
-    int32_t* amb;               // stage 1: [nreg][rq_per_block] samples left for stage 2
-    int32_t* amb_count;         // stage 1: [nreg]
-    const int32_t* amb_in;      // stages 2, 3: stage 1's amb and amb_count
+    int32_t* amb;               // stages 1, 2: [nreg][rq_per_block] samples left open
+    int32_t* amb_count;         // stages 1, 2: [nreg]
+    const int32_t* amb_in;      // stages 2, 3: the previous screen's amb and amb_count
     const int32_t* amb_in_count;
-    uint32_t* amb_key;          // stage 1: [nreg][rq_per_block] smallest key of each listed sample
-    const uint32_t* amb_key_in; // stage 3: stage 1's amb_key (same operands, so the same keys)
+    uint32_t* amb_key;          // stages 1, 2: [nreg][rq_per_block] smallest key of each listed sample
+    const uint32_t* amb_key_in; // stage 3: the BF16 screen's amb_key (same operands, so the same keys)
     const Ctrl* ctrl;
     int32_t iter;
     int32_t count_changed;
@@ -266,8 +266,10 @@ hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t
                          const XStats* xs, const float* fscale, void* Ab, float* bias, CStats* cs, float* part_cn2,
                          const Ctrl* ctrl, int32_t iter, hipStream_t s);
 // MFMA passes: stage 1 screens every sample (two smallest keys), stage 2
-// (BF16) refines the samples stage 1 listed (candidate lists, recheck queue);
-// stage 0 (the one-pass sweep) serves the batched path.
+// (BF16) screens the samples an FP8 stage 1 listed, stage 3 (BF16) refines
+// the samples the last BF16 screen listed (candidate lists inside the band
+// of the screen's smallest key, recheck queue); stage 0 (the one-pass sweep
+// with running candidate lists) serves short sweeps and the batched path.
 hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s);
 size_t mfma_lds_bytes(int fmt, int D16, int stage);
 int mfma_blocks_per_cu(int fmt, int stage, int D16);

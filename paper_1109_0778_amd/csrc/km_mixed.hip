@@ -597,10 +597,12 @@ __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
 // samples.  STAGE 1 (screen): only the two smallest keys of each sample; a
 // sample whose second key lies outside its band takes the smallest, the
 // others are listed in region `region` of a.amb (with their smallest key in
-// a.amb_key when given).  STAGE 2 (refine): the stage-0 sweep over the
-// samples listed in region `region` of a.amb_in.  STAGE 3 (refine after a
-// screen with the same operands): the smallest key, and so the band, is the
-// screen's; the sweep lists the keys inside it and nothing more.
+// a.amb_key when given).  STAGE 2: the stage-1 screen over the samples
+// listed in region `region` of a.amb_in (a BF16 screen of what an FP8 screen
+// left open).  STAGE 3 (refine after a screen with the same operands) over
+// the samples listed in a.amb_in: the smallest key, and so the band, is the
+// screen's (a.amb_key_in); the sweep lists the keys inside it and nothing
+// more.
 template <int D16, int FMT, int STAGE>
 __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
                                           int region, unsigned char* smem)
@@ -645,11 +647,12 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     const float P = (float)a.D8;
     const float gcan = (10.0f + (a.D8 > 1 ? ceilf(log2f(P)) : 0.0f)) * 5.9604645e-8f;
     const int nchunks = a.kpad / kMixCK;
-    constexpr bool REF = STAGE >= 2;       // a refining sweep over the screen's open samples
-    const int amb_n = REF ? a.amb_in_count[region] : 0;        // samples listed for this block
-    const int32_t* amb_list = REF ? a.amb_in + (size_t)region * a.rq_per_block : nullptr;
+    constexpr bool SCREEN = STAGE == 1 || STAGE == 2;   // two smallest keys only
+    constexpr bool LISTED = STAGE >= 2;                  // a sweep over an earlier pass's open samples
+    const int amb_n = LISTED ? a.amb_in_count[region] : 0;        // samples listed for this block
+    const int32_t* amb_list = LISTED ? a.amb_in + (size_t)region * a.rq_per_block : nullptr;
     const uint32_t* amb_key = STAGE == 3 ? a.amb_key_in + (size_t)region * a.rq_per_block : nullptr;
-    const int64_t ntiles = REF ? (amb_n + TILE - 1) / TILE : (n + TILE - 1) / TILE;
+    const int64_t ntiles = LISTED ? (amb_n + TILE - 1) / TILE : (n + TILE - 1) / TILE;
     const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     uint32_t* mycand = cand + (size_t)wave * NB * SLOTS * 64;
     int32_t changed = 0;
@@ -696,7 +699,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         for (int nb = 0; nb < NB; ++nb) {
             int64_t p = t * TILE + (int64_t)wave * (NB * 32) + nb * 32 + col;
             if constexpr (STAGE == 3) mfix[nb] = p < amb_n ? amb_key[p] : 0u;
-            if constexpr (REF) p = p < amb_n ? (int64_t)amb_list[p] : n;   // a listed sample, or none
+            if constexpr (LISTED) p = p < amb_n ? (int64_t)amb_list[p] : n;   // a listed sample, or none
             pidx[nb] = p;
             const bool valid = p < n;
             if constexpr (F8) {
@@ -821,7 +824,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 __builtin_amdgcn_s_setprio(0);
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
-                if constexpr (STAGE == 1 && D16 > 5) {
+                if constexpr (SCREEN && D16 > 5) {
                     // the two smallest keys of the chunk so far (lm <= lm2),
                     // one key at a time (3 VALU operations per key): at 96 or
                     // more features the MFMA chain outlasts the epilogue
@@ -838,7 +841,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                         lm2[nb] = mm2;
                     }
                     continue;
-                } else if constexpr (STAGE == 1) {
+                } else if constexpr (SCREEN) {
                     // shorter chains leave the epilogue as the longer part:
                     // keys two at a time; with a <= b <= c the sorted lm, k0,
                     // k1, the new pair is (a, min(lm2, b)), where
@@ -932,7 +935,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                     }
                 }
             }
-            if constexpr (STAGE == 1) {
+            if constexpr (SCREEN) {
                 // index bits of the chunk (c * 64) and of the lane's rows (4h)
                 // are clear in the chunk-local keys (kpad >= 64)
                 const uint32_t J = (uint32_t)(c * kMixCK) | (4u * (uint32_t)h);
@@ -950,7 +953,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
             }
         }
 
-        if constexpr (STAGE == 1) {
+        if constexpr (SCREEN) {
             // decide per sample: the second key outside the band leaves one
             // candidate; otherwise list the sample for the refining sweep
 #pragma unroll
@@ -1052,7 +1055,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         int32_t c = 0;
         for (int w = 0; w < kMixWaves; ++w) c += sred[w];
         a.changed_part[region] = c;
-        if constexpr (STAGE == 1) {
+        if constexpr (SCREEN) {
             a.amb_count[region] = blk_count;
         } else {
             a.rq_count[region] = blk_count;
@@ -1065,12 +1068,12 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
 // wave hold 64 VGPRs of operands for the whole sweep); the refine after a
 // BF16 screen fits four (128 VGPRs at 128 features).
 template <int D16, int FMT, int STAGE>
-__global__ __launch_bounds__(64 * kMixWaves) __attribute__((amdgpu_waves_per_eu(STAGE == 1 ? 3 : STAGE == 3 ? 4 : 1)))
+__global__ __launch_bounds__(64 * kMixWaves) __attribute__((amdgpu_waves_per_eu(STAGE == 1 || STAGE == 2 ? 3 : STAGE == 3 ? 4 : 1)))
 void mfma_assign(MixArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     if constexpr (STAGE >= 2)
-        mfma_body<D16, FMT, STAGE>(a, 0, INT64_MAX, 1, blockIdx.x, smem);   // block b refines region b
+        mfma_body<D16, FMT, STAGE>(a, 0, INT64_MAX, 1, blockIdx.x, smem);   // block b takes region b's list
     else
         mfma_body<D16, FMT, STAGE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
 }
@@ -1300,7 +1303,7 @@ size_t mfma_lds_bytes(int fmt, int D16, int stage)
 {
     const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
     return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
-           (stage == 1 ? 0 : (size_t)kMixWaves * mix_nb(stage) * cand_slots(fmt) * 64 * sizeof(uint32_t));
+           (stage == 1 || stage == 2 ? 0 : (size_t)kMixWaves * mix_nb(stage) * cand_slots(fmt) * 64 * sizeof(uint32_t));
 }
 
 template <int D16, int FMT, int STAGE>
@@ -1332,9 +1335,9 @@ static hipError_t launch_mfma_fs(int D16, const MixArgs& a, int grid, hipStream_
     }
 }
 
-// The single-instance passes: BF16 and FP8 screens (stage 1), the BF16 refine
-// after the FP8 screen (stage 2) and after the BF16 screen (stage 3), the BF16
-// one-pass sweep (stage 0).
+// The single-instance passes: BF16 and FP8 screens (stage 1), the BF16 screen
+// of the FP8 screen's open samples (stage 2), the BF16 refine after a BF16
+// screen (stage 3), the BF16 one-pass sweep (stage 0).
 hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s)
 {
     if (stage == 1) return fmt == FMT_FP8 ? launch_mfma_fs<FMT_FP8, 1>(D16, a, grid, s)
