@@ -1168,14 +1168,21 @@ __device__ __forceinline__ void recheck_body(const RecheckArgs& a, int region, i
         for (int off = 32; off >= 1; off >>= 1) trips = max(trips, __shfl_xor(trips, off));
         float best = __builtin_huge_valf();
         int bj = 0;
-        constexpr int TB = 8;                // candidates in flight per group
+        // candidates in flight per group: most lists hold two or three, and
+        // four (against eight) measured 20-24% faster: fewer registers, more
+        // resident waves, less work on empty slots
+        constexpr int TB = 4;
         const int lastbatch = a.rq_ints - kRqHead - TB;   // the list holds a multiple of TB slots
         for (int t0 = 0; t0 < trips; t0 += TB) {
             int jj[TB];
             {
                 const int4* lp = reinterpret_cast<const int4*>(ent + kRqHead + (t0 < lastbatch ? t0 : lastbatch));
-                const int4 l0 = lp[0], l1 = lp[1];
-                const int listed[TB] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+                int listed[TB];
+#pragma unroll
+                for (int v = 0; v < TB / 4; ++v) {
+                    const int4 l = lp[v];
+                    listed[4 * v] = l.x; listed[4 * v + 1] = l.y; listed[4 * v + 2] = l.z; listed[4 * v + 3] = l.w;
+                }
 #pragma unroll
                 for (int u = 0; u < TB; ++u) {
                     const int t = t0 + u;
