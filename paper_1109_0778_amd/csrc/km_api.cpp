@@ -85,7 +85,7 @@ struct km_plan {
     // workspace
     unsigned char* ws;
     size_t ws_bytes;
-    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, off_pbad, off_stS, off_stC, total;
+    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, off_pbad, total;
     // optional per-launch timing of the per-sample pass
     std::vector<hipEvent_t> ev;   // 2 per launch
     int32_t ev_used = 0;
@@ -177,8 +177,6 @@ FinArgs fin_args(const km_plan* p)
 {
     FinArgs f{};
     f.part = partials_of(p);
-    f.stageS = reinterpret_cast<double*>(p->ws + p->off_stS);
-    f.stageC = reinterpret_cast<int32_t*>(p->ws + p->off_stC);
     f.G = p->GS(); f.GJ = p->grid; f.k = p->k; f.d = p->d; f.D = p->D;
     f.tol = -1.0;
     f.jmode = p->mixed ? 1 : 0;
@@ -460,8 +458,6 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_poff = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
         p->off_plen = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
     }
-    p->off_stS = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(double));
-    p->off_stC = off;  off = align256(off + (size_t)kFinSplit * k * d * sizeof(int32_t));
     p->off_jt = off;   off = align256(off + (size_t)finalize_blocks(k, d) * sizeof(double));
     if (p->mixed) {
         p->off_xs = off;   off = align256(off + sizeof(XStats));

@@ -9,91 +9,9 @@
 
 namespace km {
 
-// Stage 1: block (c, s) sums partial slots [s*G/S, (s+1)*G/S) for the 64
-// elements 64c .. 64c+63 of the flat k*d sum array (S = kFinSplit).  Its 4
-// waves take consecutive quarters of that slot range, each in increasing slot
-// order over coalesced 512-byte rows; the quarters are then added in wave
-// order.  Counts travel alongside (per element, from its label's slots).
-__global__ __launch_bounds__(256) void finalize_partial_kernel(FinArgs a)
-{
-    __shared__ double sS[4][64];
-    __shared__ int32_t sC[4][64];
-    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t kd = (int64_t)a.k * a.d;
-    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-    const bool valid = e < kd;
-    const int j = valid ? (int)(e / a.d) : 0;
-    const int split = blockIdx.y;
-    const int lo = (int)(((int64_t)split * a.G) / kFinSplit);
-    const int hi = (int)(((int64_t)(split + 1) * a.G) / kFinSplit);
-    const int s0 = lo + (int)(((int64_t)wave * (hi - lo)) / 4);
-    const int s1 = lo + (int)(((int64_t)(wave + 1) * (hi - lo)) / 4);
-    double acc = 0.0;
-    int32_t cacc = 0;
-    if (valid) {
-        const double* p = a.part.S + e;
-        const int32_t* pc = a.part.cnt + j;
-#pragma unroll 16
-        for (int b = s0; b < s1; ++b) {
-            acc += p[(size_t)b * kd];
-            cacc += pc[(size_t)b * a.k];
-        }
-    }
-    sS[wave][lane] = acc;
-    sC[wave][lane] = cacc;
-    __syncthreads();
-    if (wave == 0 && valid) {
-        const double S = ((sS[0][lane] + sS[1][lane]) + sS[2][lane]) + sS[3][lane];
-        const int32_t c = sC[0][lane] + sC[1][lane] + sC[2][lane] + sC[3][lane];
-        a.stageS[(size_t)split * kd + e] = S;
-        a.stageC[(size_t)split * kd + e] = c;
-    }
-}
-
-// Stage 2: the kFinSplit stage sums of each element in split order, then the
-// mean with the empty-cluster rule.  With jmode 1 each block also writes its
-// share of sum_j (cnt_j |c_j|^2 - 2 c_j . S_j) (xor tree over its 64 elements).
-__global__ __launch_bounds__(64) void finalize_combine_kernel(FinArgs a)
-{
-    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
-
-    const int lane = threadIdx.x;
-    const int64_t kd = (int64_t)a.k * a.d;
-    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-    double term = 0.0;
-    if (e < kd) {
-        const int j = (int)(e / a.d);
-        const int f = (int)(e - (int64_t)j * a.d);
-        double S = a.stageS[e];
-        int64_t c = a.stageC[e];
-#pragma unroll
-        for (int s = 1; s < kFinSplit; ++s) {
-            S += a.stageS[(size_t)s * kd + e];
-            c += a.stageC[(size_t)s * kd + e];
-        }
-        const float old = a.C_old[(size_t)j * a.ld_old + f];
-        const float v = (c > 0) ? (float)(S / (double)c) : old;
-        a.C_new[(size_t)j * a.ld_new + f] = v;
-        if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
-        if (a.counts && f == 0) a.counts[j] = c;
-        const double co = (double)old;
-        term = (double)c * co * co - 2.0 * co * S;
-    }
-    if (a.jmode == 1) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
-        if (lane == 0) a.Jterm[blockIdx.x] = term;
-    }
-}
-
 // Objective, changed count and the tolerance decision (one wave).
-__global__ __launch_bounds__(64) void finalize_objective_kernel(FinArgs a)
+__device__ __forceinline__ void objective_wave(const FinArgs& a, int lane)
 {
-    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
-    const int lane = threadIdx.x;
     double J = 0.0;
     int64_t ch = 0;
     // unrolled: the loads of several strides are in flight together (the
@@ -127,6 +45,78 @@ __global__ __launch_bounds__(64) void finalize_objective_kernel(FinArgs a)
             c->changed_last = ch;
             c->iters_done = t + 1;
         }
+    }
+}
+
+__global__ __launch_bounds__(64) void finalize_objective_kernel(FinArgs a)
+{
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
+    objective_wave(a, threadIdx.x);
+}
+
+// The whole finalize of an iteration in one launch: block c (kFinWaves
+// waves) sums the partial slots of the 64 elements 64c .. 64c+63 of the flat
+// k*d sum array, wave w taking the slots [w G / W, (w+1) G / W) in increasing
+// order over coalesced 512-byte rows; the wave sums are added in wave order,
+// then the mean with the empty-cluster rule (and, with jmode 1, the block's
+// share of the objective).  With jmode 0 and want_J one more block reduces
+// the per-sample objective partials and the changed count and updates the
+// control block; none of that depends on this launch's other blocks.
+constexpr int kFinWaves = 16;
+__global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
+{
+    __shared__ double sS[kFinWaves][64];
+    __shared__ int32_t sC[kFinWaves][64];
+    if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if ((int)blockIdx.x == finalize_blocks(a.k, a.d)) {
+        if (wave == 0) objective_wave(a, lane);
+        return;
+    }
+    const int64_t kd = (int64_t)a.k * a.d;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = e < kd;
+    const int j = valid ? (int)(e / a.d) : 0;
+    const int s0 = (int)(((int64_t)wave * a.G) / kFinWaves);
+    const int s1 = (int)(((int64_t)(wave + 1) * a.G) / kFinWaves);
+    double acc = 0.0;
+    int32_t cacc = 0;
+    if (valid) {
+        const double* p = a.part.S + e;
+        const int32_t* pc = a.part.cnt + j;
+#pragma unroll 16
+        for (int b = s0; b < s1; ++b) {
+            acc += p[(size_t)b * kd];
+            cacc += pc[(size_t)b * a.k];
+        }
+    }
+    sS[wave][lane] = acc;
+    sC[wave][lane] = cacc;
+    __syncthreads();
+    if (wave != 0) return;
+    double term = 0.0;
+    if (valid) {
+        double S = sS[0][lane];
+        int64_t c = sC[0][lane];
+#pragma unroll
+        for (int w = 1; w < kFinWaves; ++w) {
+            S += sS[w][lane];
+            c += sC[w][lane];
+        }
+        const int f = (int)(e - (int64_t)j * a.d);
+        const float old = a.C_old[(size_t)j * a.ld_old + f];
+        const float v = (c > 0) ? (float)(S / (double)c) : old;
+        a.C_new[(size_t)j * a.ld_new + f] = v;
+        if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
+        if (a.counts && f == 0) a.counts[j] = c;
+        const double co = (double)old;
+        term = (double)c * co * co - 2.0 * co * S;
+    }
+    if (a.jmode == 1) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
+        if (lane == 0) a.Jterm[blockIdx.x] = term;
     }
 }
 
@@ -263,12 +253,11 @@ __global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __rest
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s)
 {
     const int grid = finalize_blocks(a.k, a.d);
-    hipLaunchKernelGGL(finalize_partial_kernel, dim3(grid, kFinSplit), dim3(256), 0, s, a);
+    const bool obj_block = a.want_J && a.jmode == 0;
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid + (obj_block ? 1 : 0)), dim3(64 * kFinWaves), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_combine_kernel, dim3(grid), dim3(64), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.want_J) {
+    if (a.want_J && a.jmode == 1) {
         hipLaunchKernelGGL(finalize_objective_kernel, dim3(1), dim3(64), 0, s, a);
         e = hipGetLastError();
     }

@@ -12,10 +12,6 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxD8Plain = 16;       // plain path: d <= 128 (eight-feature chunks)
 
-// Finalize geometry: 64 elements per block; the partial slots are split
-// kFinSplit ways in a first stage, whose sums a second stage adds in order.
-constexpr int kFinSplit = 16;
-
 // Per-sample pass variants: assign only; update from stored labels with the
 // fused pass's tiles (so the two give bit-identical sums); fused assign +
 // update; update over label chunks with wider tiles (records beyond LDS).
@@ -78,8 +74,6 @@ struct BatchWork {
 
 struct FinArgs {
     Partials part;
-    double* stageS;       // [kFinSplit][k*d] first-stage sums
-    int32_t* stageC;      // [kFinSplit][k*d] first-stage counts (per element)
     int32_t G;            // number of per-label partial slots (sums, counts)
     int32_t GJ;           // number of objective / changed partial slots
     int32_t k, d, D;
