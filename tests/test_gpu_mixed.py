@@ -65,6 +65,30 @@ def test_mixed_exact_ties_and_duplicates(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", ["separated", "all_tied"])
+def test_mixed_cascade_extremes(prec, case):
+    """Sweeps of more than two 64-centroid chunks screen first (FP8 plans
+    screen their open samples again in BF16) and refine the rest inside the
+    screen's band.  Tight, well separated blobs leave almost nothing open;
+    every centroid duplicated leaves every sample open down to the recheck.
+    Both give the FP32 path's labels."""
+    torch, B = _torch(), _bind()
+    if case == "separated":
+        X, C = datagen.blobs(20000, 48, 300, 300, 0.01, seed=31)
+    else:
+        X, C0 = datagen.blobs(20000, 48, 150, 150, 1.0, seed=32)
+        C = np.concatenate([C0, C0], 0)
+    say(f"cascade {case} {prec}")
+    lab_m = mixed_assign(torch, B, X, C, prec=prec)
+    lab_p, _, _ = run_assign(torch, B, X, C)
+    diff = np.flatnonzero(lab_m != lab_p)
+    assert diff.size == 0, f"{diff.size} labels differ from the FP32 path, first {diff[:5]}"
+    check_labels(lab_m, C, X, f"cascade {case}")
+    if case == "all_tied":
+        assert lab_m.max() < 150                # the lower index of each duplicate pair wins
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,d,k,iters", [(30000, 32, 48, 6), (12000, 128, 180, 4), (5000, 7, 11, 5)])
 def test_mixed_lloyd_equals_fp32(n, d, k, iters, prec):
     torch, B = _torch(), _bind()
