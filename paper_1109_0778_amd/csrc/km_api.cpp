@@ -294,7 +294,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     }
     RecheckArgs r{};
     r.X = X; r.Cp = Cp; r.n = p->n; r.d = p->d; r.k = p->k;
-    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = rq_ints(FMT_BF16);
+    r.rq = m.rq; r.rq_count = m.rq_count; r.rq_per_block = p->rq_per_block; r.rq_ints = kRqInts;
     r.nreg = G;
     r.labels = labels; r.changed_part = changed + p->mfma_passes() * G;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
@@ -468,7 +468,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_cs = off;   off = align256(off + sizeof(CStats));
         p->off_pcn = off;  off = align256(off + (size_t)prep_c_blocks(p->kpad) * sizeof(float));
         p->off_rqc = off;  off = align256(off + 2 * (size_t)p->grid_mfma * sizeof(int32_t));
-        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * rq_ints(FMT_BF16) * sizeof(int32_t));
+        p->off_rq = off;   off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * kRqInts * sizeof(int32_t));
         p->off_amb = off;  off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(int32_t));
         p->off_ambc = off; off = align256(off + (size_t)p->grid_mfma * sizeof(int32_t));
         p->off_ambk = off; off = align256(off + (size_t)p->grid_mfma * p->rq_per_block * sizeof(uint32_t));

@@ -228,7 +228,7 @@ void layout(km_batch* B)
             B->off_ab[i] = off;   off = al256(off + (size_t)kpad * 16 * D16 * sizeof(__bf16));
             B->off_bias[i] = off; off = al256(off + (size_t)kpad * sizeof(float));
             B->off_cs[i] = off;   off = al256(off + sizeof(CStats));
-            B->off_rq[i] = off;   off = al256(off + (size_t)nr * tpm * kMixTile * rq_ints(FMT_BF16) * sizeof(int32_t));
+            B->off_rq[i] = off;   off = al256(off + (size_t)nr * tpm * kMixTile * kRqInts * sizeof(int32_t));
             B->off_rqc[i] = off;  off = al256(off + 2 * (size_t)nr * sizeof(int32_t));
             B->off_chg[i] = off;  off = al256(off + (size_t)(1 + kBatchRecheckSplit) * nr * sizeof(int32_t));
             B->off_jt[i] = off;   off = al256(off + (size_t)finalize_blocks(x.k, x.d) * sizeof(double));
@@ -315,7 +315,7 @@ km_status upload(km_batch* B)
         mm.ctrl = nullptr; mm.iter = 0; mm.count_changed = 0;
         RecheckArgs& r = b.r;
         r.X = x.X; r.Cp = reinterpret_cast<const float*>(ws + B->off_cp[i]); r.n = x.n; r.d = x.d; r.k = x.k;
-        r.rq = mm.rq; r.rq_count = mm.rq_count; r.rq_per_block = mm.rq_per_block; r.rq_ints = rq_ints(FMT_BF16);
+        r.rq = mm.rq; r.rq_count = mm.rq_count; r.rq_per_block = mm.rq_per_block; r.rq_ints = kRqInts;
         r.nreg = nr; r.labels = x.labels; r.changed_part = chg + nr; r.ctrl = nullptr; r.iter = 0; r.count_changed = 0;
         b.Cp = r.Cp;
         b.D = 8 * d8_of(x.d);

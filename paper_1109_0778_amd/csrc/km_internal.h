@@ -170,14 +170,14 @@ constexpr int kMixNBScreen = 2;
 __host__ __device__ constexpr int mix_nb(int stage) { return stage == 1 || stage == 2 ? kMixNBScreen : kMixNB; }
 __host__ __device__ constexpr int mix_tile(int stage) { return kMixWaves * mix_nb(stage) * 32; }
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
-// Candidates kept per lane (half a sample's rows); the FP8 band is about 16
-// times wider than the BF16 one, so it keeps more.
-__host__ __device__ constexpr int cand_cap(int fmt) { return fmt == FMT_FP8 ? 23 : 7; }
-__host__ __device__ constexpr int cand_slots(int fmt) { return cand_cap(fmt) + 8; }   // room for 8 appends
+// Candidates kept per lane (half a sample's rows).  Candidate lists are only
+// built by BF16 sweeps (an FP8 plan's open samples get a BF16 screen first).
+constexpr int kCandCap = 7;
+constexpr int kCandSlots = kCandCap + 8;        // room for 8 appends
 // Recheck entry: sample, count, 2 pad, then the candidate ids, 16-byte
-// aligned and rounded up to a multiple of 8 (read 8 at a time).
+// aligned and rounded up to a multiple of 8.
 constexpr int kRqHead = 4;
-__host__ __device__ constexpr int rq_ints(int fmt) { return kRqHead + (2 * cand_cap(fmt) + 7) / 8 * 8; }
+constexpr int kRqInts = kRqHead + (2 * kCandCap + 7) / 8 * 8;
 constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
 constexpr int kXStatBlocks = 256;
 constexpr int kFmaxBlocks = 1024;               // FP8 per-feature maxima

@@ -615,9 +615,9 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     constexpr int TILE = mix_tile(STAGE);   // samples per block per tile
     constexpr int CHB = kMixCK * ROWB;     // bytes of one chunk buffer
     constexpr int V = DP * ES / 16;        // uint4 per centroid row
-    constexpr int CAP = cand_cap(FMT);
-    constexpr int SLOTS = cand_slots(FMT);
-    constexpr int RQI = rq_ints(FMT);
+    constexpr int CAP = kCandCap;
+    constexpr int SLOTS = kCandSlots;
+    constexpr int RQI = kRqInts;
     constexpr int PF = (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
     unsigned char* Abuf = smem;                                                   // [2][CK][ROWB]
     float* bbuf = reinterpret_cast<float*>(smem + 2 * CHB);                       // [2][CK]
@@ -1310,7 +1310,7 @@ size_t mfma_lds_bytes(int fmt, int D16, int stage)
 {
     const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
     return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
-           (stage == 1 || stage == 2 ? 0 : (size_t)kMixWaves * mix_nb(stage) * cand_slots(fmt) * 64 * sizeof(uint32_t));
+           (stage == 1 || stage == 2 ? 0 : (size_t)kMixWaves * mix_nb(stage) * kCandSlots * 64 * sizeof(uint32_t));
 }
 
 template <int D16, int FMT, int STAGE>
