@@ -68,6 +68,41 @@ def pin_golden_lloyd(lib):
     assert r0["iters"] == g["iters_tol0"], r0["iters"]
 
 
+def pin_golden_tolerance(lib):
+    """Tolerance mode: the relative-decrease rule (not only unchanged labels)
+    decides the stop, with equality counting as a stop."""
+    g = _golden("lloyd_tol.json")
+    X = np.array(g["X"], np.float32)
+    C0 = np.array(g["C0"], np.float64)
+    r = oracle.lloyd(X, C0, 3, lib=lib)
+    assert r["J"].tolist() == g["J"], r["J"]
+    assert r["changed"].tolist() == g["changed"], r["changed"]
+    for tol, iters in g["stops"]:
+        rt = oracle.lloyd(X, C0, 10, tol=tol, lib=lib)
+        assert rt["iters"] == iters, (tol, rt["iters"], iters)
+        assert rt["J"].tolist() == g["J"][:iters]
+        if iters == 2:
+            assert rt["labels"].tolist() == g["labels_after_t1"]
+            assert np.array_equal(rt["C"], np.array(g["C_after_t1"], np.float64))
+            assert rt["counts"].tolist() == g["counts_after_t1"]
+
+
+def pin_near_tie_margin(lib, margin_fn=None):
+    """The near-tie margin against hand-worked values (exact ties, a shared
+    zero distance, no second centroid, and both sides of the 1e-6 band)."""
+    fn = margin_fn or oracle.near_tie_margin
+    g = _golden("near_tie_margin.json")
+    f = lambda v: np.array([float(x) for x in v], np.float64)   # noqa: E731  ("inf" -> inf)
+    m = np.asarray(fn(f(g["d1"]), f(g["d2"])), np.float64)
+    want = f(g["margin"])
+    assert m.shape == want.shape
+    assert not np.isnan(m).any(), m
+    exact = np.isinf(want) | (want == 0.0)
+    assert np.array_equal(m[exact], want[exact]), (m, want)
+    np.testing.assert_allclose(m[~exact], want[~exact], rtol=1e-8, atol=0)
+    assert ((m < 1e-6) == np.array(g["near_tie_1e-6"])).all(), m
+
+
 def pin_golden_empty(lib):
     g = _golden("empty_cluster.json")
     X = np.array(g["X"], np.float32)
@@ -243,7 +278,7 @@ def pin_lloyd_invariants(lib):
 
 
 ALL_PINS = [
-    pin_golden_assign, pin_golden_lloyd, pin_golden_empty, pin_assign_vs_scipy,
+    pin_golden_assign, pin_golden_lloyd, pin_golden_tolerance, pin_near_tie_margin, pin_golden_empty, pin_assign_vs_scipy,
     pin_lloyd_vs_sklearn, pin_assign_bruteforce, pin_lloyd_bruteforce,
     pin_k1_closed_form, pin_k_equals_n, pin_blobs_recovered, pin_scale_invariance,
     pin_permutation, pin_lloyd_invariants,

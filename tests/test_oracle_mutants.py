@@ -23,6 +23,12 @@ MUTANTS = {
     "transposed": ("C + (size_t)j * (size_t)d, d);", "C + (size_t)j, d);"),
     # objective taken from the second-nearest centroid
     "objective_term": ("best[i] = b1;", "best[i] = (k > 1) ? b2 : b1;"),
+    # tolerance rule relative to the new objective instead of the previous one
+    "tol_denominator": ("(J_prev - J) <= tol * J_prev", "(J_prev - J) <= tol * J"),
+    # tolerance rule with a strict comparison (an exact equality no longer stops)
+    "tol_strict": ("(J_prev - J) <= tol * J_prev", "(J_prev - J) < tol * J_prev"),
+    # the previous objective is never advanced
+    "tol_stale_prev": ("        J_prev = J;\n", "\n"),
     # the update sums into the wrong label
     "update_index": ("double *s = S + (size_t)j * (size_t)d;",
                      "double *s = S + (size_t)((j + 1) % k) * (size_t)d;"),
@@ -44,3 +50,26 @@ def test_mutant_is_caught(name, tmp_path):
         except (AssertionError, ValueError):
             caught.append(pin.__name__)
     assert caught, f"no pin catches mutant {name}"
+
+
+# Mistakes in the near-tie margin (Python side of the oracle): each replaces
+# one expression inside near_tie_margin.
+PY_MUTANTS = {
+    "margin_sign": ("(d2nd - dmin) / den", "(dmin - d2nd) / den"),
+    "margin_half": ("den = dmin + d2nd", "den = 2.0 * (dmin + d2nd)"),
+    "margin_relative_to_d2": ("den = dmin + d2nd", "den = d2nd"),
+    "margin_zero_case": ("m = np.where(den == 0.0, 0.0, m)", "m = m"),
+    "margin_inf_case": ("m = np.where(np.isinf(d2nd), np.inf, m)", "m = m"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_margin_mutant_is_caught(name):
+    import inspect
+    old, new = PY_MUTANTS[name]
+    src = inspect.getsource(oracle.oracle.near_tie_margin)
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    ns = {"np": __import__("numpy")}
+    exec(src.replace(old, new), ns)
+    with pytest.raises(AssertionError):
+        oracle_pins.pin_near_tie_margin(None, margin_fn=ns["near_tie_margin"])
