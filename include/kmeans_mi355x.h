@@ -101,7 +101,9 @@ size_t km_plan_workspace_bytes(const km_plan *plan);
  * Bind caller-owned device memory as the plan's workspace.  `ws` must be
  * 256-byte aligned and at least km_plan_workspace_bytes() long
  * (KM_EWORKSPACE otherwise).  The workspace is borrowed until the plan is
- * destroyed or another workspace is bound.
+ * destroyed or another workspace is bound.  Binding a different workspace
+ * drops a graph captured by km_plan_use_graphs (its kernels hold the old
+ * addresses); the next kmeans_lloyd captures afresh.
  */
 km_status km_plan_set_workspace(km_plan *plan, void *ws, size_t bytes);
 
@@ -131,7 +133,8 @@ km_status kmeans_assign(km_plan *plan, const float *X, const float *C,
  * Update step (the predicated per-label reduce of section 2.3 and the mean of
  * section 2.1) from given labels.
  *   X       [n x d] FP32 samples
- *   labels  [n] int32 labels; entries outside [0, k) are ignored
+ *   labels  [n] int32 labels; entries outside [0, k) are ignored, or, in the
+ *           debug-validate mode of km_plan_set_validate, rejected
  *   C_old   [k x d] FP32 centroids kept for empty clusters
  *   C_new   [k x d] FP32 output: fl32(S_j / cnt_j) or C_old[j] if cnt_j = 0
  *           (may alias C_old)
@@ -140,6 +143,15 @@ km_status kmeans_assign(km_plan *plan, const float *X, const float *C,
 km_status kmeans_update(km_plan *plan, const float *X, const int32_t *labels,
                         const float *C_old, float *C_new, int64_t *counts,
                         hipStream_t stream);
+
+/*
+ * Debug-validate mode of kmeans_update (off by default).  With enable != 0,
+ * kmeans_update first counts the labels outside [0, k) on the device, waits
+ * on its stream for the count, and returns KM_EINVAL (nothing more enqueued,
+ * outputs untouched, the count in km_last_error()) when there is any.  Off,
+ * such labels are skipped without a check and the call stays asynchronous.
+ */
+km_status km_plan_set_validate(km_plan *plan, int32_t enable);
 
 /*
  * Lloyd iterations, each one assign (with C_t) fused with the reduce and
@@ -182,8 +194,10 @@ typedef struct km_batch km_batch;
 /*
  * Create a batch over `count` instances (host array, copied).  Validates every
  * instance like km_plan_create (KM_EINVAL), needs d <= 128 and a per-label
- * record k * d * 8 bytes of at most 80 KiB (KM_ENOTSUP otherwise), FP32
- * distances only (KM_ENOTSUP for other precisions).  Queries the device.
+ * record k * d * 8 bytes of at most 80 KiB (KM_ENOTSUP otherwise).  Precision
+ * KM_FP32 (direct-form FP32 distances) or KM_BF16 (BF16 MFMA distances with
+ * the proven-band FP32 recheck, labels equal to the FP32 batch's); KM_ENOTSUP
+ * for KM_FP8_E4M3.  Queries the device.
  */
 km_status km_batch_create(const km_instance *inst, int32_t count, km_precision prec,
                           km_batch **out);

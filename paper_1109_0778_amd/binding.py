@@ -22,7 +22,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_plan_destroy", "km_last_error", "kmeans_assign", "kmeans_update",
            "kmeans_lloyd", "km_plan_enable_timing", "km_plan_kernel_times", "km_plan_recheck_count",
-           "km_plan_use_graphs", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
+           "km_plan_use_graphs", "km_plan_set_validate", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
            "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched"]
 
 
@@ -86,6 +86,8 @@ def lib():
         L.kmeans_lloyd_batched.argtypes = [P, I32, P]
         L.km_plan_use_graphs.restype = I32
         L.km_plan_use_graphs.argtypes = [P, I32]
+        L.km_plan_set_validate.restype = I32
+        L.km_plan_set_validate.argtypes = [P, I32]
         L.km_plan_recheck_count.restype = I32
         L.km_plan_recheck_count.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
         _lib = L
@@ -152,6 +154,19 @@ class Plan:
     def use_graphs(self, enable: bool = True):
         """km_plan_use_graphs: capture kmeans_lloyd calls into HIP graphs."""
         _check(lib().km_plan_use_graphs(self._h, int(bool(enable))))
+
+    def set_validate(self, enable: bool = True):
+        """km_plan_set_validate: kmeans_update rejects labels outside [0, k)."""
+        _check(lib().km_plan_set_validate(self._h, int(bool(enable))))
+
+    def rebind_workspace(self):
+        """Allocate a fresh workspace tensor and bind it (km_plan_set_workspace)."""
+        import torch
+        nbytes = self.workspace_bytes
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off:off + nbytes]
+        _check(lib().km_plan_set_workspace(self._h, self.workspace.data_ptr(), nbytes))
 
     def enable_timing(self, cap: int):
         """km_plan_enable_timing: time up to ``cap`` launches of the per-sample pass."""

@@ -85,7 +85,8 @@ struct km_plan {
     // workspace
     unsigned char* ws;
     size_t ws_bytes;
-    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, off_pbad, total;
+    size_t off_ctrl, off_cp, off_pS, off_pcnt, off_pJ, off_pch, total;
+    bool validate = false;   // kmeans_update checks its labels first (debug-validate mode)
     // optional per-launch timing of the per-sample pass
     std::vector<hipEvent_t> ev;   // 2 per launch
     int32_t ev_used = 0;
@@ -137,7 +138,6 @@ Partials partials_of(const km_plan* p)
     pt.cnt = reinterpret_cast<int32_t*>(p->ws + p->off_pcnt);
     pt.J = reinterpret_cast<double*>(p->ws + p->off_pJ);
     pt.changed = reinterpret_cast<int32_t*>(p->ws + p->off_pch);
-    pt.bad = reinterpret_cast<int32_t*>(p->ws + p->off_pbad);
     return pt;
 }
 
@@ -451,7 +451,6 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->off_pcnt = off; off = align256(off + (size_t)p->GS() * k * sizeof(int32_t));
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
     p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, 3 * p->grid_mfma + p->grid_rc) * sizeof(int32_t));
-    p->off_pbad = off; off = align256(off + (size_t)std::max(p->grid, p->GS()) * sizeof(int32_t));
     if (p->chunked) {
         p->off_perm = off; off = align256(off + (size_t)n * sizeof(int32_t));
         p->off_plab = off; off = align256(off + (size_t)n * sizeof(int32_t));
@@ -503,6 +502,8 @@ km_status km_plan_set_workspace(km_plan* plan, void* ws, size_t bytes)
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(KM_EWORKSPACE, "workspace must be 256-byte aligned");
     if (bytes < plan->total)
         return fail(KM_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu the plan needs", bytes, plan->total);
+    // a captured graph holds the old workspace's addresses in its kernel arguments
+    if (plan->ws != static_cast<unsigned char*>(ws)) plan->drop_graph();
     plan->ws = static_cast<unsigned char*>(ws);
     plan->ws_bytes = bytes;
     return KM_OK;
@@ -551,8 +552,26 @@ km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, co
     if (!aligned16(X)) return fail(KM_EINVAL, "X must be 16-byte aligned");
     if ((st = set_device(plan)) != KM_OK) return st;
 
+    hipError_t e;
+    if (plan->validate) {
+        // debug-validate mode: count labels outside [0, k) before anything
+        // else is enqueued, so a rejected call leaves the outputs untouched
+        int32_t* part = reinterpret_cast<int32_t*>(plan->ws + plan->off_pch);
+        const int cap = std::max(plan->grid, 3 * plan->grid_mfma + plan->grid_rc);
+        int g = 0;
+        if ((e = launch_count_bad_labels(labels, plan->n, plan->k, part, cap, &g, stream)) != hipSuccess)
+            return hip_fail(e, "label check launch");
+        std::vector<int32_t> v((size_t)g);
+        if ((e = hipMemcpyAsync(v.data(), part, v.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(label check)");
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        int64_t bad = 0;
+        for (int32_t c : v) bad += c;
+        if (bad > 0)
+            return fail(KM_EINVAL, "%lld labels lie outside [0, %d)", (long long)bad, plan->k);
+    }
     PassArgs a = pass_args(plan, X, nullptr, const_cast<int32_t*>(labels));
-    hipError_t e = enqueue_update(plan, a, stream);
+    e = enqueue_update(plan, a, stream);
     if (e != hipSuccess) return hip_fail(e, "update pass launch");
     FinArgs f = fin_args(plan);
     f.C_old = C_old; f.ld_old = plan->d; f.C_new = C_new; f.ld_new = plan->d; f.Cp_out = nullptr;
@@ -616,6 +635,14 @@ km_status kmeans_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels,
             *iters_done = v;
         }
     }
+    return KM_OK;
+}
+
+km_status km_plan_set_validate(km_plan* plan, int32_t enable)
+{
+    g_err.clear();
+    if (!plan) return fail(KM_EINVAL, "plan is NULL");
+    plan->validate = enable != 0;
     return KM_OK;
 }
 

@@ -64,7 +64,7 @@ struct km_batch {
     int order = 1;         // 0: instance order, 1: decreasing work per block
     // derived layout
     std::vector<int> nslots;
-    std::vector<size_t> off_cp, off_S, off_cnt, off_J, off_ch, off_bad;
+    std::vector<size_t> off_cp, off_S, off_cnt, off_J, off_ch;
     std::vector<BatchWork> work;
     std::vector<BatchFinWork> fwork;
     std::vector<Group> groups;
@@ -157,7 +157,7 @@ void layout(km_batch* B)
     const int m = (int)B->inst.size();
     B->nslots.assign(m, 0);
     B->off_cp.assign(m, 0); B->off_S.assign(m, 0); B->off_cnt.assign(m, 0);
-    B->off_J.assign(m, 0); B->off_ch.assign(m, 0); B->off_bad.assign(m, 0);
+    B->off_J.assign(m, 0); B->off_ch.assign(m, 0);
     std::map<std::pair<int, size_t>, std::vector<BatchWork>> by_group;
     std::map<std::pair<int, size_t>, std::vector<double>> costs;
     B->fwork.clear();
@@ -186,7 +186,6 @@ void layout(km_batch* B)
         B->off_cnt[i] = off; off = al256(off + (size_t)nb * x.k * sizeof(int32_t));
         B->off_J[i] = off;   off = al256(off + (size_t)nb * sizeof(double));
         B->off_ch[i] = off;  off = al256(off + (size_t)nb * sizeof(int32_t));
-        B->off_bad[i] = off; off = al256(off + (size_t)nb * sizeof(int32_t));
     }
     emit_groups(by_group, costs, B->order, B->work, B->groups);
     if (B->mixed) {
@@ -269,7 +268,6 @@ km_status upload(km_batch* B)
         pt.cnt = reinterpret_cast<int32_t*>(ws + B->off_cnt[i]);
         pt.J = reinterpret_cast<double*>(ws + B->off_J[i]);
         pt.changed = reinterpret_cast<int32_t*>(ws + B->off_ch[i]);
-        pt.bad = reinterpret_cast<int32_t*>(ws + B->off_bad[i]);
         float* Cp = reinterpret_cast<float*>(ws + B->off_cp[i]);
         PassArgs& a = pa[i];
         std::memset(&a, 0, sizeof a);

@@ -227,7 +227,6 @@ __global__ void pad_centroids_kernel(const float* __restrict__ C, int32_t k, int
     if (ctrl != nullptr && e == 0) {
         ctrl->stop_iter = INT_MAX;
         ctrl->iters_done = 0;
-        ctrl->bad_labels = 0;
         ctrl->J_prev = 0.0;
         ctrl->changed_last = 0;
     }
@@ -248,6 +247,35 @@ __global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __rest
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
+}
+
+// Debug-validate mode of the update from given labels: how many labels lie
+// outside [0, k).  Block b counts a grid-stride share and writes part[b]; the
+// host adds the partials (integers: any order gives the same total).
+__global__ __launch_bounds__(256) void count_bad_labels_kernel(const int32_t* __restrict__ labels, int64_t n,
+                                                               int32_t k, int32_t* __restrict__ part)
+{
+    __shared__ int32_t red[4];
+    int32_t c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int32_t L = labels[i];
+        c += (L < 0 || L >= k) ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_count_bad_labels(const int32_t* labels, int64_t n, int32_t k, int32_t* part, int nblk,
+                                   int* grid_used, hipStream_t s)
+{
+    const int64_t want = (n + 255) / 256;
+    const int grid = (int)(want < nblk ? (want > 0 ? want : 1) : nblk);
+    *grid_used = grid;
+    hipLaunchKernelGGL(count_bad_labels_kernel, dim3(grid), dim3(256), 0, s, labels, n, k, part);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s)

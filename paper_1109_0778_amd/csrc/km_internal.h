@@ -21,8 +21,7 @@ enum Mode : int { MODE_ASSIGN = 0, MODE_UPDATE = 1, MODE_FUSED = 2 };
 struct Ctrl {
     int32_t stop_iter;    // iteration at which a tolerance stop was decided (INT32_MAX: none)
     int32_t iters_done;   // iterations completed
-    int32_t bad_labels;   // update-only calls: labels outside [0, k) seen
-    int32_t pad0;
+    int32_t pad0, pad2;
     double J_prev;        // objective of the previous iteration
     int64_t changed_last; // labels changed in the last completed iteration
     double pad1[12];
@@ -35,7 +34,6 @@ struct Partials {
     int32_t* cnt;       // [G][k]   per-label counts
     double* J;          // [G]      objective partials
     int32_t* changed;   // [G]      changed-label partials
-    int32_t* bad;       // [G]      invalid-label partials (update-only)
 };
 
 struct PassArgs {
@@ -126,6 +124,10 @@ hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* plab, int
 hipError_t launch_part_update(int D8, const PassArgs& a, dim3 grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce_objective(const double* part_J, int32_t G, double* out, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStream_t s);
+// Labels outside [0, k): per-block counts of a grid-stride scan (grid <= nblk
+// blocks), written to part[0 .. grid); returns the grid used.
+hipError_t launch_count_bad_labels(const int32_t* labels, int64_t n, int32_t k, int32_t* part, int nblk,
+                                   int* grid_used, hipStream_t s);
 
 // Samples per lane in the plain pass.  One: measured on MI355X at d = 64,
 // k = 64, two samples per lane (sharing each SGPR centroid operand) ran 18%

@@ -200,7 +200,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     constexpr int TILE = kBlock * R;
     __shared__ double redJ[kWaves];
     __shared__ int32_t redC[kWaves];
-    __shared__ int32_t redB[kWaves];
 
     if (a.ctrl != nullptr && a.ctrl->stop_iter < a.iter) return;  // converged earlier
 
@@ -226,7 +225,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     __syncthreads();
 
     double Jl = 0.0;
-    int32_t changed = 0, bad = 0;
+    int32_t changed = 0;
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t t_last = t_end < ntiles ? t_end : ntiles;
     const int64_t nmine = t_first < t_last ? (t_last - t_first + t_step - 1) / t_step : 0;
@@ -280,8 +279,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     } else if constexpr (UPD) {
         // steps of UT of the block's tiles: every wave reads the whole step's
         // labels (INT_MIN: past the last sample), the next step's in flight
-        // while this one is added; wave w counts the invalid labels of row
-        // group w of each tile
+        // while this one is added; labels outside [0, k) are skipped
         auto steps = [&](auto ut_c) {
             constexpr int UT = decltype(ut_c)::value;
             constexpr int NL = UT * TILE / 64;
@@ -309,10 +307,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
 #pragma unroll
                 for (int g = 0; g < NL; ++g) {
                     lab[g] = -1;
-                    if (L[g] != INT_MIN) {
-                        if (L[g] < 0 || L[g] >= k) bad += ((g % (TILE / 64)) == wave);
-                        else if (L[g] >= j0 && L[g] < j0 + kc) lab[g] = L[g] - j0;   // chunk-local label
-                    }
+                    if (L[g] != INT_MIN && L[g] >= j0 && L[g] < j0 + kc && L[g] < k)
+                        lab[g] = L[g] - j0;   // chunk-local label
                 }
                 // the step's samples are consecutive (one tile, or contiguous tiles)
                 const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)d;
@@ -346,19 +342,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
     for (int off = 32; off >= 1; off >>= 1) {
         Jl += __shfl_xor(Jl, off);
         changed += __shfl_xor(changed, off);
-        bad += __shfl_xor(bad, off);
     }
-    if (lane == 0) { redJ[wave] = Jl; redC[wave] = changed; redB[wave] = bad; }
+    if (lane == 0) { redJ[wave] = Jl; redC[wave] = changed; }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && !UPD) {
         double J = redJ[0];
-        int32_t c = redC[0], bb = redB[0];
-        for (int w = 1; w < kWaves; ++w) { J += redJ[w]; c += redC[w]; bb += redB[w]; }
-        if (!UPD) {
-            a.part.J[b] = J;
-            a.part.changed[b] = c;
-        }
-        if (chunk == 0) a.part.bad[b] = bb;
+        int32_t c = redC[0];
+        for (int w = 1; w < kWaves; ++w) { J += redJ[w]; c += redC[w]; }
+        a.part.J[b] = J;
+        a.part.changed[b] = c;
     }
 }
 

@@ -12,8 +12,8 @@ import pytest
 
 import oracle
 from paper_1109_0778_amd import datagen
-from test_gpu_plain import (REL_TOL, _bind, _torch, check_centroids, check_labels, run_assign,
-                            run_lloyd, run_update, say)
+from test_gpu_plain import (REL_TOL, _bind, _torch, check_centroids, check_labels, check_tolerance_run,
+                            no_near_ties, robust_tolerances, run_assign, run_lloyd, run_update, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -121,14 +121,21 @@ def test_mixed_stepwise_against_oracle(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n,d,k", [(8000, 8, 6), (20000, 16, 300)])   # one-pass sweep; screen + refine
-def test_mixed_tolerance_mode_matches_fp32(prec, n, d, k):
-    """Tolerance mode stops where the FP32 path stops: the changed-label counts
-    of every pass (screen, refine, recheck) add up to the FP32 pass's."""
+@pytest.mark.parametrize("n,d,k,seed", [(8000, 8, 6, 8), (6000, 16, 200, 7)])   # one-pass sweep; screen + refine
+def test_mixed_tolerance_mode_against_oracle(prec, n, d, k, seed):
+    """Tolerance mode of the mixed paths against oracle.lloyd(X, C0, 40, tol):
+    the changed-label counts of every pass (screen, refine, recheck) add up to
+    the stop decision, so stop iteration, labels, counts, objective history
+    and centroids follow the oracle's run; and they equal the FP32 path's."""
     torch, B = _torch(), _bind()
-    X, C = datagen.blobs(n, d, k, k, 1.0, seed=5)
-    for tol in (0.0, 1e-3):
+    X, C = datagen.blobs(n, d, k, k, 1.0, seed=seed)
+    full = oracle.lloyd(X, C.astype(np.float64), 40)
+    assert no_near_ties(X, C, full["iters"]) > 1e-5, "input has near-ties: pick another seed"
+    for tol in [0.0] + robust_tolerances(full["J"])[:2]:
+        say(f"mixed tolerance {prec} n={n} d={d} k={k} tol={tol:.6g}")
+        o = oracle.lloyd(X, C.astype(np.float64), 40, tol=tol)
         m = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(n, d, k, prec))
+        check_tolerance_run(m, o, X, f"{prec} tol={tol}")
         p = run_lloyd(torch, B, X, C, 40, tol=tol, plan=B.Plan(n, d, k, "fp32"))
         assert m["iters"] == p["iters"]
         assert np.array_equal(m["C"], p["C"]) and np.array_equal(m["labels"], p["labels"])
