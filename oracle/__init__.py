@@ -5,7 +5,7 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg use this
 package.  It shares no code with the GPU library and imports nothing from it.
 """
 from .oracle import (  # noqa: F401
-    build, assign, update, lloyd, near_tie_margin, num_threads, LIB_PATH,
+    build, assign, update, lloyd, objective, near_tie_margin, num_threads, LIB_PATH,
 )
 from . import ml  # noqa: F401,E402
 

@@ -163,6 +163,23 @@ int orc_lloyd(const float *X, const double *C0, int64_t n, int d, int k,
     return t;
 }
 
+/*
+ * Objective of given labels: J = sum_i d(x_i, c_{labels[i]}) (the J of the
+ * assign step when the labels are the nearest centroids), samples in
+ * increasing i.  Returns -1.0 if a label is out of range.
+ */
+double orc_objective(const float *X, const double *C, const int32_t *labels, int64_t n, int d, int k)
+{
+    double J = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t j = labels[i];
+        if (j < 0 || j >= k) return -1.0;
+        const double *cj = C + (size_t)j * (size_t)d;
+        J += sqdist(X + (size_t)i * (size_t)d, cj, d);
+    }
+    return J;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -46,6 +46,8 @@ def _lib(path: str = LIB_PATH):
         lib.orc_lloyd.restype = ctypes.c_int
         lib.orc_lloyd.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_double, P, P, P, P, P]
+        lib.orc_objective.restype = ctypes.c_double
+        lib.orc_objective.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
         lib.orc_num_threads.restype = ctypes.c_int
         _LIB[path] = lib
     return _LIB[path]
@@ -112,6 +114,18 @@ def lloyd(X, C0, max_iter: int, tol: float = -1.0, lib: str = LIB_PATH):
         raise MemoryError("orc_lloyd failed")
     return {"C": C, "labels": labels, "counts": counts, "J": J[:it].copy(),
             "changed": ch[:it].copy(), "iters": it}
+
+
+def objective(X, C, labels, lib: str = LIB_PATH) -> float:
+    """J of given labels against C (FP64)."""
+    X = _f32(X)
+    C = _f64(C)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    n, d = X.shape
+    J = _lib(lib).orc_objective(_p(X), _p(C), _p(labels), n, d, C.shape[0])
+    if J < 0:
+        raise ValueError("label out of range")
+    return float(J)
 
 
 def near_tie_margin(dmin, d2nd):

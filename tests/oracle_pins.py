@@ -296,3 +296,21 @@ def pin_tie_duplicates(lib):
 
 
 ALL_PINS.append(pin_tie_duplicates)
+
+
+def pin_objective(lib):
+    """J of given labels: the hand-worked value for the nearest labels, and
+    scipy's distances summed over arbitrary labels."""
+    from scipy.spatial.distance import cdist
+    g = _golden("assign_pythagorean.json")
+    X = np.array(g["X"], np.float32)
+    C = np.array(g["C"], np.float64)
+    assert oracle.objective(X, C, g["labels"], lib=lib) == g["J"]
+    assert oracle.objective(X, C, [1, 1, 0, 1], lib=lib) == 100 + 25 + 100 + 225
+    X, C = _rand_case(21, 400, 6, 9)
+    L = np.random.default_rng(22).integers(0, 9, 400)
+    D = cdist(X.astype(np.float64), C, "sqeuclidean")
+    np.testing.assert_allclose(oracle.objective(X, C, L, lib=lib), D[np.arange(400), L].sum(), rtol=1e-13)
+
+
+ALL_PINS.append(pin_objective)

@@ -29,6 +29,9 @@ MUTANTS = {
     "tol_strict": ("(J_prev - J) <= tol * J_prev", "(J_prev - J) < tol * J_prev"),
     # the previous objective is never advanced
     "tol_stale_prev": ("        J_prev = J;\n", "\n"),
+    # the objective of given labels uses the wrong centroid row
+    "objective_index": ("const double *cj = C + (size_t)j * (size_t)d;",
+                        "const double *cj = C + (size_t)((j + 1) % k) * (size_t)d;"),
     # the update sums into the wrong label
     "update_index": ("double *s = S + (size_t)j * (size_t)d;",
                      "double *s = S + (size_t)((j + 1) % k) * (size_t)d;"),
