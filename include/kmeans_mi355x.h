@@ -25,7 +25,8 @@
  *     (to return iters_done).
  *   - The library never allocates device memory.  Scratch comes from a
  *     caller-provided workspace of km_plan_workspace_bytes() bytes bound with
- *     km_plan_set_workspace().
+ *     km_plan_set_workspace(), or, for kmeans_lloyd_static, from one static
+ *     device array per GPU that the library's code object holds.
  *   - On any error nothing is enqueued, outputs are untouched, the status is
  *     returned and km_last_error() describes it.  No exception crosses the ABI.
  *   - Shape limits: 1 <= k <= n < 2^31, 1 <= d <= 1024 (the FP32 path
@@ -171,6 +172,34 @@ km_status km_plan_set_validate(km_plan *plan, int32_t enable);
 km_status kmeans_lloyd(km_plan *plan, const float *X, float *C, int32_t *labels,
                        int64_t *counts, double *obj_hist, int32_t max_iter,
                        double tol, int32_t *iters_done, hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as kmeans_lloyd (same arguments, kernels, launch order and results,
+ * always direct launches, no timing events), but with no workspace.  The
+ * plan's scratch lives in one library-owned device array of
+ * KM_STATIC_SCRATCH_BYTES, allocated per device when the library's code
+ * object is loaded and held until the process ends; its address is looked up
+ * (hipGetSymbolAddress) on the first call on each device.  No device memory
+ * is allocated or freed by the call.
+ *   - The plan needs no bound workspace; one that is bound is left untouched
+ *     and stays valid for kmeans_lloyd.
+ *   - km_plan_workspace_bytes(plan) must be at most KM_STATIC_SCRATCH_BYTES,
+ *     else KM_EWORKSPACE with nothing enqueued (64 MiB covers FP32 plans up
+ *     to e.g. n = 2^20, d = k = 64; mixed-precision plans keep a copy of X
+ *     in their scratch and rarely fit).
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (nothing in it needs to start at zero): calls that
+ *     overlap in time on one GPU (other streams, other threads, other plans)
+ *     race and corrupt each other's results.  Order them on one stream.
+ *   - With tol >= 0 and iters_done non-NULL the call waits on `stream`, as
+ *     kmeans_lloyd does (not possible under graph capture: pass NULL there).
+ */
+#define KM_STATIC_SCRATCH_BYTES (64u << 20)
+km_status kmeans_lloyd_static(km_plan *plan, const float *X, float *C, int32_t *labels,
+                              int64_t *counts, double *obj_hist, int32_t max_iter,
+                              double tol, int32_t *iters_done, hipStream_t stream);
 
 /*
  * Batched Lloyd: many independent k-means problems of different n, d and k

@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 # Entry points the header declares (checked by the ABI tests).
 EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_plan_destroy", "km_last_error", "kmeans_assign", "kmeans_update",
-           "kmeans_lloyd", "km_plan_enable_timing", "km_plan_kernel_times", "km_plan_recheck_count",
+           "kmeans_lloyd", "kmeans_lloyd_static", "km_plan_enable_timing", "km_plan_kernel_times", "km_plan_recheck_count",
            "km_plan_use_graphs", "km_plan_set_validate", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
            "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched"]
 
@@ -66,6 +66,8 @@ def lib():
         L.kmeans_update.argtypes = [P, P, P, P, P, P, P]
         L.kmeans_lloyd.restype = I32
         L.kmeans_lloyd.argtypes = [P, P, P, P, P, P, I32, F64, ctypes.POINTER(I32), P]
+        L.kmeans_lloyd_static.restype = I32
+        L.kmeans_lloyd_static.argtypes = [P, P, P, P, P, P, I32, F64, ctypes.POINTER(I32), P]
         L.km_plan_enable_timing.restype = I32
         L.km_plan_enable_timing.argtypes = [P, I32]
         L.km_plan_kernel_times.restype = I32
@@ -128,7 +130,8 @@ def _stream(stream):
 class Plan:
     """km_plan plus a workspace tensor it owns (allocated by torch)."""
 
-    def __init__(self, n: int, d: int, k: int, precision: str = "fp32", device=None):
+    def __init__(self, n: int, d: int, k: int, precision: str = "fp32", device=None,
+                 bind_workspace: bool = True):
         import torch
         self.n, self.d, self.k, self.precision = int(n), int(d), int(k), precision
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -137,6 +140,9 @@ class Plan:
             h = ctypes.c_void_p()
             _check(lib().km_plan_create(self.n, self.d, self.k, PRECISIONS[precision], ctypes.byref(h)))
             self._h = h
+            self.workspace = None
+            if not bind_workspace:
+                return
             nbytes = int(lib().km_plan_workspace_bytes(h))
             raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
             off = (-raw.data_ptr()) % 256
@@ -231,6 +237,25 @@ def kmeans_lloyd(plan: Plan, X, C, labels, counts=None, obj_hist=None, max_iter:
         _ptr(obj_hist, torch.float64, "obj_hist"), int(max_iter), float(tol), ctypes.byref(it),
         _stream(stream)))
     return int(it.value)
+
+
+def kmeans_lloyd_static(plan: Plan, X, C, labels, counts=None, obj_hist=None, max_iter: int = 1,
+                        tol: float = -1.0, stream=None) -> int:
+    """kmeans_lloyd on the library's static scratch (no workspace); returns iters_done."""
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    if obj_hist is not None and obj_hist.numel() < max_iter:
+        raise ValueError("obj_hist needs max_iter entries")
+    it = ctypes.c_int32(0)
+    _check(lib().kmeans_lloyd_static(
+        plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(C, torch.float32, "C", k * d),
+        _ptr(labels, torch.int32, "labels", n), _ptr(counts, torch.int64, "counts", k),
+        _ptr(obj_hist, torch.float64, "obj_hist"), int(max_iter), float(tol), ctypes.byref(it),
+        _stream(stream)))
+    return int(it.value)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20   # KM_STATIC_SCRATCH_BYTES
 
 
 class Batch:

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -90,6 +91,8 @@ struct km_plan {
     // optional per-launch timing of the per-sample pass
     std::vector<hipEvent_t> ev;   // 2 per launch
     int32_t ev_used = 0;
+    bool untimed = false;    // set while a call must not record timing events
+    bool timing_on() const { return !untimed && ev_used * 2 + 1 < (int32_t)ev.size(); }
     // optional graph of a whole kmeans_lloyd call, keyed by its arguments
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -144,7 +147,7 @@ Partials partials_of(const km_plan* p)
 // Launch the per-sample pass, bracketed by timing events when enabled.
 hipError_t timed_pass(km_plan* p, Mode mode, const PassArgs& a, dim3 grid, size_t lds, hipStream_t s)
 {
-    const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
+    const bool timed = p->timing_on();
     hipError_t e;
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
     e = launch_plain_pass(p->D8, mode, a, grid, lds, s);
@@ -278,7 +281,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m2.amb_key = nullptr;
     m2.amb_key_in = last_screen.amb_key;
     m2.changed_part = changed + (p->mfma_passes() - 1) * G;
-    const bool timed = p->ev_used * 2 + 1 < (int32_t)p->ev.size();
+    const bool timed = p->timing_on();
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
     if (p->cascade) {
         if ((e = launch_mfma_assign(p->fmt, 1, p->D16, m, G, s)) != hipSuccess) return e;
@@ -752,6 +755,101 @@ km_status km_plan_kernel_times(km_plan* plan, float* ms, int32_t cap, int32_t* c
         if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
     }
     *count = plan->ev_used;
+    return KM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of kmeans_lloyd: the plan's scratch (control block,
+// padded centroids, per-block partial records, queues) lives in one
+// library-owned device array instead of a caller-bound workspace.  Every GPU
+// the library runs on holds its own copy of the array from the moment the
+// code object is loaded until the process ends.
+
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[KM_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of this device's `scratch` (the host-side name is only a
+// stand-in); looked up once per device, with that device current.
+km_status scratch_of_device(int dev, unsigned char** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(KM_ENOTSUP, "device %d: static scratch supports devices 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+            return fail(KM_EHIP, "static scratch address %p is not 256-byte aligned", ptr);
+        g_scratch_dev[dev] = static_cast<unsigned char*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return KM_OK;
+}
+
+// Points the plan at the static scratch for the duration of one call, with
+// timing off, and restores its own workspace afterwards.
+struct StaticScratchScope {
+    km_plan* p;
+    unsigned char* ws;
+    size_t bytes;
+    bool untimed;
+    StaticScratchScope(km_plan* plan, unsigned char* s) : p(plan), ws(plan->ws), bytes(plan->ws_bytes), untimed(plan->untimed)
+    {
+        p->ws = s;
+        p->ws_bytes = KM_STATIC_SCRATCH_BYTES;
+        p->untimed = true;
+    }
+    ~StaticScratchScope()
+    {
+        p->ws = ws;
+        p->ws_bytes = bytes;
+        p->untimed = untimed;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+km_status kmeans_lloyd_static(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
+                              double* obj_hist, int32_t max_iter, double tol, int32_t* iters_done,
+                              hipStream_t stream)
+{
+    g_err.clear();
+    if (!plan) return fail(KM_EINVAL, "plan is NULL");
+    if (!X || !C || !labels) return fail(KM_EINVAL, "X, C and labels must be non-NULL");
+    if (!aligned16(X) || !aligned16(C)) return fail(KM_EINVAL, "X and C must be 16-byte aligned");
+    if (max_iter < 1) return fail(KM_EINVAL, "max_iter = %d must be >= 1", max_iter);
+    if (tol != tol) return fail(KM_EINVAL, "tol is NaN");
+    if (plan->total > (size_t)KM_STATIC_SCRATCH_BYTES)
+        return fail(KM_EWORKSPACE, "the plan needs %zu bytes of scratch; the static scratch holds %zu (use kmeans_lloyd "
+                    "with a bound workspace)", plan->total, (size_t)KM_STATIC_SCRATCH_BYTES);
+    km_status st = set_device(plan);
+    if (st != KM_OK) return st;
+    unsigned char* s = nullptr;
+    if ((st = scratch_of_device(plan->device, &s)) != KM_OK) return st;
+
+    StaticScratchScope scope(plan, s);
+    st = enqueue_lloyd(plan, X, C, labels, counts, obj_hist, max_iter, tol, stream);
+    if (st != KM_OK) return st;
+    if (iters_done) {
+        if (tol < 0.0) {
+            *iters_done = max_iter;
+        } else {
+            int32_t v = 0;
+            hipError_t e = hipMemcpyAsync(&v, &ctrl_of(plan)->iters_done, sizeof v, hipMemcpyDeviceToHost, stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(iters_done)");
+            if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            *iters_done = v;
+        }
+    }
     return KM_OK;
 }
 
