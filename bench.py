@@ -1,33 +1,40 @@
 #!/usr/bin/env python3
 """Throughput of the fused k-means Lloyd iteration on one MI355X.
 
-One step = one Lloyd iteration over the whole input: the per-sample pass
-(distances to every centroid, argmin label, per-label FP64 sums and counts,
-objective) and the finalize (fixed-order combine, mean, empty-cluster rule),
-all inside one kmeans_lloyd call of STEPS iterations with the input already
-resident in HBM.  The call is timed twice, launched directly and as one
-captured graph; the headline takes the faster when both give identical
-results.  Default workload: n = 2^20 samples, d = 64, k = 64, 64
-Gaussian blobs (sigma 1, centres uniform in [-10, 10]^d, seed 1), k initial
-centroids sampled without replacement, 20 iterations, FP32 distances.
+One step = one Lloyd iteration over the whole input: the distance pass
+(distances to every centroid, argmin label), the per-label FP64 sums and
+counts, the objective and the finalize (fixed-order combine, mean, empty
+rule), inside one kmeans_lloyd call of STEPS iterations with the input
+already resident in HBM.
 
-Prints ONE JSON line on stdout (diagnostics go to stderr).  Besides the timed
+Headline workload (default ``--workload bf16``): n = 2^22 samples, d = 128,
+k = 1024, 1024 Gaussian blobs (sigma 2, centres uniform in [-10, 10]^d,
+seed 2), k initial centroids sampled without replacement, 20 iterations;
+distances as a BF16 MFMA contraction with FP32 accumulation, an exact FP32
+recheck of every sample inside the proven band, FP64 sums; the same call on
+the plain FP32 path beside it, and the labels and centroids of the two
+compared bit for bit ("mixed vs FP32 at equal labels").
+
+Timing (the paper's method, section 4.2): RUNS timed runs of the whole call
+(default 10) from the same initial centroids, launched directly with HIP
+events around every distance pass, the reported time the mean of the last
+five; the same call captured as one graph is timed beside them.
+
+Prints ONE JSON line on stdout (diagnostics go to stderr).  Besides the
 throughput it carries:
-  roofline       the per-sample pass (dominant kernel): algorithmic VALU work
-                 per launch / its mean duration from HIP events recorded on the
-                 launch stream during the timed region;
-  mixed_bf16     the same workload through the BF16-MFMA path (labels and
-                 centroids compared bit for bit with the FP32 run), with its
-                 MFMA pass on the MFMA or HBM roofline;
-  bf16_workload  FP32 and BF16 on n = 2^22, d = 128, k = 1024 (1024 blobs,
-                 sigma 2, seed 2, 20 iterations);
-  fp8_workload   FP32, FP8 and BF16 on n = 2^24, d = 32, k = 256 (256
-                 anisotropic blobs, seed 3, 15 iterations);
-  batched_workload  512 independent instances advanced together with BF16
-                 MFMA distances (autotuned schedule, one graph launch), next
-                 to the FP32 batch and to per-instance FP32 calls;
-  cpu_baseline   the FP64 oracle timed on this host's cores on a bounded sample
-                 of the headline workload.
+  roofline        the dominant kernel (the BF16 screen: every sample against
+                  every centroid) at 2 n k d FLOP per launch over its mean
+                  duration from HIP events on its launch stream;
+  error_vs_oracle the last iteration against the FP64 oracle (stepwise: the
+                  GPU's C_{T-1} fed to the oracle's assign on a 2^16-sample
+                  subsample, the GPU's labels to its full update and
+                  objective);
+  plain_workload  n = 2^20, d = 64, k = 64 in FP32 and BF16;
+  fp8_workload    n = 2^24, d = 32, k = 256 in FP8, BF16 and FP32;
+  batched_workload  512 independent instances, BF16 and FP32 batches;
+  cpu_baseline    the FP64 oracle on this host's cores, one Lloyd iteration
+                  over a bounded subsample of the headline input, scaled to
+                  the whole input.
 """
 from __future__ import annotations
 
@@ -41,143 +48,236 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published FP32 vector peak: 256 CUs x 128 FP32 FMA lanes per clock x
-# 2 FLOP x 2.4 GHz = 157.3 TFLOP/s (reached only with packed FP32 operations,
-# which this library does not emit).
+# MI355X published peaks.  FP32 vector: 256 CUs x 128 FP32 FMA lanes per
+# clock x 2 FLOP x 2.4 GHz = 157.3 TFLOP/s (reached only with packed FP32
+# operations, which this library does not emit).  Dense MFMA (no sparsity).
 VALU_PEAK_TFLOPS = 256 * 128 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plain_pass_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1109_0778_amd", "csrc", "km_plain.hip")
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_1109_0778_amd", "csrc")
+NEAR_TIE = 1e-6
+LAST = 5          # runs averaged (the last LAST of RUNS)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def src_sha256(path):
-    with open(path, "rb") as fh:
+def src_sha256(name):
+    with open(os.path.join(CSRC, name), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(n_launch_units):
-    """HBM bytes per launch from committed rocprofv3 PMC counts, valid only
-    while the kernel source is unchanged since they were taken."""
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel on a workload, from committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE counts, valid only while the kernel's source file
+    is unchanged since they were taken (else None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
+            entries = json.load(fh)["entries"]
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("source_sha256") != src_sha256(KERNEL_SRC) or t.get("workload") != n_launch_units:
-        return None
-    return t.get("bytes_per_launch")
+    for e in entries:
+        if e.get("key") == key and e.get("source_sha256") == src_sha256(e["source"]):
+            return e.get("bytes_per_launch")
+    return None
 
 
-def timed_lloyd(B, torch, X, C0, precision, steps, warmup):
-    """One timed kmeans_lloyd call of `steps` iterations from C0 (inputs
-    resident), after `warmup` untimed iterations; HIP-event durations of the
-    dominant kernel over the timed call."""
+def lloyd_runs(B, torch, Xg, C0g, precision, iters, warmup, runs, graph_runs=2):
+    """`runs` timed direct-launch calls from C0, with HIP events around every
+    distance-pass launch inside each timed call; then the same call captured
+    as one graph and replayed `graph_runs` times (its time and results are
+    reported beside the direct runs')."""
     import numpy as np
-    n, d = X.shape
-    k = C0.shape[0]
-    dev = torch.device("cuda", 0)
-    Xg = torch.from_numpy(X).to(dev)
-    C0g = torch.from_numpy(C0).to(dev)
+    n, d = Xg.shape
+    k = C0g.shape[0]
     plan = B.Plan(n, d, k, precision)
+    dev = Xg.device
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     counts = torch.empty(k, dtype=torch.int64, device=dev)
-    hist = torch.empty(max(steps, warmup, 1), dtype=torch.float64, device=dev)
-    if warmup > 0:
-        Cw = C0g.clone()
-        B.kmeans_lloyd(plan, Xg, Cw, labels, counts, hist, warmup, -1.0)
-        torch.cuda.synchronize()
+    hist = torch.empty(max(iters, warmup, 1), dtype=torch.float64, device=dev)
     C = C0g.clone()
-    plan.enable_timing(steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kt = plan.kernel_times(steps)
+    if warmup > 0:
+        B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, warmup, -1.0)
+        torch.cuda.synchronize()
+    cap = 3 * iters
+    run_s, kts = [], []
+    for _ in range(runs):
+        plan.enable_timing(cap)           # fresh events; recording restarts
+        C.copy_(C0g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, iters, -1.0)
+        torch.cuda.synchronize()
+        run_s.append(time.perf_counter() - t0)
+        kts.append(plan.kernel_times(cap))
     plan.enable_timing(0)
-    res = {"el": el, "kt": kt, "C": C.cpu().numpy(), "labels": labels.cpu().numpy(),
-           "J": hist[:steps].cpu().numpy()}
+    res = {"run_s": run_s, "el": float(np.mean(run_s[-LAST:])),
+           "C": C.cpu().numpy(), "labels": labels.cpu().numpy(), "J": hist[:iters].cpu().numpy(),
+           "counts": counts.cpu().numpy()}
+    # per-iteration launches of the distance passes (1 FP32 / short BF16 sweep; 2 BF16 cascade; 3 FP8)
+    per = max(1, len(kts[-1]) // iters)
+    res["passes"] = per
+    res["pass_ms"] = [float(np.mean([kt[p::per] for kt in kts[-LAST:]])) for p in range(per)]
+    res["launches_timed"] = sum(len(kt[0::per]) for kt in kts[-LAST:])
     if precision != "fp32":
         res["recheck"], res["full_scans"] = plan.recheck_count()
-    del plan, Xg
-    torch.cuda.empty_cache()
+    if graph_runs > 0:
+        plan.use_graphs(True)
+        C.copy_(C0g)
+        B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, iters, -1.0)   # capture + run
+        torch.cuda.synchronize()
+        gs = []
+        for _ in range(graph_runs):
+            C.copy_(C0g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, iters, -1.0)
+            torch.cuda.synchronize()
+            gs.append(time.perf_counter() - t0)
+        res["el_graph"] = float(np.mean(gs))
+        res["graph_equals_direct"] = bool(np.array_equal(C.cpu().numpy(), res["C"])
+                                          and np.array_equal(labels.cpu().numpy(), res["labels"]))
+    plan.close()
     return res
 
 
-def timed_lloyd_graph(B, torch, X, C0, precision, steps):
-    """The same call launched as one captured graph: the first call captures
-    and runs it, the second (same arguments, C reset to C0) is timed."""
+def c_prev(B, torch, Xg, C0g, precision, iters):
+    """C_{T-1}: the first T-1 iterations of the same deterministic call."""
+    if iters <= 1:
+        return C0g.cpu().numpy()
+    n, d = Xg.shape
+    k = C0g.shape[0]
+    plan = B.Plan(n, d, k, precision)
+    C = C0g.clone()
+    lab = torch.empty(n, dtype=torch.int32, device=Xg.device)
+    B.kmeans_lloyd(plan, Xg, C, lab, None, None, iters - 1, -1.0)
+    torch.cuda.synchronize()
+    plan.close()
+    return C.cpu().numpy()
+
+
+def error_vs_oracle(X, Cprev, res, sample=1 << 16, seed=0):
+    """The last iteration against the FP64 oracle (stepwise protocol): labels
+    of a seeded subsample against the oracle's assign with the GPU's C_{T-1}
+    (mismatches outside and inside the 1e-6 near-tie band), C_T against the
+    oracle's update of the GPU's labels (per-centroid relative L2 error),
+    J_{T-1} against the oracle's objective of those labels."""
+    import numpy as np
+    import oracle
     n, d = X.shape
-    k = C0.shape[0]
+    t0 = time.perf_counter()
+    C64 = Cprev.astype(np.float64)
+    idx = np.sort(np.random.default_rng(seed).choice(n, min(sample, n), replace=False))
+    lab_o, dmin, d2, _ = oracle.assign(X[idx], C64)
+    m = oracle.near_tie_margin(dmin, d2)
+    mism = res["labels"][idx] != lab_o
+    C_o, cnt_o = oracle.update(X, res["labels"], C64)
+    nrm = np.linalg.norm(C_o, axis=1)
+    floor = float(np.sqrt(np.mean(X[idx].astype(np.float64) ** 2)))
+    cerr = np.linalg.norm(res["C"].astype(np.float64) - C_o, axis=1) / np.maximum(nrm, floor)
+    J_o = oracle.objective(X, C64, res["labels"])
+    J_g = float(res["J"][-1])
+    return {"assign_sample": int(idx.size),
+            "label_mismatches_outside_near_ties": int((mism & (m >= NEAR_TIE)).sum()),
+            "label_mismatches_in_near_ties": int((mism & (m < NEAR_TIE)).sum()),
+            "near_ties_in_sample": int((m < NEAR_TIE).sum()),
+            "counts_equal": bool(np.array_equal(res["counts"], cnt_o)),
+            "centroid_max_rel_err": float(cerr.max()),
+            "objective_rel_err": abs(J_g - J_o) / J_o,
+            "bars": "labels exact outside near-ties; centroids and objective within 1e-5",
+            "within_bars": bool(not (mism & (m >= NEAR_TIE)).any() and cerr.max() <= 1e-5
+                                and abs(J_g - J_o) <= 1e-5 * J_o and np.array_equal(res["counts"], cnt_o)),
+            "seconds": time.perf_counter() - t0}
+
+
+def pass_bytes(w, precision, stage):
+    """HBM bytes one distance pass must move: its copy of X (FP32 rows for the
+    plain pass; the BF16 copy with 4-byte |x| bounds for BF16 passes; the
+    e4m3 copy with 8 bytes of band inputs for the FP8 screen) plus labels
+    read (changed count) and written."""
+    dp = (w.d + 15) // 16 * 16
+    if precision == "fp32":
+        return w.n * w.d * 4 + 8 * w.n
+    if precision == "fp8" and stage == "screen":
+        return w.n * (dp + 8) + 8 * w.n
+    return w.n * (2 * dp + 4) + 8 * w.n
+
+
+def roof(kind, amount, ms, peak, unit, **extra):
+    achieved = amount / (ms * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
+    r = {"bound": kind, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak}
+    r.update(extra)
+    return r
+
+
+def workload_report(B, torch, w, X, C0, precision, iters, warmup, runs, fp=None, oracle_check=True):
+    """One precision on one workload: throughput (mean of the last runs),
+    the distance passes on their rooflines, equality with the FP32 run, and
+    the error against the oracle."""
     dev = torch.device("cuda", 0)
     Xg = torch.from_numpy(X).to(dev)
     C0g = torch.from_numpy(C0).to(dev)
-    plan = B.Plan(n, d, k, precision)
-    plan.use_graphs(True)
-    labels = torch.empty(n, dtype=torch.int32, device=dev)
-    counts = torch.empty(k, dtype=torch.int64, device=dev)
-    hist = torch.empty(max(steps, 1), dtype=torch.float64, device=dev)
-    C = C0g.clone()
-    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
-    torch.cuda.synchronize()
-    C.copy_(C0g)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B.kmeans_lloyd(plan, Xg, C, labels, counts, hist, steps, -1.0)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    res = {"el": el, "C": C.cpu().numpy(), "labels": labels.cpu().numpy()}
-    del plan, Xg
-    torch.cuda.empty_cache()
-    return res
-
-
-# dense MFMA peaks of MI355X (no sparsity), TFLOP/s
-MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
-
-
-def mixed_report(B, torch, w, X, C0, steps, warmup, fp, precision="bf16"):
-    """A mixed-precision path on the same input: throughput, equality of its
-    labels and centroids with the FP32 run, recheck fraction, and the MFMA
-    pass on its roofline (MFMA or HBM, whichever the shape is bound by)."""
-    import numpy as np
-    mx = timed_lloyd(B, torch, X, C0, precision, steps, warmup)
-    kmean_ms = float(np.mean(mx["kt"]))
+    r = lloyd_runs(B, torch, Xg, C0g, precision, iters, warmup, runs)
+    ms_step = r["el"] * 1e3 / iters
     flops = 2.0 * w.n * w.k * w.d
-    # BF16 reads FP32 X; FP8 reads its e4m3 copy (d bytes padded to 16) and 8 bytes of band inputs
-    dq = (w.d + 15) // 16 * 16
-    nbytes = (w.n * w.d * 4 if precision == "bf16" else w.n * (dq + 8)) + 2 * w.n * 4
-    peak = MFMA_PEAK_TFLOPS[precision]
-    tflops = flops / (kmean_ms * 1e-3) / 1e12
-    gbps = nbytes / (kmean_ms * 1e-3) / 1e9
-    ai = flops / nbytes
-    bound = "mfma" if ai > peak * 1e12 / (HBM_PEAK_GBPS * 1e9) else "hbm"
-    if bound == "mfma":
-        roof = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak}
+    out = {"precision": precision, "value": iters / r["el"], "unit": "Lloyd iters/s", "ms_per_step": ms_step,
+           "dist_evals_per_s": w.n * w.k * iters / r["el"],
+           "runs_ms": [s * 1e3 for s in r["run_s"]], "reported": f"mean of the last {min(LAST, runs)} of {runs} runs",
+           "ms_per_step_graph": r["el_graph"] * 1e3 / iters, "graph_equals_direct": r["graph_equals_direct"],
+           "iteration_hbm_frac": (w.n * w.d * 4) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    if precision == "fp32":
+        km = r["pass_ms"][0]
+        out["roofline"] = roof("alu", flops, km, VALU_PEAK_TFLOPS, "TFLOP/s",
+                               kernel="plain_pass (distances + argmin, fused with the per-label reduce when the record fits)",
+                               traffic=measured_traffic(f"plain_pass:{w.name}"), flops_per_launch=flops,
+                               bytes_per_launch=pass_bytes(w, "fp32", "pass"), mean_launch_ms=km,
+                               launches=r["launches_timed"])
+        out["iteration_valu_frac"] = flops / (ms_step * 1e-3) / 1e12 / VALU_PEAK_TFLOPS
     else:
-        roof = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": gbps / HBM_PEAK_GBPS}
-    roof.update({"kernel": f"mfma_assign<{precision}> (MFMA distances, key min, candidate band)",
-                 "traffic": None, "flops_per_launch": flops, "bytes_per_launch": nbytes,
-                 "mean_launch_ms": kmean_ms, "launches": len(mx["kt"]),
-                 "mfma_tflops": tflops, "hbm_gbps": gbps})
-    same_labels = bool(np.array_equal(mx["labels"], fp["labels"]))
-    same_c = bool(np.array_equal(mx["C"], fp["C"]))
-    log(f"{precision} on {w.name}: {steps} iterations in {mx['el'] * 1e3:.2f} ms (fp32 {fp['el'] * 1e3:.2f} ms); "
-        f"MFMA pass {kmean_ms * 1e3:.1f} us; labels equal {same_labels}, centroids equal {same_c}; "
-        f"recheck {mx['recheck']} of {w.n} ({mx['full_scans']} full scans)")
-    return {"precision": precision, "value": steps / mx["el"], "unit": "Lloyd iters/s",
-            "ms_per_step": mx["el"] * 1e3 / steps,
-            "fp32_value": steps / fp["el"], "speedup_vs_fp32": fp["el"] / mx["el"],
-            "dist_evals_per_s": w.n * w.k * steps / mx["el"],
-            "labels_equal_fp32": same_labels, "centroids_equal_fp32": same_c,
-            "objective_rel_diff_vs_fp32": float(np.max(np.abs(mx["J"] - fp["J"]) / fp["J"])),
-            "recheck_fraction_last_iter": mx["recheck"] / w.n,
-            "full_scan_fraction_last_iter": mx["full_scans"] / w.n, "roofline": roof}
+        peak = MFMA_PEAK_TFLOPS[precision]
+        names = (["screen"] if r["passes"] == 1 else ["screen", "refine"] if r["passes"] == 2
+                 else ["screen", "bf16_screen", "refine"])
+        km = r["pass_ms"][0]
+        nb = pass_bytes(w, precision, "screen")
+        ai = flops / nb
+        bound = "mfma" if ai > peak * 1e12 / (HBM_PEAK_GBPS * 1e9) else "hbm"
+        kern = f"mfma_assign<{precision}> {'screen (two smallest keys)' if r['passes'] > 1 else 'one sweep with candidate lists'}"
+        extra = dict(kernel=kern, traffic=measured_traffic(f"mfma_screen_{precision}:{w.name}"),
+                     flops_per_launch=flops, bytes_per_launch=nb, mean_launch_ms=km, launches=r["launches_timed"],
+                     mfma_tflops=flops / (km * 1e-3) / 1e12, hbm_gbps=nb / (km * 1e-3) / 1e9)
+        if bound == "mfma":
+            out["roofline"] = roof("mfma", flops, km, peak, "TFLOP/s", **extra)
+        else:
+            out["roofline"] = roof("hbm", nb, km, HBM_PEAK_GBPS, "GB/s", **extra)
+        out["pass_ms"] = dict(zip(names, r["pass_ms"]))
+        out["iteration_mfma_frac"] = flops / (ms_step * 1e-3) / 1e12 / peak
+        out["recheck_fraction_last_iter"] = r["recheck"] / w.n
+        out["full_scan_fraction_last_iter"] = r["full_scans"] / w.n
+    if fp is not None:
+        import numpy as np
+        out["fp32_value"] = iters / fp["el"]
+        out["speedup_vs_fp32"] = fp["el"] / r["el"]
+        out["labels_equal_fp32"] = bool(np.array_equal(r["labels"], fp["labels"]))
+        out["centroids_equal_fp32"] = bool(np.array_equal(r["C"], fp["C"]))
+        out["objective_rel_diff_vs_fp32"] = float(np.max(np.abs(r["J"] - fp["J"]) / fp["J"]))
+    if oracle_check:
+        Cp = c_prev(B, torch, Xg, C0g, precision, iters)
+        out["error_vs_oracle"] = error_vs_oracle(X, Cp, r)
+    log(f"{w.name} {precision}: {ms_step:.3f} ms/iteration ({out['reported']}); passes {r['pass_ms']} ms; "
+        f"roofline {out['roofline']['bound']} frac {out['roofline']['frac']:.3f}"
+        + (f"; vs fp32 {out['speedup_vs_fp32']:.2f}x, labels equal {out['labels_equal_fp32']}" if fp else "")
+        + (f"; oracle {out['error_vs_oracle']}" if oracle_check else ""))
+    del Xg, C0g
+    torch.cuda.empty_cache()
+    return out, r
+
+
+def workload_desc(w):
+    shape = "anisotropic blobs (per-blob per-feature sigma U[0.5,3])" if w.aniso else f"Gaussian blobs sigma={w.sigma}"
+    return (f"{w.name}: Lloyd k-means, n={w.n}, d={w.d}, k={w.k}, {w.blobs} {shape}, centres U[-10,10]^d, "
+            f"seed {w.seed}, init={w.init}, {w.iters} iterations")
 
 
 def _batched_run(B, torch, inst, C0, iters, precision, schedule=None):
@@ -232,8 +332,8 @@ def batched_report(B, torch, iters, per_instance_sample=32):
     same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(res16, res32s))
     pts = sum(s_.n for s_ in shapes)
     evals = sum(s_.n * s_.k for s_ in shapes)
+    flops = sum(2.0 * s_.n * s_.k * s_.d for s_ in shapes)
     nbytes = sum(s_.n * s_.d * 4 + 8 * s_.n for s_ in shapes)
-    # per-instance launches on a sample of instances (same iterations)
     idx = np.random.default_rng(0).choice(len(inst), per_instance_sample, replace=False)
     el_single = 0.0
     for i in idx:
@@ -250,15 +350,19 @@ def batched_report(B, torch, iters, per_instance_sample=32):
         torch.cuda.synchronize()
         el_single += time.perf_counter() - t1
     el_single *= len(inst) / per_instance_sample
+    ms_round = el16 * 1e3 / iters
     log(f"batched: {len(inst)} instances x {iters} iterations: BF16 {el16 * 1e3:.1f} ms (schedule {ch16}), "
         f"FP32 {el32 * 1e3:.1f} ms (schedule {ch32}); identical to FP32 at the same schedule: {same}; "
         f"per-instance FP32 launches, extrapolated: {el_single * 1e3:.1f} ms")
     return {"workload": f"batched: {len(inst)} instances, n log-uniform [1e3, 2e5] (total {pts}), d in {{16,32,64}}, "
                         f"k uniform [4,128], blobs = k, sigma 1, seeds 0..{len(inst) - 1}, {iters} iterations",
             "precision": "bf16", "value": len(inst) * iters / el16, "unit": "instance-iterations/s",
-            "ms_per_round": el16 * 1e3 / iters,
+            "ms_per_round": ms_round,
             "dist_evals_per_s": evals * iters / el16,
-            "hbm_gbps_algorithmic": nbytes * iters / el16 / 1e9,
+            "roofline": roof("hbm", nbytes, ms_round, HBM_PEAK_GBPS, "GB/s",
+                             kernel="one round of every instance (all launches of one iteration)",
+                             traffic=None, bytes_per_round=nbytes, flops_per_round=flops,
+                             mfma_frac_of_round=flops / (ms_round * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"]),
             "fp32_batched_value": len(inst) * iters / el32,
             "speedup_vs_fp32_batched": el32 / el16,
             "labels_and_centroids_equal_fp32_batched": bool(same),
@@ -269,24 +373,33 @@ def batched_report(B, torch, iters, per_instance_sample=32):
             "graph": True}
 
 
-def cpu_baseline(X, C0, iters, budget_s):
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, X, C0, rows):
+    """The FP64 oracle as it stands: one Lloyd iteration (assign against all k
+    centroids, update) over the first `rows` samples of the input, on every
+    host core; both steps are linear in n, so the whole input's rate is the
+    sample's scaled by rows / n."""
     import oracle
-    C = C0.astype(np.float64)
-    done = 0
+    rows = min(rows, X.shape[0])
+    Xs = X[:rows]
     t0 = time.perf_counter()
-    while done < iters:
-        r = oracle.lloyd(X, C, 1)
-        C = r["C"]
-        done += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
+    oracle.lloyd(Xs, C0.astype("float64"), 1)
     el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "Lloyd iters/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{done} full Lloyd iteration(s) of the same input from the same initial centroids "
-                      f"(n={X.shape[0]}, d={X.shape[1]}, k={C0.shape[0]}), FP64, OpenMP over samples; "
-                      f"{el:.1f} s",
+    full = el * X.shape[0] / rows
+    return {"value": 1.0 / full, "unit": "Lloyd iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one FP64 Lloyd iteration (assign over all k={w.k} centroids + update) of the first {rows} "
+                      f"of the {X.shape[0]} samples (d={w.d}), {el:.1f} s, scaled by n/{rows} to the whole input",
+            "dist_evals_per_s": rows * w.k / el, "cpu_model": cpu_model(),
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
@@ -302,20 +415,24 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
+HEADLINE_PRECISION = {"small": "fp32", "plain": "fp32", "bf16": "bf16", "fp8": "fp8"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed Lloyd iterations (default: workload's 20)")
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain", choices=["plain", "small", "bf16"])
+    ap.add_argument("--steps", type=int, default=None, help="Lloyd iterations per timed run (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed Lloyd iterations before the runs")
+    ap.add_argument("--runs", type=int, default=10, help="timed runs; the mean of the last five is reported")
+    ap.add_argument("--workload", default="bf16", choices=["bf16", "plain", "fp8", "small", "batched"],
+                    help="headline workload (batched: only the 512-instance workload, for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the BF16-MFMA comparison")
-    ap.add_argument("--no-bf16-workload", action="store_true",
-                    help="skip the n=2^22, d=128, k=1024 mixed-precision workload")
-    ap.add_argument("--no-fp8-workload", action="store_true",
-                    help="skip the n=2^24, d=32, k=256 FP8 workload")
+    ap.add_argument("--no-oracle-check", action="store_true", help="skip the error-vs-oracle reports")
+    ap.add_argument("--no-plain-workload", action="store_true", help="skip n=2^20, d=64, k=64")
+    ap.add_argument("--no-fp8-workload", action="store_true", help="skip n=2^24, d=32, k=256")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched workload")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 22,
+                    help="samples in the oracle's timed iteration (default: all 2^22 of the headline input)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (PMC calibration)")
     args = ap.parse_args()
@@ -323,6 +440,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.runs < 1:
+        print("--runs must be >= 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -337,95 +457,86 @@ def main():
     from paper_1109_0778_amd import binding as B
     from paper_1109_0778_amd import datagen
 
+    if args.workload == "batched":
+        rep = batched_report(B, torch, datagen.BATCH_ITERS)
+        rep.update({"metric": "instance-iterations/s of the batched workload", "n_gpus": 1,
+                    "higher_is_better": True, "data": "synthetic"})
+        print(json.dumps(rep), flush=True)
+        return
     w = datagen.WORKLOADS[args.workload]
+    prec = HEADLINE_PRECISION[args.workload]
     steps = args.steps if args.steps is not None else w.iters
-    log(f"workload {w.name}: n={w.n} d={w.d} k={w.k}, {steps} timed iterations, {args.warmup} warmup")
+    check = not args.no_oracle_check
+    log(f"headline workload {w.name}: n={w.n} d={w.d} k={w.k}, {prec}, {args.runs} runs x {steps} iterations, "
+        f"{args.warmup} warmup")
     X, C0 = datagen.workload(w.name)
-    fp = timed_lloyd(B, torch, X, C0, "fp32", steps, args.warmup)
-    el, kt, J = fp["el"], fp["kt"], fp["J"]
-    kmean_ms = float(np.mean(kt)) if kt else float("nan")
-    ops = 3.0 * w.n * w.k * w.d                # FLOP: one subtract (1) + one FMA (2) per (sample, centroid, feature)
-    achieved = ops / (kmean_ms * 1e-3) / 1e12
-    algo_bytes = w.n * w.d * 4 + 2 * w.n * 4   # X once, labels read + written
-    traffic = measured_traffic(f"{w.name}:{w.n}x{w.d}x{w.k}")
-    log(f"fp32: {steps} iterations in {el * 1e3:.2f} ms; per-sample pass mean {kmean_ms * 1e3:.1f} us "
-        f"over {len(kt)} launches; J[0]={J[0]:.6e} J[-1]={J[-1]:.6e}")
-    # the same call as one graph launch; the headline takes it when it matches the direct run
-    gr = timed_lloyd_graph(B, torch, X, C0, "fp32", steps)
-    graph_ok = bool(np.array_equal(gr["C"], fp["C"]) and np.array_equal(gr["labels"], fp["labels"]))
-    log(f"fp32 graph launch: {steps} iterations in {gr['el'] * 1e3:.2f} ms (equal to direct: {graph_ok})")
-    el_direct = el
-    if graph_ok and gr["el"] < el:
-        el = gr["el"]
-
+    fp_rep, fp = workload_report(B, torch, w, X, C0, "fp32", steps, args.warmup, args.runs,
+                                 oracle_check=check and prec == "fp32")
+    if prec == "fp32":
+        head, hr = fp_rep, fp
+    else:
+        head, hr = workload_report(B, torch, w, X, C0, prec, steps, args.warmup, args.runs, fp=fp, oracle_check=check)
     out = {
         "metric": "Lloyd iters/s and point-centroid dist evals/s; mixed vs FP32 at equal labels",
-        "value": steps / el,
+        "value": head["value"],
         "unit": "Lloyd iters/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8-e4m3"}[prec],
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: FP32 Lloyd, n={w.n}, d={w.d}, k={w.k}, {w.blobs} Gaussian blobs "
-                               f"sigma={w.sigma}, centres U[-10,10]^d, seed {w.seed}, init={w.init}, "
-                               f"{w.iters} iterations",
-                   "n": w.n, "d": w.d, "k": w.k, "iters": steps, "precision": "fp32"},
-        "launch": "graph" if el != el_direct else "direct",
-        "ms_per_step_direct": el_direct * 1e3 / steps,
-        "ms_per_step_graph": gr["el"] * 1e3 / steps,
-        "graph_equals_direct": graph_ok,
-        "dist_evals_per_s": w.n * w.k * steps / el,
-        "hbm_gbps_algorithmic": algo_bytes * steps / el / 1e9,
-        "roofline": {
-            "kernel": "plain_pass (fused assign + per-label reduce)",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / VALU_PEAK_TFLOPS,
-            "traffic": traffic,
-            "flops_per_launch": ops,
-            "mean_launch_ms": kmean_ms,
-            "launches": len(kt),
-            "hbm_gbps_algorithmic_kernel": algo_bytes / (kmean_ms * 1e-3) / 1e9,
-        },
-        "objective_first_last": [float(J[0]), float(J[-1])],
+        "config": {"workload": workload_desc(w) + (
+                       "; distances as a BF16 MFMA contraction with FP32 accumulation, exact FP32 recheck inside "
+                       "the proven band, FP64 sums" if prec == "bf16" else
+                       "; distances as an FP8 e4m3 MFMA contraction (per-feature power-of-two scales), exact FP32 "
+                       "recheck, FP64 sums" if prec == "fp8" else "; FP32 direct-form distances, FP64 sums"),
+                   "n": w.n, "d": w.d, "k": w.k, "iters": steps, "precision": prec},
+        "launch": "direct (HIP events around the distance passes inside the timed calls; the graph-launched "
+                  "call's time is ms_per_step_graph)",
+        "runs": args.runs,
+        "reported": head["reported"],
+        "dist_evals_per_s": head["dist_evals_per_s"],
+        "roofline": head["roofline"],
     }
-    if not args.no_mixed:
-        out["mixed_bf16"] = mixed_report(B, torch, w, X, C0, steps, args.warmup, fp)
-        if args.workload == "plain" and not args.no_bf16_workload:
-            wb = datagen.WORKLOADS["bf16"]
-            log(f"bf16 workload: n={wb.n} d={wb.d} k={wb.k}")
-            Xb, Cb = datagen.workload("bf16")
-            fpb = timed_lloyd(B, torch, Xb, Cb, "fp32", wb.iters, 1)
-            rep = mixed_report(B, torch, wb, Xb, Cb, wb.iters, 1, fpb)
-            rep["workload"] = (f"bf16: n={wb.n}, d={wb.d}, k={wb.k}, {wb.blobs} blobs sigma={wb.sigma}, "
-                               f"seed {wb.seed}, {wb.iters} iterations")
-            out["bf16_workload"] = rep
-            del Xb, Cb
-        if args.workload == "plain" and not args.no_fp8_workload:
-            w8 = datagen.WORKLOADS["fp8"]
-            log(f"fp8 workload: n={w8.n} d={w8.d} k={w8.k}")
-            X8, C8 = datagen.workload("fp8")
-            fp8 = timed_lloyd(B, torch, X8, C8, "fp32", w8.iters, 1)
-            rep = {"workload": (f"fp8: n={w8.n}, d={w8.d}, k={w8.k}, {w8.blobs} anisotropic blobs "
-                                f"(per-blob per-feature sigma U[0.5,3]), seed {w8.seed}, {w8.iters} iterations"),
-                   "fp32_value": w8.iters / fp8["el"], "unit": "Lloyd iters/s"}
-            for prec in ("fp8", "bf16"):
-                rep[prec] = mixed_report(B, torch, w8, X8, C8, w8.iters, 1, fp8, prec)
-            out["fp8_workload"] = rep
-            del X8, C8
-    if not args.no_batched and args.workload == "plain":
-        from paper_1109_0778_amd import datagen as dg
-        out["batched_workload"] = batched_report(B, torch, dg.BATCH_ITERS)
+    for key in ("fp32_value", "speedup_vs_fp32", "labels_equal_fp32", "centroids_equal_fp32",
+                "objective_rel_diff_vs_fp32", "pass_ms", "iteration_mfma_frac", "iteration_hbm_frac",
+                "recheck_fraction_last_iter", "full_scan_fraction_last_iter", "error_vs_oracle", "runs_ms",
+                "ms_per_step_graph", "graph_equals_direct"):
+        if key in head:
+            out[key] = head[key]
+    if prec != "fp32":
+        out["fp32"] = fp_rep
+    objective = [float(hr["J"][0]), float(hr["J"][-1])]
+    out["objective_first_last"] = objective
+    del fp, hr
+
+    if args.workload == "bf16" and not args.no_plain_workload:
+        wp = datagen.WORKLOADS["plain"]
+        Xp, Cp = datagen.workload("plain")
+        rep32, fpp = workload_report(B, torch, wp, Xp, Cp, "fp32", wp.iters, args.warmup, args.runs, oracle_check=check)
+        rep16, _ = workload_report(B, torch, wp, Xp, Cp, "bf16", wp.iters, args.warmup, args.runs, fp=fpp,
+                                   oracle_check=False)
+        out["plain_workload"] = {"workload": workload_desc(wp), "fp32": rep32, "bf16": rep16}
+        del Xp, Cp, fpp
+    if args.workload == "bf16" and not args.no_fp8_workload:
+        w8 = datagen.WORKLOADS["fp8"]
+        X8, C8 = datagen.workload("fp8")
+        rep32, fp8 = workload_report(B, torch, w8, X8, C8, "fp32", w8.iters, 1, min(args.runs, 3), oracle_check=False)
+        rep = {"workload": workload_desc(w8), "fp32": rep32}
+        for p_ in ("fp8", "bf16"):
+            rep[p_], _ = workload_report(B, torch, w8, X8, C8, p_, w8.iters, 1, args.runs, fp=fp8,
+                                         oracle_check=check and p_ == "fp8")
+        out["fp8_workload"] = rep
+        del X8, C8, fp8
+    if args.workload == "bf16" and not args.no_batched:
+        out["batched_workload"] = batched_report(B, torch, datagen.BATCH_ITERS)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(X, C0, w.iters, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, X, C0, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 

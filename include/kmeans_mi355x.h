@@ -259,9 +259,13 @@ km_status kmeans_lloyd_batched(km_batch *batch, int32_t iterations, hipStream_t 
 km_status km_plan_use_graphs(km_plan *plan, int32_t enable);
 
 /*
- * Diagnostics: per-launch duration of the per-sample pass (the kernel that
- * computes the distances, labels and per-label partial sums; it dominates
- * every call).  km_plan_enable_timing(plan, cap) makes the plan record a pair
+ * Diagnostics: per-launch duration of the kernels that compute the
+ * distances (they dominate every call): on FP32 plans the per-sample pass
+ * (distances, labels and, fused, the per-label partial sums), one launch per
+ * iteration; on BF16 and FP8 plans each MFMA pass, in launch order: the
+ * screen, for FP8 the BF16 screen of the samples it left open, then the
+ * refine (one pass per iteration for BF16 plans with k <= 128, which sweep
+ * once).  km_plan_enable_timing(plan, cap) makes the plan record a pair
  * of HIP events on the call's stream around each such launch, for up to
  * `cap` launches (cap = 0 turns timing off and releases the events; events are
  * host-side HIP objects, no device memory is allocated).  Recording restarts

@@ -281,19 +281,25 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m2.amb_key = nullptr;
     m2.amb_key_in = last_screen.amb_key;
     m2.changed_part = changed + (p->mfma_passes() - 1) * G;
-    const bool timed = p->timing_on();
-    if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
+    // each MFMA pass is timed on its own (one event pair per launch)
+    auto timed_mfma = [&](int fmt, int stage, const MixArgs& args) -> hipError_t {
+        const bool timed = p->timing_on();
+        hipError_t r;
+        if (timed && (r = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return r;
+        if ((r = launch_mfma_assign(fmt, stage, p->D16, args, G, s)) != hipSuccess) return r;
+        if (timed) {
+            if ((r = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return r;
+            ++p->ev_used;
+        }
+        return hipSuccess;
+    };
     if (p->cascade) {
-        if ((e = launch_mfma_assign(p->fmt, 1, p->D16, m, G, s)) != hipSuccess) return e;
-        if (f8 && (e = launch_mfma_assign(FMT_BF16, 2, p->D16, mb, G, s)) != hipSuccess) return e;
+        if ((e = timed_mfma(p->fmt, 1, m)) != hipSuccess) return e;
+        if (f8 && (e = timed_mfma(FMT_BF16, 2, mb)) != hipSuccess) return e;
         // after a BF16 screen the refine's keys are the screen's: its band is known
-        if ((e = launch_mfma_assign(FMT_BF16, 3, p->D16, m2, G, s)) != hipSuccess) return e;
-    } else if ((e = launch_mfma_assign(FMT_BF16, 0, p->D16, m, G, s)) != hipSuccess) {
+        if ((e = timed_mfma(FMT_BF16, 3, m2)) != hipSuccess) return e;
+    } else if ((e = timed_mfma(FMT_BF16, 0, m)) != hipSuccess) {
         return e;
-    }
-    if (timed) {
-        if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
-        ++p->ev_used;
     }
     RecheckArgs r{};
     r.X = X; r.Cp = Cp; r.n = p->n; r.d = p->d; r.k = p->k;
