@@ -288,6 +288,53 @@ km_status km_plan_kernel_times(km_plan *plan, float *ms, int32_t cap,
 km_status km_plan_recheck_count(km_plan *plan, int64_t *count,
                                 int64_t *full_scans, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Applications built from the same building blocks (paper section 4).
+ */
+
+/* Distance of the applications below: sum_f |a_f - b_f| (the L1 distance of
+ * the section 4.1 generated code) or sum_f (a_f - b_f)^2. */
+typedef enum {
+    KM_METRIC_L1 = 0,
+    KM_METRIC_SQEUCLIDEAN = 1
+} km_metric;
+
+/*
+ * SPADE's density step (section 4.1, "Downsampling in Bioinformatics"): the
+ * rows of the all-pairs distance matrix of X are visited in increasing index
+ * order; a row whose density is already set is skipped (its distances are
+ * never formed); a visited row i counts the samples j with
+ * dist(i, j) < apprx_width or dist(i, j) < kernel_width (i itself included)
+ * and gives that count to itself and to every sample within apprx_width whose
+ * density is still unset (the first visited row to reach a sample sets it;
+ * later rows never overwrite it).
+ *   X              [n x d] FP32 samples, row-major (device, 4-byte aligned)
+ *   apprx_width, kernel_width  thresholds (strict <), compared in FP64
+ *   metric         KM_METRIC_L1 or KM_METRIC_SQEUCLIDEAN
+ *   densities      [n] int32 output (device)
+ *   visited        [n] int8 output (device): 1 for the visited rows, or NULL
+ *   visited_count  HOST int64 output: number of visited rows, or NULL
+ *   ws, ws_bytes   device workspace of spade_workspace_bytes(n, d) bytes,
+ *                  256-byte aligned (no state is kept between calls)
+ * Distances are evaluated in FP64 with the features summed in increasing
+ * order, so every threshold decision (and every density) equals that of a
+ * sequential FP64 evaluation of the same definition.  The rows are processed
+ * in batches whose end the host reads back: the call waits on `stream`.
+ * 1 <= n < 2^31, 1 <= d <= 1024 (KM_EINVAL otherwise); NaN widths are
+ * rejected.
+ */
+size_t spade_workspace_bytes(int64_t n, int32_t d);
+km_status spade_densities(const float *X, int64_t n, int32_t d, double apprx_width,
+                          double kernel_width, km_metric metric, int32_t *densities,
+                          int8_t *visited, int64_t *visited_count, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
+/* Diagnostics of the last spade_densities call on this workspace: batches run
+ * and candidate rows whose distances were formed (visited rows plus rows
+ * formed speculatively inside a batch and then found claimed).  HOST outputs;
+ * waits on `stream`. */
+km_status spade_stats(const void *ws, int64_t n, int32_t d, int64_t *batches,
+                      int64_t *candidates, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

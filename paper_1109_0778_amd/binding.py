@@ -23,7 +23,9 @@ EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_plan_destroy", "km_last_error", "kmeans_assign", "kmeans_update",
            "kmeans_lloyd", "kmeans_lloyd_static", "km_plan_enable_timing", "km_plan_kernel_times", "km_plan_recheck_count",
            "km_plan_use_graphs", "km_plan_set_validate", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
-           "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched"]
+           "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched",
+           "spade_workspace_bytes", "spade_densities", "spade_stats"]
+METRICS = {"l1": 0, "sqeuclidean": 1}
 
 
 class KmInstance(ctypes.Structure):
@@ -92,6 +94,12 @@ def lib():
         L.km_plan_set_validate.argtypes = [P, I32]
         L.km_plan_recheck_count.restype = I32
         L.km_plan_recheck_count.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
+        L.spade_workspace_bytes.restype = ctypes.c_size_t
+        L.spade_workspace_bytes.argtypes = [I64, I32]
+        L.spade_densities.restype = I32
+        L.spade_densities.argtypes = [P, I64, I32, F64, F64, I32, P, P, ctypes.POINTER(I64), P, ctypes.c_size_t, P]
+        L.spade_stats.restype = I32
+        L.spade_stats.argtypes = [P, I64, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
         _lib = L
     return _lib
 
@@ -322,3 +330,39 @@ def kmeans_lloyd_batched(batch: Batch, iterations: int, stream=None):
         if h is not None and h.numel() < iterations:
             raise ValueError("obj_hist needs one entry per iteration")
     _check(lib().kmeans_lloyd_batched(batch.handle, int(iterations), _stream(stream)))
+
+
+def _workspace(nbytes, device):
+    import torch
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + nbytes]
+
+
+def spade_densities(X, apprx_width: float, kernel_width: float, metric: str = "l1", densities=None,
+                    visited=None, workspace=None, stream=None):
+    """spade_densities: returns (densities, visited_count, workspace); the
+    workspace is allocated here when not given."""
+    import torch
+    n, d = X.shape
+    if densities is None:
+        densities = torch.empty(n, dtype=torch.int32, device=X.device)
+    nbytes = int(lib().spade_workspace_bytes(n, d))
+    if nbytes == 0:
+        raise KMeansError(KM_EINVAL, f"bad shape n={n}, d={d}")
+    if workspace is None:
+        workspace = _workspace(nbytes, X.device)
+    cnt = ctypes.c_int64(0)
+    _check(lib().spade_densities(_ptr(X, torch.float32, "X", n * d), n, d, float(apprx_width),
+                                 float(kernel_width), METRICS[metric], _ptr(densities, torch.int32, "densities", n),
+                                 _ptr(visited, torch.int8, "visited", n), ctypes.byref(cnt),
+                                 workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return densities, int(cnt.value), workspace
+
+
+def spade_stats(workspace, n: int, d: int, stream=None):
+    """spade_stats: (batches, candidate rows formed) of the last call on ``workspace``."""
+    b = ctypes.c_int64(0)
+    c = ctypes.c_int64(0)
+    _check(lib().spade_stats(workspace.data_ptr(), n, d, ctypes.byref(b), ctypes.byref(c), _stream(stream)))
+    return int(b.value), int(c.value)

@@ -1,0 +1,483 @@
+// SPADE density step on gfx950 (paper section 4.1, "Downsampling in
+// Bioinformatics"): rows of the all-pairs distance matrix are visited in
+// increasing index order; a visited row counts the samples within the kernel
+// width (or the approximation width) and hands that count to every sample
+// within the approximation width whose density is still unset; a row whose
+// density is already set is skipped (its distances are never formed).
+//
+// The order dependence is kept exactly, with the rows processed in
+// speculative batches:
+//   select  the next B undecided rows in index order become candidates (one
+//           block), their rows widened to FP64 into the workspace;
+//   rows    every sample j against every candidate c: the distance in FP64
+//           with the features in increasing order (the same IEEE operations
+//           as a sequential loop, so every threshold decision is exact), the
+//           count of c (wave ballots, block LDS counters, one atomic per
+//           block and candidate) and the bit "j within the approximation
+//           width of c" (a B-bit mask per sample);
+//   mark    candidate c is a visited row iff no visited candidate before it
+//           in the batch has it within the approximation width (resolved in
+//           candidate order from the candidates' own masks); every undecided
+//           sample takes the count of the first visited candidate that has
+//           it within the approximation width, visited candidates their own.
+// A candidate that an earlier one in its batch claims is wasted work (its row
+// was formed speculatively); the batch size adapts to the previous batch's
+// visited count.  Integer counts and first-writer claims are independent of
+// scheduling, so densities are deterministic.
+#include "kmeans_mi355x.h"
+#include "km_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+
+km_status km_set_error(km_status st, const char* msg);
+
+namespace km {
+namespace {
+
+constexpr int kSpB = 256;               // most candidates per batch
+constexpr int kSpW = kSpB / 64;         // 64-bit words of a sample's candidate mask
+constexpr int kSpBMin = 32;             // fewest candidates per batch (while rows remain)
+constexpr int kSpMaxD8Reg = 8;          // d <= 64: the sample row lives in registers
+constexpr int kSpCG = 8;                // wide rows: candidates per pass over a sample row
+constexpr int kSpSelThreads = 1024;
+
+struct SpadeCtrl {
+    int64_t cursor;       // every row below is decided (visited or claimed)
+    int32_t nc;           // candidates of the current batch
+    int32_t done;         // no undecided row left
+    int32_t bsize;        // candidates to take in the next batch
+    int32_t last_visited; // visited candidates of the last batch
+    int64_t visited;      // visited rows so far
+    int64_t batches;
+    int64_t candidates;   // candidate rows formed (visited + speculative)
+    int64_t pad[10];
+};
+static_assert(sizeof(SpadeCtrl) <= 256, "control block must fit 256 bytes");
+
+struct SpadeArgs {
+    const float* X;
+    int64_t n;
+    int32_t d, DP;        // DP = d rounded up to 8 (candidate rows zero padded)
+    double apprx, kern;   // approximation and kernel widths
+    SpadeCtrl* ctrl;
+    int32_t* owner;       // [n] row whose count a sample took (INT_MAX: undecided)
+    int32_t* cand;        // [kSpB] candidate rows of the batch, increasing
+    int32_t* cnt;         // [kSpB] count of each candidate
+    double* crow;         // [kSpB][DP] candidate rows in FP64
+    uint64_t* near;       // [n][kSpW] bit c of sample j: d(cand c, j) < apprx
+    int32_t* dens;        // [n] output densities
+    int8_t* visited;      // [n] output visited flags, or nullptr
+};
+
+typedef __attribute__((address_space(4))) const double cdouble;
+
+__global__ __launch_bounds__(256) void spade_init_kernel(SpadeArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        a.owner[i] = INT_MAX;
+        a.dens[i] = 0;
+        if (a.visited) a.visited[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        SpadeCtrl c{};
+        c.bsize = 64;
+        *a.ctrl = c;
+    }
+}
+
+// One block: the next candidates in index order from the cursor.
+__global__ __launch_bounds__(kSpSelThreads) void spade_select_kernel(SpadeArgs a)
+{
+    __shared__ int32_t wsum[kSpSelThreads / 64];
+    __shared__ int32_t s_found;
+    if (a.ctrl->done) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = kSpSelThreads / 64;
+    // batch size from the last batch: about twice its visited count
+    const int B = a.ctrl->batches == 0 ? a.ctrl->bsize
+                                       : min(kSpB, max(kSpBMin, 2 * a.ctrl->last_visited));
+    int64_t base = a.ctrl->cursor;
+    int found = 0;
+    while (found < B && base < a.n) {
+        const int64_t i = base + tid;
+        const bool open = i < a.n && a.owner[i] == INT_MAX;
+        const uint64_t bal = __ballot(open);
+        const int below = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < NW; ++w) {
+            const int c = wsum[w];
+            off += w < wave ? c : 0;
+            tot += c;
+        }
+        const int pos = found + off + below;
+        if (open && pos < B) a.cand[pos] = (int32_t)i;
+        found += tot;
+        base += kSpSelThreads;
+        __syncthreads();   // wsum is rewritten by the next chunk
+    }
+    if (tid == 0) s_found = found;
+    __syncthreads();
+    const int nc = min(s_found, B);
+    if (tid == 0) {
+        SpadeCtrl* c = a.ctrl;
+        c->nc = nc;
+        c->cursor = s_found >= B ? (int64_t)a.cand[B - 1] + 1 : a.n;
+        if (nc == 0) c->done = 1;
+        c->batches += nc > 0 ? 1 : 0;
+        c->candidates += nc;
+        c->bsize = B;
+    }
+    for (int c = tid; c < nc; c += kSpSelThreads) a.cnt[c] = 0;
+    for (int e = tid; e < nc * a.DP; e += kSpSelThreads) {
+        const int c = e / a.DP, f = e - c * a.DP;
+        a.crow[e] = f < a.d ? (double)a.X[(size_t)a.cand[c] * a.d + f] : 0.0;
+    }
+}
+
+// Distance of one candidate row (wave-uniform, scalar operands) to the
+// lane's sample, features in increasing order.
+template <int D, int METRIC>
+__device__ __forceinline__ double cand_dist(const double (&x)[D], cdouble* row)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int f = 0; f < D; ++f) {
+        const double diff = row[f] - x[f];
+        if constexpr (METRIC == 0) acc = acc + __builtin_fabs(diff);
+        else acc = acc + diff * diff;
+    }
+    return acc;
+}
+
+// Count bookkeeping shared by both row kernels: ballot of "within either
+// width" over the wave, one LDS atomic per wave and candidate.
+__device__ __forceinline__ void count_within(bool within, int lane, int32_t* cnt_s, int c)
+{
+    const uint64_t b = __ballot(within);
+    if (lane == 0 && b) atomicAdd(&cnt_s[c], (int32_t)__popcll(b));
+}
+
+// Sample rows of at most 64 features, held in registers (FP64).
+template <int D8, int METRIC>
+__global__ __launch_bounds__(256) void spade_rows_kernel(SpadeArgs a)
+{
+    constexpr int D = 8 * D8;
+    __shared__ int32_t cnt_s[kSpB];
+    if (a.ctrl->done) return;
+    const int nc = a.ctrl->nc;
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int c = tid; c < kSpB; c += 256) cnt_s[c] = 0;
+    const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+    const bool valid = j < a.n;
+    double x[D];
+    {
+        const float* row = a.X + (valid ? j : 0) * a.d;
+#pragma unroll
+        for (int f = 0; f < D; ++f) x[f] = (valid && f < a.d) ? (double)row[f] : 0.0;
+    }
+    __syncthreads();
+    const double apprx = a.apprx, kern = a.kern;
+    cdouble* crow = (cdouble*)a.crow;
+#pragma unroll
+    for (int g = 0; g < kSpW; ++g) {
+        const int c0 = g * 64;
+        if (c0 >= nc) break;
+        const int c1 = min(nc, c0 + 64);
+        uint64_t word = 0;
+        for (int c = c0; c < c1; ++c) {
+            const double dist = cand_dist<D, METRIC>(x, crow + (size_t)c * D);
+            const bool nr = dist < apprx;
+            word |= (uint64_t)nr << (c - c0);
+            count_within(valid && (nr || dist < kern), lane, cnt_s, c);
+        }
+        if (valid) a.near[(size_t)j * kSpW + g] = word;
+    }
+    __syncthreads();
+    for (int c = tid; c < nc; c += 256)
+        if (cnt_s[c]) atomicAdd(&a.cnt[c], cnt_s[c]);
+}
+
+// Rows of more than 64 features: kSpCG candidates at a time, the sample row
+// streamed in chunks of 8 features (from L1/L2), each candidate's sum still
+// taken in increasing feature order.
+template <int METRIC>
+__global__ __launch_bounds__(256) void spade_rows_wide_kernel(SpadeArgs a)
+{
+    __shared__ int32_t cnt_s[kSpB];
+    if (a.ctrl->done) return;
+    const int nc = a.ctrl->nc;
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int c = tid; c < kSpB; c += 256) cnt_s[c] = 0;
+    const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+    const bool valid = j < a.n;
+    const float* row = a.X + (valid ? j : 0) * a.d;
+    const int d = a.d, DP = a.DP;
+    __syncthreads();
+    const double apprx = a.apprx, kern = a.kern;
+    cdouble* crow = (cdouble*)a.crow;
+#pragma unroll
+    for (int g = 0; g < kSpW; ++g) {
+        const int c0 = g * 64;
+        if (c0 >= nc) break;
+        const int c1 = min(nc, c0 + 64);
+        uint64_t word = 0;
+        for (int cg = c0; cg < c1; cg += kSpCG) {
+            double acc[kSpCG];
+#pragma unroll
+            for (int q = 0; q < kSpCG; ++q) acc[q] = 0.0;
+            for (int f0 = 0; f0 < DP; f0 += 8) {
+                double x[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[i] = (valid && f0 + i < d) ? (double)row[f0 + i] : 0.0;
+#pragma unroll
+                for (int q = 0; q < kSpCG; ++q) {
+                    const int c = min(cg + q, c1 - 1);   // rows past the batch repeat the last (discarded)
+                    cdouble* cr = crow + (size_t)c * DP + f0;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const double diff = cr[i] - x[i];
+                        if constexpr (METRIC == 0) acc[q] = acc[q] + __builtin_fabs(diff);
+                        else acc[q] = acc[q] + diff * diff;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kSpCG; ++q) {
+                const int c = cg + q;
+                if (c < c1) {
+                    const bool nr = acc[q] < apprx;
+                    word |= (uint64_t)nr << (c - c0);
+                    count_within(valid && (nr || acc[q] < kern), lane, cnt_s, c);
+                }
+            }
+        }
+        if (valid) a.near[(size_t)j * kSpW + g] = word;
+    }
+    __syncthreads();
+    for (int c = tid; c < nc; c += 256)
+        if (cnt_s[c]) atomicAdd(&a.cnt[c], cnt_s[c]);
+}
+
+// Resolve the batch (each block, from the candidates' masks) and claim.
+__global__ __launch_bounds__(256) void spade_mark_kernel(SpadeArgs a)
+{
+    __shared__ uint64_t cm[kSpB][kSpW];
+    __shared__ uint64_t vis[kSpW];
+    if (a.ctrl->done) return;
+    const int nc = a.ctrl->nc;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nc * kSpW; e += 256) {
+        const int c = e / kSpW, w = e - c * kSpW;
+        cm[c][w] = a.near[(size_t)a.cand[c] * kSpW + w];
+    }
+    if (tid < kSpW) vis[tid] = 0;
+    __syncthreads();
+    if (tid == 0) {
+        // candidate order: c is visited unless a visited candidate before it
+        // has it within the approximation width
+        for (int c = 0; c < nc; ++c) {
+            const int cw = c >> 6;
+            bool killed = false;
+#pragma unroll
+            for (int w = 0; w < kSpW; ++w) {
+                const uint64_t below = w < cw ? ~0ull : w == cw ? ((1ull << (c & 63)) - 1ull) : 0ull;
+                killed |= (cm[c][w] & vis[w] & below) != 0;
+            }
+            if (!killed) vis[cw] |= 1ull << (c & 63);
+        }
+    }
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+    if (j < a.n && a.owner[j] == INT_MAX) {
+#pragma unroll
+        for (int w = 0; w < kSpW; ++w) {
+            const uint64_t m = a.near[(size_t)j * kSpW + w] & vis[w];
+            if (m) {
+                const int c = w * 64 + __builtin_ctzll(m);
+                a.owner[j] = a.cand[c];
+                a.dens[j] = a.cnt[c];
+                break;
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        // visited candidates take their own count (also when the approximation
+        // width admits no sample, not even the row itself)
+        for (int c = tid; c < nc; c += 256) {
+            if ((vis[c >> 6] >> (c & 63)) & 1ull) {
+                const int32_t i = a.cand[c];
+                a.owner[i] = i;
+                a.dens[i] = a.cnt[c];
+                if (a.visited) a.visited[i] = 1;
+            }
+        }
+        if (tid == 0) {
+            int v = 0;
+#pragma unroll
+            for (int w = 0; w < kSpW; ++w) v += __popcll(vis[w]);
+            a.ctrl->visited += v;
+            a.ctrl->last_visited = v;
+        }
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct SpadeLayout {
+    size_t ctrl, owner, cand, cnt, crow, near, total;
+};
+
+SpadeLayout spade_layout(int64_t n, int32_t d)
+{
+    SpadeLayout L{};
+    const int DP = (d + 7) / 8 * 8;
+    size_t off = 0;
+    L.ctrl = off;  off = align256(off + sizeof(SpadeCtrl));
+    L.owner = off; off = align256(off + (size_t)n * sizeof(int32_t));
+    L.cand = off;  off = align256(off + kSpB * sizeof(int32_t));
+    L.cnt = off;   off = align256(off + kSpB * sizeof(int32_t));
+    L.crow = off;  off = align256(off + (size_t)kSpB * DP * sizeof(double));
+    L.near = off;  off = align256(off + (size_t)n * kSpW * sizeof(uint64_t));
+    L.total = off;
+    return L;
+}
+
+km_status sp_fail(km_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return km_set_error(st, buf);
+}
+
+km_status sp_hip(hipError_t e, const char* what)
+{
+    return sp_fail(KM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <int D8>
+void launch_rows_d8(int metric, const SpadeArgs& a, dim3 grid, hipStream_t s)
+{
+    if (metric == 0) hipLaunchKernelGGL((spade_rows_kernel<D8, 0>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((spade_rows_kernel<D8, 1>), grid, dim3(256), 0, s, a);
+}
+
+void launch_rows(int metric, int D8, const SpadeArgs& a, dim3 grid, hipStream_t s)
+{
+    switch (D8) {
+    case 1: launch_rows_d8<1>(metric, a, grid, s); break;
+    case 2: launch_rows_d8<2>(metric, a, grid, s); break;
+    case 3: launch_rows_d8<3>(metric, a, grid, s); break;
+    case 4: launch_rows_d8<4>(metric, a, grid, s); break;
+    case 5: launch_rows_d8<5>(metric, a, grid, s); break;
+    case 6: launch_rows_d8<6>(metric, a, grid, s); break;
+    case 7: launch_rows_d8<7>(metric, a, grid, s); break;
+    case 8: launch_rows_d8<8>(metric, a, grid, s); break;
+    default:
+        if (metric == 0) hipLaunchKernelGGL((spade_rows_wide_kernel<0>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((spade_rows_wide_kernel<1>), grid, dim3(256), 0, s, a);
+    }
+}
+
+}  // namespace
+}  // namespace km
+
+using namespace km;
+
+extern "C" {
+
+size_t spade_workspace_bytes(int64_t n, int32_t d)
+{
+    if (n < 1 || n >= ((int64_t)1 << 31) || d < 1 || d > 1024) return 0;
+    return spade_layout(n, d).total;
+}
+
+km_status spade_densities(const float* X, int64_t n, int32_t d, double apprx_width, double kernel_width,
+                          km_metric metric, int32_t* densities, int8_t* visited, int64_t* visited_count,
+                          void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    km_set_error(KM_OK, "");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return sp_fail(KM_EINVAL, "n = %lld outside [1, 2^31)", (long long)n);
+    if (d < 1 || d > 1024) return sp_fail(KM_EINVAL, "d = %d outside [1, 1024]", d);
+    if (metric != KM_METRIC_L1 && metric != KM_METRIC_SQEUCLIDEAN)
+        return sp_fail(KM_EINVAL, "unknown metric %d", (int)metric);
+    if (!X || !densities) return sp_fail(KM_EINVAL, "X and densities must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(X) & 3u) return sp_fail(KM_EINVAL, "X must be 4-byte aligned");
+    if (apprx_width != apprx_width || kernel_width != kernel_width)
+        return sp_fail(KM_EINVAL, "widths must not be NaN");
+    const SpadeLayout L = spade_layout(n, d);
+    if (!ws) return sp_fail(KM_EWORKSPACE, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return sp_fail(KM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return sp_fail(KM_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    SpadeArgs a{};
+    a.X = X; a.n = n; a.d = d; a.DP = (d + 7) / 8 * 8;
+    a.apprx = apprx_width; a.kern = kernel_width;
+    a.ctrl = reinterpret_cast<SpadeCtrl*>(w + L.ctrl);
+    a.owner = reinterpret_cast<int32_t*>(w + L.owner);
+    a.cand = reinterpret_cast<int32_t*>(w + L.cand);
+    a.cnt = reinterpret_cast<int32_t*>(w + L.cnt);
+    a.crow = reinterpret_cast<double*>(w + L.crow);
+    a.near = reinterpret_cast<uint64_t*>(w + L.near);
+    a.dens = densities;
+    a.visited = visited;
+    const int D8 = (d + 7) / 8;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    hipError_t e;
+    hipLaunchKernelGGL(spade_init_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048)), dim3(256), 0,
+                       stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return sp_hip(e, "spade init launch");
+    // Batches are enqueued in groups; after each group the host reads the
+    // done flag (kernels of batches past the end return at once).
+    int group = 2;
+    int64_t batches = 0;
+    SpadeCtrl hc{};
+    for (;;) {
+        for (int g = 0; g < group; ++g) {
+            hipLaunchKernelGGL(spade_select_kernel, dim3(1), dim3(kSpSelThreads), 0, stream, a);
+            launch_rows(metric, D8 <= kSpMaxD8Reg ? D8 : 0, a, grid, stream);
+            hipLaunchKernelGGL(spade_mark_kernel, grid, dim3(256), 0, stream, a);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return sp_hip(e, "spade batch launch");
+        batches += group;
+        if ((e = hipMemcpyAsync(&hc, a.ctrl, sizeof hc, hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return sp_hip(e, "hipMemcpyAsync(spade control)");
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return sp_hip(e, "hipStreamSynchronize");
+        if (hc.done) break;
+        if (batches > 2 * n + 64) return sp_fail(KM_EHIP, "spade: no progress after %lld batches", (long long)batches);
+        group = std::min(group * 2, 64);
+    }
+    if (visited_count) *visited_count = hc.visited;
+    return KM_OK;
+}
+
+km_status spade_stats(const void* ws, int64_t n, int32_t d, int64_t* batches, int64_t* candidates,
+                      hipStream_t stream)
+{
+    km_set_error(KM_OK, "");
+    if (!ws || n < 1 || d < 1 || d > 1024) return sp_fail(KM_EINVAL, "bad workspace or shape");
+    SpadeCtrl hc{};
+    const SpadeLayout L = spade_layout(n, d);
+    hipError_t e = hipMemcpyAsync(&hc, static_cast<const unsigned char*>(ws) + L.ctrl, sizeof hc,
+                                  hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return sp_hip(e, "hipMemcpyAsync(spade control)");
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return sp_hip(e, "hipStreamSynchronize");
+    if (batches) *batches = hc.batches;
+    if (candidates) *candidates = hc.candidates;
+    return KM_OK;
+}
+
+}  // extern "C"
