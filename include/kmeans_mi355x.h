@@ -335,6 +335,49 @@ km_status spade_densities(const float *X, int64_t n, int32_t d, double apprx_wid
 km_status spade_stats(const void *ws, int64_t n, int32_t d, int64_t *batches,
                       int64_t *candidates, hipStream_t stream);
 
+/*
+ * Per-class sums of given labels: the predicated per-label reduce of section
+ * 2.3 on its own (the update step without the mean), on a plan's workspace.
+ *   X       [n x d] FP32 samples (16-byte aligned)
+ *   labels  [n] int32 classes in [0, k) (others are skipped, or rejected in
+ *           the debug-validate mode of km_plan_set_validate)
+ *   S       [k x d] FP64 output: S_cf = sum of x_if over the samples of class c
+ *   counts  [k] int64 output n_c, or NULL
+ * The sums are taken in a fixed order (per-block sums in sample order,
+ * combined block by block), so they are deterministic; sums of integer-valued
+ * features below 2^53 are exact.
+ */
+km_status km_class_sums(km_plan *plan, const float *X, const int32_t *labels, double *S,
+                        int64_t *counts, hipStream_t stream);
+
+/*
+ * Multinomial naive Bayes training (one of the section 4.2 applications),
+ * with add-one smoothing, on a plan for n samples, d features, k classes:
+ *   prior  [k] FP64 output: n_c / n
+ *   phi    [k x d] FP64 output: (S_cf + 1) / (T_c + d), T_c = sum_f S_cf
+ *          summed in increasing f (a class without samples gets 1 / d)
+ * X holds per-sample feature counts (non-negative).  labels as for
+ * km_class_sums (classes must lie in [0, k)).
+ */
+km_status nb_train(km_plan *plan, const float *X, const int32_t *labels, double *prior,
+                   double *phi, hipStream_t stream);
+
+/*
+ * Gaussian discriminant analysis training with one covariance shared by the
+ * classes (one of the section 4.2 applications):
+ *   prior  [k] FP64 output: n_c / n
+ *   mu     [k x d] FP64 output: S_c / n_c (0 for a class without samples)
+ *   sigma  [d x d] FP64 output: (1/n) sum_i z_i z_i^T, z_i = x_i - mu_{y_i}
+ * The sum of outer products runs on the FP64 matrix cores in 64 x 64 output
+ * regions per block of samples, the block partials combined in a fixed
+ * order.  ws: device workspace of gda_workspace_bytes(plan) bytes, 256-byte
+ * aligned (KM_EWORKSPACE otherwise), besides the plan's own.  labels as for
+ * km_class_sums (classes must lie in [0, k)).
+ */
+size_t gda_workspace_bytes(const km_plan *plan);
+km_status gda_train(km_plan *plan, const float *X, const int32_t *labels, double *prior,
+                    double *mu, double *sigma, void *ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

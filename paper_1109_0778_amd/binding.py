@@ -24,7 +24,8 @@ EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "kmeans_lloyd", "kmeans_lloyd_static", "km_plan_enable_timing", "km_plan_kernel_times", "km_plan_recheck_count",
            "km_plan_use_graphs", "km_plan_set_validate", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
            "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched",
-           "spade_workspace_bytes", "spade_densities", "spade_stats"]
+           "spade_workspace_bytes", "spade_densities", "spade_stats", "km_class_sums", "nb_train",
+           "gda_workspace_bytes", "gda_train"]
 METRICS = {"l1": 0, "sqeuclidean": 1}
 
 
@@ -100,6 +101,14 @@ def lib():
         L.spade_densities.argtypes = [P, I64, I32, F64, F64, I32, P, P, ctypes.POINTER(I64), P, ctypes.c_size_t, P]
         L.spade_stats.restype = I32
         L.spade_stats.argtypes = [P, I64, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), P]
+        L.km_class_sums.restype = I32
+        L.km_class_sums.argtypes = [P, P, P, P, P, P]
+        L.nb_train.restype = I32
+        L.nb_train.argtypes = [P, P, P, P, P, P]
+        L.gda_workspace_bytes.restype = ctypes.c_size_t
+        L.gda_workspace_bytes.argtypes = [P]
+        L.gda_train.restype = I32
+        L.gda_train.argtypes = [P, P, P, P, P, P, P, ctypes.c_size_t, P]
         _lib = L
     return _lib
 
@@ -366,3 +375,33 @@ def spade_stats(workspace, n: int, d: int, stream=None):
     c = ctypes.c_int64(0)
     _check(lib().spade_stats(workspace.data_ptr(), n, d, ctypes.byref(b), ctypes.byref(c), _stream(stream)))
     return int(b.value), int(c.value)
+
+
+def km_class_sums(plan: Plan, X, labels, S, counts=None, stream=None):
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    _check(lib().km_class_sums(plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(labels, torch.int32, "labels", n),
+                               _ptr(S, torch.float64, "S", k * d), _ptr(counts, torch.int64, "counts", k),
+                               _stream(stream)))
+
+
+def nb_train(plan: Plan, X, labels, prior, phi, stream=None):
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    _check(lib().nb_train(plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(labels, torch.int32, "labels", n),
+                          _ptr(prior, torch.float64, "prior", k), _ptr(phi, torch.float64, "phi", k * d),
+                          _stream(stream)))
+
+
+def gda_train(plan: Plan, X, labels, prior, mu, sigma, workspace=None, stream=None):
+    """gda_train; returns the GDA workspace (allocated here when not given)."""
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    nbytes = int(lib().gda_workspace_bytes(plan.handle))
+    if workspace is None:
+        workspace = _workspace(nbytes, X.device)
+    _check(lib().gda_train(plan.handle, _ptr(X, torch.float32, "X", n * d), _ptr(labels, torch.int32, "labels", n),
+                           _ptr(prior, torch.float64, "prior", k), _ptr(mu, torch.float64, "mu", k * d),
+                           _ptr(sigma, torch.float64, "sigma", d * d), workspace.data_ptr(), workspace.numel(),
+                           _stream(stream)))
+    return workspace

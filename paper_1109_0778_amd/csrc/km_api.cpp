@@ -551,16 +551,16 @@ km_status kmeans_assign(km_plan* plan, const float* X, const float* C, int32_t* 
     return KM_OK;
 }
 
-km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, const float* C_old, float* C_new,
-                        int64_t* counts, hipStream_t stream)
-{
-    g_err.clear();
-    km_status st = check_plan(plan);
-    if (st != KM_OK) return st;
-    if (!X || !labels || !C_old || !C_new) return fail(KM_EINVAL, "X, labels, C_old and C_new must be non-NULL");
-    if (!aligned16(X)) return fail(KM_EINVAL, "X must be 16-byte aligned");
-    if ((st = set_device(plan)) != KM_OK) return st;
+}  // extern "C"
 
+namespace {
+
+// The per-label (per-class) reduce from given labels, finalized into FP32
+// means (C_new), FP64 sums (S_out) and/or int64 counts; in debug-validate
+// mode the labels are checked first.
+km_status enqueue_label_reduce(km_plan* plan, const float* X, const int32_t* labels, const float* C_old,
+                               float* C_new, double* S_out, int64_t* counts, hipStream_t stream)
+{
     hipError_t e;
     if (plan->validate) {
         // debug-validate mode: count labels outside [0, k) before anything
@@ -584,9 +584,103 @@ km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, co
     if (e != hipSuccess) return hip_fail(e, "update pass launch");
     FinArgs f = fin_args(plan);
     f.C_old = C_old; f.ld_old = plan->d; f.C_new = C_new; f.ld_new = plan->d; f.Cp_out = nullptr;
-    f.counts = counts; f.want_J = 0;
+    f.counts = counts; f.want_J = 0; f.S_out = S_out;
     e = launch_finalize(f, stream);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    return KM_OK;
+}
+
+km_status check_reduce_call(km_plan* plan, const float* X, const int32_t* labels)
+{
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    if (!X || !labels) return fail(KM_EINVAL, "X and labels must be non-NULL");
+    if (!aligned16(X)) return fail(KM_EINVAL, "X must be 16-byte aligned");
+    return set_device(plan);
+}
+
+// GDA covariance geometry: 64-feature regions, upper-triangle region pairs,
+// and sample ranges (about 1024 one-wave blocks in all, at least 256 samples
+// per range).
+void gda_geometry(const km_plan* p, int& R, int& RP, int& G)
+{
+    R = (p->d + 63) / 64;
+    RP = R * (R + 1) / 2;
+    const int64_t byn = std::max<int64_t>(1, (p->n + 255) / 256);
+    G = (int)std::max<int64_t>(1, std::min<int64_t>(byn, std::max(1, 1024 / RP)));
+}
+
+}  // namespace
+
+extern "C" {
+
+km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, const float* C_old, float* C_new,
+                        int64_t* counts, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_reduce_call(plan, X, labels);
+    if (st != KM_OK) return st;
+    if (!C_old || !C_new) return fail(KM_EINVAL, "X, labels, C_old and C_new must be non-NULL");
+    return enqueue_label_reduce(plan, X, labels, C_old, C_new, nullptr, counts, stream);
+}
+
+km_status km_class_sums(km_plan* plan, const float* X, const int32_t* labels, double* S, int64_t* counts,
+                        hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_reduce_call(plan, X, labels);
+    if (st != KM_OK) return st;
+    if (!S) return fail(KM_EINVAL, "S must be non-NULL");
+    return enqueue_label_reduce(plan, X, labels, nullptr, nullptr, S, counts, stream);
+}
+
+km_status nb_train(km_plan* plan, const float* X, const int32_t* labels, double* prior, double* phi,
+                   hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_reduce_call(plan, X, labels);
+    if (st != KM_OK) return st;
+    if (!prior || !phi) return fail(KM_EINVAL, "prior and phi must be non-NULL");
+    // the class sums land in phi and the counts (int64) in prior, then both
+    // are finalized in place
+    if ((st = enqueue_label_reduce(plan, X, labels, nullptr, nullptr, phi, reinterpret_cast<int64_t*>(prior), stream)) !=
+        KM_OK)
+        return st;
+    hipError_t e = launch_nb_finalize(prior, phi, plan->k, plan->d, plan->n, stream);
+    if (e != hipSuccess) return hip_fail(e, "naive Bayes finalize launch");
+    return KM_OK;
+}
+
+size_t gda_workspace_bytes(const km_plan* plan)
+{
+    if (!plan) return 0;
+    int R, RP, G;
+    gda_geometry(plan, R, RP, G);
+    return (size_t)G * RP * 64 * 64 * sizeof(double);
+}
+
+km_status gda_train(km_plan* plan, const float* X, const int32_t* labels, double* prior, double* mu,
+                    double* sigma, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_reduce_call(plan, X, labels);
+    if (st != KM_OK) return st;
+    if (!prior || !mu || !sigma) return fail(KM_EINVAL, "prior, mu and sigma must be non-NULL");
+    if (!ws) return fail(KM_EWORKSPACE, "GDA workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(KM_EWORKSPACE, "GDA workspace must be 256-byte aligned");
+    if (ws_bytes < gda_workspace_bytes(plan))
+        return fail(KM_EWORKSPACE, "GDA workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                    gda_workspace_bytes(plan));
+    if ((st = enqueue_label_reduce(plan, X, labels, nullptr, nullptr, mu, reinterpret_cast<int64_t*>(prior), stream)) !=
+        KM_OK)
+        return st;
+    CovArgs a{};
+    a.X = X; a.labels = labels; a.prior = prior; a.mu = mu; a.sigma = sigma;
+    a.part = static_cast<double*>(ws);
+    a.n = plan->n; a.d = plan->d;
+    gda_geometry(plan, a.R, a.RP, a.G);
+    hipError_t e = launch_gda(a, plan->k, stream);
+    if (e != hipSuccess) return hip_fail(e, "GDA launch");
     return KM_OK;
 }
 

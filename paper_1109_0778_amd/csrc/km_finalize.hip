@@ -105,11 +105,12 @@ __global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
             c += sC[w][lane];
         }
         const int f = (int)(e - (int64_t)j * a.d);
-        const float old = a.C_old[(size_t)j * a.ld_old + f];
+        const float old = a.C_old ? a.C_old[(size_t)j * a.ld_old + f] : 0.0f;
         const float v = (c > 0) ? (float)(S / (double)c) : old;
-        a.C_new[(size_t)j * a.ld_new + f] = v;
+        if (a.C_new) a.C_new[(size_t)j * a.ld_new + f] = v;
         if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
         if (a.counts && f == 0) a.counts[j] = c;
+        if (a.S_out) a.S_out[e] = S;
         const double co = (double)old;
         term = (double)c * co * co - 2.0 * co * S;
     }

@@ -92,6 +92,7 @@ struct FinArgs {
     double* Jterm;                        // [ceil(k*d/64)] (jmode 1)
     const double* sum_xn2;                // (jmode 1)
     int32_t GC;                           // changed partial slots in part.changed
+    double* S_out;                        // [k*d] combined FP64 sums, or nullptr
 };
 
 // Launchers (return the launch status).
@@ -128,6 +129,23 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int32_t n, hipStrea
 // blocks), written to part[0 .. grid); returns the grid used.
 hipError_t launch_count_bad_labels(const int32_t* labels, int64_t n, int32_t k, int32_t* part, int nblk,
                                    int* grid_used, hipStream_t s);
+
+// Section 4.2 applications on the per-class reduce: naive Bayes finalize
+// (in place on the class sums and counts) and GDA (means in place, then the
+// shared covariance from per-block 64 x 64 partial regions).
+struct CovArgs {
+    const float* X;          // [n x d]
+    const int32_t* labels;   // [n] classes in [0, k)
+    double* prior;           // [k] counts (int64) in, priors out
+    double* mu;              // [k x d] sums in, means out
+    double* sigma;           // [d x d] output
+    double* part;            // [G][RP][64][64] partial regions
+    int64_t n;
+    int32_t d;
+    int32_t R, RP, G;        // 64-feature regions, upper-triangle region pairs, sample ranges
+};
+hipError_t launch_nb_finalize(double* prior, double* phi, int32_t k, int32_t d, int64_t n, hipStream_t s);
+hipError_t launch_gda(const CovArgs& a, int32_t k, hipStream_t s);
 
 // Samples per lane in the plain pass.  One: measured on MI355X at d = 64,
 // k = 64, two samples per lane (sharing each SGPR centroid operand) ran 18%

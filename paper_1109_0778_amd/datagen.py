@@ -163,3 +163,30 @@ def cytometry(n: int = SPADE_N, d: int = SPADE_D, pops: int = SPADE_POPS, seed: 
     pop = rng.choice(pops, n, p=w)
     X = mu[pop] + sd[pop] * rng.standard_normal((n, d))
     return np.ascontiguousarray(X, dtype=np.float32), pop
+
+
+# ----------------------------------------------------- classification data
+# Labelled samples for the section 4.2 training applications (their datasets
+# are not available).  Labels are i.i.d. uniform over k classes.
+def nb_counts(n: int, d: int, k: int, seed: int, rate_hi: float = 5.0):
+    """Naive Bayes input: per-sample feature counts, ``X[i, f] ~
+    Poisson(rate[y_i, f])`` with ``rate ~ U(0, rate_hi)`` per class and
+    feature, as FP32 (exact integers); returns ``(X, y)``."""
+    rng = np.random.default_rng(seed)
+    rate = rng.uniform(0.0, rate_hi, (k, d))
+    y = rng.integers(0, k, n).astype(np.int32)
+    X = rng.poisson(rate[y]).astype(np.float32)
+    return np.ascontiguousarray(X), y
+
+
+def gda_classes(n: int, d: int, k: int, seed: int):
+    """GDA input: class means ``U(-5, 5)^d``, one shared covariance
+    ``A A^T`` with ``A`` having i.i.d. ``N(0, 1/d)`` entries plus the
+    identity; ``X = mu[y] + eps A^T`` with ``eps ~ N(0, I)``, rounded once
+    to FP32; returns ``(X, y)``."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-5.0, 5.0, (k, d))
+    A = np.eye(d) + rng.standard_normal((d, d)) / np.sqrt(d)
+    y = rng.integers(0, k, n).astype(np.int32)
+    X = mu[y] + rng.standard_normal((n, d)) @ A.T
+    return np.ascontiguousarray(X, dtype=np.float32), y
