@@ -292,12 +292,37 @@ km_status km_plan_recheck_count(km_plan *plan, int64_t *count,
  * Applications built from the same building blocks (paper section 4).
  */
 
-/* Distance of the applications below: sum_f |a_f - b_f| (the L1 distance of
+/* Distance of kmeans_assign_metric and the applications below: sum_f |a_f - b_f| (the L1 distance of
  * the section 4.1 generated code) or sum_f (a_f - b_f)^2. */
 typedef enum {
     KM_METRIC_L1 = 0,
     KM_METRIC_SQEUCLIDEAN = 1
 } km_metric;
+
+/* Sample layouts of kmeans_assign_metric. */
+typedef enum {
+    KM_ROW_MAJOR = 0,       /* X[i * d + f] (n x d, as everywhere else)        */
+    KM_FEATURE_MAJOR = 1    /* X[f * n + i] (d x n, struct of arrays)          */
+} km_layout;
+
+/*
+ * Assign step under a chosen metric and sample layout (FP32 plans;
+ * KM_ENOTSUP for BF16 / FP8 plans): for every sample the nearest centroid,
+ * lowest index on ties.  The squared Euclidean form is the plain path's
+ * canonical distance (labels and distances bit-equal to kmeans_assign's);
+ * the L1 form sums |fl(x - c)| in the same chunked order, so its error is at
+ * most (1 + 8 + ceil(log2 ceil(d/8))) 2^-24 of the exact L1 distance.  Both
+ * layouts give bit-identical results.
+ *   X         [n x d] (row-major) or [d x n] (feature-major) FP32, 16-byte
+ *             aligned
+ *   C         [k x d] FP32 centroids (row-major)
+ *   labels    [n] int32 output
+ *   mindist   [n] FP32 output distance to the chosen centroid, or NULL
+ *   objective [1] FP64 output sum of those distances, or NULL
+ */
+km_status kmeans_assign_metric(km_plan *plan, const float *X, km_layout layout,
+                               km_metric metric, const float *C, int32_t *labels,
+                               float *mindist, double *objective, hipStream_t stream);
 
 /*
  * SPADE's density step (section 4.1, "Downsampling in Bioinformatics"): the

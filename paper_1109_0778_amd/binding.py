@@ -25,7 +25,8 @@ EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_plan_use_graphs", "km_plan_set_validate", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
            "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched",
            "spade_workspace_bytes", "spade_densities", "spade_stats", "km_class_sums", "nb_train",
-           "gda_workspace_bytes", "gda_train"]
+           "gda_workspace_bytes", "gda_train", "kmeans_assign_metric"]
+LAYOUTS = {"row": 0, "feature": 1}
 METRICS = {"l1": 0, "sqeuclidean": 1}
 
 
@@ -109,6 +110,8 @@ def lib():
         L.gda_workspace_bytes.argtypes = [P]
         L.gda_train.restype = I32
         L.gda_train.argtypes = [P, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.kmeans_assign_metric.restype = I32
+        L.kmeans_assign_metric.argtypes = [P, P, I32, I32, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -405,3 +408,15 @@ def gda_train(plan: Plan, X, labels, prior, mu, sigma, workspace=None, stream=No
                            _ptr(sigma, torch.float64, "sigma", d * d), workspace.data_ptr(), workspace.numel(),
                            _stream(stream)))
     return workspace
+
+
+def kmeans_assign_metric(plan: Plan, X, C, labels, metric: str = "l1", layout: str = "row", mindist=None,
+                         objective=None, stream=None):
+    """kmeans_assign_metric; X is n x d (layout "row") or d x n ("feature")."""
+    import torch
+    n, d, k = plan.n, plan.d, plan.k
+    _check(lib().kmeans_assign_metric(
+        plan.handle, _ptr(X, torch.float32, "X", n * d), LAYOUTS[layout], METRICS[metric],
+        _ptr(C, torch.float32, "C", k * d), _ptr(labels, torch.int32, "labels", n),
+        _ptr(mindist, torch.float32, "mindist", n), _ptr(objective, torch.float64, "objective", 1),
+        _stream(stream)))

@@ -614,6 +614,31 @@ void gda_geometry(const km_plan* p, int& R, int& RP, int& G)
 
 extern "C" {
 
+km_status kmeans_assign_metric(km_plan* plan, const float* X, km_layout layout, km_metric metric, const float* C,
+                               int32_t* labels, float* mindist, double* objective, hipStream_t stream)
+{
+    g_err.clear();
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    if (!X || !C || !labels) return fail(KM_EINVAL, "X, C and labels must be non-NULL");
+    if (!aligned16(X) || !aligned16(C)) return fail(KM_EINVAL, "X and C must be 16-byte aligned");
+    if (layout != KM_ROW_MAJOR && layout != KM_FEATURE_MAJOR) return fail(KM_EINVAL, "unknown layout %d", (int)layout);
+    if (metric != KM_METRIC_L1 && metric != KM_METRIC_SQEUCLIDEAN) return fail(KM_EINVAL, "unknown metric %d", (int)metric);
+    if (plan->mixed) return fail(KM_ENOTSUP, "kmeans_assign_metric needs an FP32 plan");
+    if ((st = set_device(plan)) != KM_OK) return st;
+    hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, cp_of(plan), nullptr, stream);
+    if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
+    MetricArgs a{};
+    a.X = X; a.Cp = cp_of(plan); a.labels = labels; a.mindist = mindist;
+    a.partJ = partials_of(plan).J;
+    a.n = plan->n; a.d = plan->d; a.k = plan->k;
+    if ((e = launch_assign_metric(plan->D8, (int)metric, (int)layout, a, plan->grid, stream)) != hipSuccess)
+        return hip_fail(e, "assign launch");
+    if (objective && (e = launch_reduce_objective(a.partJ, plan->grid, objective, stream)) != hipSuccess)
+        return hip_fail(e, "objective reduce launch");
+    return KM_OK;
+}
+
 km_status kmeans_update(km_plan* plan, const float* X, const int32_t* labels, const float* C_old, float* C_new,
                         int64_t* counts, hipStream_t stream)
 {

@@ -147,6 +147,19 @@ struct CovArgs {
 hipError_t launch_nb_finalize(double* prior, double* phi, int32_t k, int32_t d, int64_t n, hipStream_t s);
 hipError_t launch_gda(const CovArgs& a, int32_t k, hipStream_t s);
 
+// Assign under a chosen metric (0 = L1, 1 = squared Euclidean) and sample
+// layout (0 = row-major n x d, 1 = feature-major d x n).
+struct MetricArgs {
+    const float* X;
+    const float* Cp;         // [k x 8 D8] padded centroids
+    int32_t* labels;         // [n]
+    float* mindist;          // [n] or nullptr
+    double* partJ;           // [grid] per-block FP64 sums of the chosen distances
+    int64_t n;
+    int32_t d, k;
+};
+hipError_t launch_assign_metric(int D8, int metric, int layout, const MetricArgs& a, int grid, hipStream_t s);
+
 // Samples per lane in the plain pass.  One: measured on MI355X at d = 64,
 // k = 64, two samples per lane (sharing each SGPR centroid operand) ran 18%
 // slower (3 instead of 4 resident waves per SIMD), and LDS-broadcast centroid
