@@ -32,6 +32,10 @@ throughput it carries:
   plain_workload  n = 2^20, d = 64, k = 64 in FP32 and BF16;
   fp8_workload    n = 2^24, d = 32, k = 256 in FP8, BF16 and FP32;
   batched_workload  512 independent instances, BF16 and FP32 batches;
+  spade_workload  SPADE's density step (section 4.1) at n = 235,000, d = 32;
+  nb_workload, gda_workload  naive Bayes and GDA training, n = 2^20, d = 64;
+  metric_layout   the assign step under L1 / squared Euclidean distances with
+                  row-major / feature-major samples;
   cpu_baseline    the FP64 oracle on this host's cores, one Lloyd iteration
                   over a bounded subsample of the headline input, scaled to
                   the whole input.
@@ -373,6 +377,155 @@ def batched_report(B, torch, iters, per_instance_sample=32):
             "graph": True}
 
 
+# MI355X FP64: one FP64 add (or FMA) per lane per clock, 256 CUs x 64 lanes
+# x 2.4 GHz = 39.3 T lane-operations/s (the published 78.6 TFLOP/s counts an
+# FMA as two); the dense FP64 matrix peak is 78.6 TFLOP/s.
+FP64_LANE_OPS = 256 * 64 * 2.4e9
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def spade_report(B, torch, runs):
+    """SPADE's density step (section 4.1) on the synthetic cytometry matrix:
+    n = 235,000 rows, d = 32, the section's two widths, L1 distances in FP64.
+    Algorithmic work: the rows the sequential loop visits, each against every
+    sample, 2 d FP64 operations per pair (subtract, add of the magnitude)."""
+    import numpy as np
+    from paper_1109_0778_amd import datagen
+    X, _ = datagen.cytometry()
+    n, d = X.shape
+    Xg = torch.from_numpy(X).cuda()
+    dens, nvis, ws = B.spade_densities(Xg, datagen.SPADE_APPRX_WIDTH, datagen.SPADE_KERNEL_WIDTH, "l1")
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(runs):
+        e0, e1 = _events(torch)
+        e0.record()
+        dens, nvis, ws = B.spade_densities(Xg, datagen.SPADE_APPRX_WIDTH, datagen.SPADE_KERNEL_WIDTH, "l1",
+                                           densities=dens, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    batches, cands = B.spade_stats(ws, n, d)
+    ms = float(np.mean(times[-LAST:]))
+    ops = float(nvis) * n * 2 * d
+    log(f"spade: n={n} d={d}: {ms:.2f} ms, visited {nvis}, {batches} batches, {cands} candidate rows")
+    return {"workload": f"SPADE density step (section 4.1): synthetic cytometry matrix n={n}, d={d} "
+                        f"({datagen.SPADE_POPS} populations, seed {datagen.SPADE_SEED}), L1 distance, widths "
+                        f"{datagen.SPADE_APPRX_WIDTH} / {datagen.SPADE_KERNEL_WIDTH}, FP64",
+            "ms": ms, "runs_ms": times, "visited_rows": nvis, "batches": batches, "candidate_rows": cands,
+            "speculation_efficiency": nvis / max(cands, 1),
+            "row_evals_per_s": float(nvis) * n / (ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": FP64_LANE_OPS / 1e12,
+                         "unit": "T FP64 op/s", "frac": ops / (ms * 1e-3) / FP64_LANE_OPS,
+                         "kernel": "spade_densities, whole call (select + rows + mark launches of every batch)",
+                         "ops_per_call": ops, "formed_ops_per_call": float(cands) * n * 2 * d, "traffic": None}}
+
+
+def nb_gda_report(B, torch, runs, n=1 << 20, d=64, k=16):
+    """Naive Bayes (count features) and GDA training on n = 2^20 labelled
+    samples, d = 64, k = 16 classes."""
+    import numpy as np
+    from paper_1109_0778_amd import datagen
+    out = {}
+    X, y = datagen.nb_counts(n, d, k, seed=11)
+    Xg, yg = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    plan = B.Plan(n, d, k)
+    prior = torch.empty(k, dtype=torch.float64, device="cuda")
+    phi = torch.empty((k, d), dtype=torch.float64, device="cuda")
+    B.nb_train(plan, Xg, yg, prior, phi)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(runs):
+        e0, e1 = _events(torch)
+        e0.record()
+        B.nb_train(plan, Xg, yg, prior, phi)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.mean(times[-LAST:]))
+    nbytes = n * d * 4 + n * 4
+    out["nb_workload"] = {"workload": f"multinomial naive Bayes training: n={n} Poisson count samples, d={d}, "
+                                      f"k={k} classes, seed 11", "ms": ms, "runs_ms": times,
+                          "samples_per_s": n / (ms * 1e-3),
+                          "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
+                                       "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                       "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                       "kernel": "nb_train, whole call (class reduce + combine + finalize)",
+                                       "bytes_per_call": nbytes, "traffic": None}}
+    X, y = datagen.gda_classes(n, d, k, seed=12)
+    Xg, yg = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    mu = torch.empty((k, d), dtype=torch.float64, device="cuda")
+    sigma = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    ws = B.gda_train(plan, Xg, yg, prior, mu, sigma)
+    torch.cuda.synchronize()
+    times, kts = [], []
+    for _ in range(runs):
+        plan.enable_timing(1)
+        e0, e1 = _events(torch)
+        e0.record()
+        B.gda_train(plan, Xg, yg, prior, mu, sigma, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        kts.append(plan.kernel_times(1)[0])
+    plan.enable_timing(0)
+    ms = float(np.mean(times[-LAST:]))
+    kms = float(np.mean(kts[-LAST:]))
+    flops = 2.0 * n * d * d
+    out["gda_workload"] = {"workload": f"GDA training: n={n} samples of {k} Gaussian classes with one shared "
+                                       f"covariance, d={d}, seed 12", "ms": ms, "runs_ms": times,
+                           "samples_per_s": n / (ms * 1e-3),
+                           "roofline": {"bound": "mfma", "achieved": flops / (kms * 1e-3) / 1e12,
+                                        "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": flops / (kms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                                        "kernel": "gda_cov_kernel (FP64 MFMA sum of outer products)",
+                                        "flops_per_launch": flops, "mean_launch_ms": kms,
+                                        "launches": len(kts[-LAST:]), "traffic": None}}
+    log(f"nb: {out['nb_workload']['ms']:.3f} ms; gda: {ms:.3f} ms (covariance {kms:.3f} ms)")
+    plan.close()
+    return out
+
+
+def metric_layout_report(B, torch, runs, n=1 << 22, k=64):
+    """Assign step under L1 and squared Euclidean distances with row-major and
+    feature-major samples, d = 8, 16, 32: one kmeans_assign_metric call each
+    (2 n k d FP32 operations: subtract, then add of the magnitude or FMA)."""
+    import numpy as np
+    from paper_1109_0778_amd import datagen
+    rows = []
+    for d in (8, 16, 32):
+        X, C = datagen.blobs(n, d, k, k, 1.0, seed=40 + d)
+        plan = B.Plan(n, d, k)
+        Cg = torch.from_numpy(C).cuda()
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        for layout in ("row", "feature"):
+            Xg = torch.from_numpy(X if layout == "row" else np.ascontiguousarray(X.T)).cuda()
+            for metric in ("l1", "sqeuclidean"):
+                B.kmeans_assign_metric(plan, Xg, Cg, lab, metric, layout)
+                times = []
+                for _ in range(runs):
+                    e0, e1 = _events(torch)
+                    e0.record()
+                    B.kmeans_assign_metric(plan, Xg, Cg, lab, metric, layout)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                ms = float(np.mean(times[-LAST:]))
+                flops = 2.0 * n * k * d
+                rows.append({"d": d, "layout": layout, "metric": metric, "ms": ms,
+                             "dist_evals_per_s": n * k / (ms * 1e-3),
+                             "valu_frac": flops / (ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS})
+            del Xg
+        plan.close()
+    log("metric/layout: " + ", ".join(f"d{r['d']} {r['layout']} {r['metric']} {r['ms']:.3f}ms" for r in rows))
+    return {"workload": f"assign step, n={n}, k={k}, blobs sigma 1, d in 8/16/32, L1 and squared Euclidean, "
+                        f"row-major and feature-major samples", "results": rows}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -431,6 +584,8 @@ def main():
     ap.add_argument("--no-plain-workload", action="store_true", help="skip n=2^20, d=64, k=64")
     ap.add_argument("--no-fp8-workload", action="store_true", help="skip n=2^24, d=32, k=256")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched workload")
+    ap.add_argument("--no-apps", action="store_true",
+                    help="skip SPADE, naive Bayes, GDA and the metric / layout comparison")
     ap.add_argument("--cpu-rows", type=int, default=1 << 22,
                     help="samples in the oracle's timed iteration (default: all 2^22 of the headline input)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -534,6 +689,10 @@ def main():
         del X8, C8, fp8
     if args.workload == "bf16" and not args.no_batched:
         out["batched_workload"] = batched_report(B, torch, datagen.BATCH_ITERS)
+    if args.workload == "bf16" and not args.no_apps:
+        out["spade_workload"] = spade_report(B, torch, args.runs)
+        out.update(nb_gda_report(B, torch, args.runs))
+        out["metric_layout"] = metric_layout_report(B, torch, args.runs)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(w, X, C0, args.cpu_rows)

@@ -265,7 +265,7 @@ km_status km_plan_use_graphs(km_plan *plan, int32_t enable);
  * iteration; on BF16 and FP8 plans each MFMA pass, in launch order: the
  * screen, for FP8 the BF16 screen of the samples it left open, then the
  * refine (one pass per iteration for BF16 plans with k <= 128, which sweep
- * once).  km_plan_enable_timing(plan, cap) makes the plan record a pair
+ * once); in gda_train, the covariance contraction.  km_plan_enable_timing(plan, cap) makes the plan record a pair
  * of HIP events on the call's stream around each such launch, for up to
  * `cap` launches (cap = 0 turns timing off and releases the events; events are
  * host-side HIP objects, no device memory is allocated).  Recording restarts

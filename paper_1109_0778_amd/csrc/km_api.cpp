@@ -704,8 +704,19 @@ km_status gda_train(km_plan* plan, const float* X, const int32_t* labels, double
     a.part = static_cast<double*>(ws);
     a.n = plan->n; a.d = plan->d;
     gda_geometry(plan, a.R, a.RP, a.G);
-    hipError_t e = launch_gda(a, plan->k, stream);
-    if (e != hipSuccess) return hip_fail(e, "GDA launch");
+    hipError_t e = launch_gda_means(a, plan->k, stream);
+    if (e != hipSuccess) return hip_fail(e, "GDA means launch");
+    // the covariance contraction is the plan's timed kernel here
+    const bool timed = plan->timing_on();
+    if (timed && (e = hipEventRecord(plan->ev[2 * plan->ev_used], stream)) != hipSuccess)
+        return hip_fail(e, "hipEventRecord");
+    if ((e = launch_gda_cov(a, stream)) != hipSuccess) return hip_fail(e, "GDA covariance launch");
+    if (timed) {
+        if ((e = hipEventRecord(plan->ev[2 * plan->ev_used + 1], stream)) != hipSuccess)
+            return hip_fail(e, "hipEventRecord");
+        ++plan->ev_used;
+    }
+    if ((e = launch_gda_combine(a, stream)) != hipSuccess) return hip_fail(e, "GDA combine launch");
     return KM_OK;
 }
 

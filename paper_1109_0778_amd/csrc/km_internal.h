@@ -145,7 +145,9 @@ struct CovArgs {
     int32_t R, RP, G;        // 64-feature regions, upper-triangle region pairs, sample ranges
 };
 hipError_t launch_nb_finalize(double* prior, double* phi, int32_t k, int32_t d, int64_t n, hipStream_t s);
-hipError_t launch_gda(const CovArgs& a, int32_t k, hipStream_t s);
+hipError_t launch_gda_means(const CovArgs& a, int32_t k, hipStream_t s);
+hipError_t launch_gda_cov(const CovArgs& a, hipStream_t s);
+hipError_t launch_gda_combine(const CovArgs& a, hipStream_t s);
 
 // Assign under a chosen metric (0 = L1, 1 = squared Euclidean) and sample
 // layout (0 = row-major n x d, 1 = feature-major d x n).

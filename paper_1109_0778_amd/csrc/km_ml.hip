@@ -129,13 +129,20 @@ hipError_t launch_nb_finalize(double* prior, double* phi, int32_t k, int32_t d, 
     return hipGetLastError();
 }
 
-hipError_t launch_gda(const CovArgs& a, int32_t k, hipStream_t s)
+hipError_t launch_gda_means(const CovArgs& a, int32_t k, hipStream_t s)
 {
     hipLaunchKernelGGL(gda_means_kernel, dim3(k), dim3(256), 0, s, a.prior, a.mu, a.d, a.n);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_gda_cov(const CovArgs& a, hipStream_t s)
+{
     hipLaunchKernelGGL(gda_cov_kernel, dim3(a.G, a.RP), dim3(64), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_gda_combine(const CovArgs& a, hipStream_t s)
+{
     const int64_t dd = (int64_t)a.d * a.d;
     hipLaunchKernelGGL(gda_combine_kernel, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
