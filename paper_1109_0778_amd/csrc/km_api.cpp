@@ -600,14 +600,14 @@ km_status check_reduce_call(km_plan* plan, const float* X, const int32_t* labels
 }
 
 // GDA covariance geometry: 64-feature regions, upper-triangle region pairs,
-// and sample ranges (about 1024 one-wave blocks in all, at least 256 samples
-// per range).
+// and sample ranges (about 512 four-wave blocks in all, two per CU; at least
+// 1024 samples per range).
 void gda_geometry(const km_plan* p, int& R, int& RP, int& G)
 {
     R = (p->d + 63) / 64;
     RP = R * (R + 1) / 2;
-    const int64_t byn = std::max<int64_t>(1, (p->n + 255) / 256);
-    G = (int)std::max<int64_t>(1, std::min<int64_t>(byn, std::max(1, 1024 / RP)));
+    const int64_t byn = std::max<int64_t>(1, (p->n + 1023) / 1024);
+    G = (int)std::max<int64_t>(1, std::min<int64_t>(byn, std::max(1, 512 / RP)));
 }
 
 }  // namespace
@@ -702,7 +702,7 @@ km_status gda_train(km_plan* plan, const float* X, const int32_t* labels, double
     CovArgs a{};
     a.X = X; a.labels = labels; a.prior = prior; a.mu = mu; a.sigma = sigma;
     a.part = static_cast<double*>(ws);
-    a.n = plan->n; a.d = plan->d;
+    a.n = plan->n; a.d = plan->d; a.k = plan->k;
     gda_geometry(plan, a.R, a.RP, a.G);
     hipError_t e = launch_gda_means(a, plan->k, stream);
     if (e != hipSuccess) return hip_fail(e, "GDA means launch");

@@ -141,7 +141,7 @@ struct CovArgs {
     double* sigma;           // [d x d] output
     double* part;            // [G][RP][64][64] partial regions
     int64_t n;
-    int32_t d;
+    int32_t d, k;
     int32_t R, RP, G;        // 64-feature regions, upper-triangle region pairs, sample ranges
 };
 hipError_t launch_nb_finalize(double* prior, double* phi, int32_t k, int32_t d, int64_t n, hipStream_t s);
