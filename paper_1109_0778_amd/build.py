@@ -17,7 +17,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "libkmeans_mi355x.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-SOURCES = ["km_api.cpp", "km_batch.cpp", "km_plain.hip", "km_finalize.hip", "km_mixed.hip", "km_spade.hip", "km_ml.hip", "km_metric.hip"]
+SOURCES = ["km_api.cpp", "km_batch.cpp", "km_plain.hip", "km_finalize.hip", "km_mixed.hip", "km_spade.hip", "km_ml.hip", "km_metric.hip", "km_wide.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -55,6 +55,10 @@ struct km_plan {
     int device;
     int num_cu;
     int D8, D;           // padded feature count (8-feature chunks)
+    bool wide = false;   // d > 128: streaming assign, per-label reduce over 128-feature slices
+    int dsl = 0;         // features per reduce slice (d, or 128 when wide)
+    int nsl = 1;         // reduce slices
+    int D8s(int s) const { return (std::min(dsl, d - s * dsl) + 7) / 8; }
     int grid;            // blocks of the assign / fused pass (one resident wave)
     bool split;          // assign and reduce as two passes (the fused pass would lose occupancy)
     bool chunked;        // per-label record too large for one block: the reduce runs over label chunks
@@ -150,7 +154,7 @@ hipError_t timed_pass(km_plan* p, Mode mode, const PassArgs& a, dim3 grid, size_
     const bool timed = p->timing_on();
     hipError_t e;
     if (timed && (e = hipEventRecord(p->ev[2 * p->ev_used], s)) != hipSuccess) return e;
-    e = launch_plain_pass(p->D8, mode, a, grid, lds, s);
+    e = p->wide ? launch_assign_wide(a, (int)grid.x, s) : launch_plain_pass(p->D8, mode, a, grid, lds, s);
     if (e != hipSuccess) return e;
     if (timed) {
         if ((e = hipEventRecord(p->ev[2 * p->ev_used + 1], s)) != hipSuccess) return e;
@@ -164,7 +168,8 @@ PassArgs pass_args(const km_plan* p, const float* X, const float* Cp, int32_t* l
     PassArgs a{};
     a.X = X; a.Cp = Cp; a.labels = labels; a.mindist = nullptr;
     a.part = partials_of(p); a.ctrl = nullptr;
-    a.n = p->n; a.d = p->d; a.k = p->k; a.iter = 0; a.count_changed = 0; a.kc = p->kc; a.upd_tiles = p->upd_tiles;
+    a.n = p->n; a.d = p->d; a.ldx = p->d; a.k = p->k; a.iter = 0; a.count_changed = 0; a.kc = p->kc;
+    a.upd_tiles = p->upd_tiles;
     if (p->chunked) {
         a.perm = reinterpret_cast<const int32_t*>(p->ws + p->off_perm);
         a.plab = reinterpret_cast<const int32_t*>(p->ws + p->off_plab);
@@ -180,7 +185,7 @@ FinArgs fin_args(const km_plan* p)
 {
     FinArgs f{};
     f.part = partials_of(p);
-    f.G = p->GS(); f.GJ = p->grid; f.k = p->k; f.d = p->d; f.D = p->D;
+    f.G = p->GS(); f.GJ = p->grid; f.k = p->k; f.d = p->d; f.D = p->D; f.ld_S = p->d;
     f.tol = -1.0;
     f.jmode = p->mixed ? 1 : 0;
     f.Jterm = reinterpret_cast<double*>(p->ws + p->off_jt);
@@ -190,19 +195,52 @@ FinArgs fin_args(const km_plan* p)
 }
 
 // The reduce from stored labels: one pass (whole record) or a 2-D grid of
-// label chunks.
-hipError_t enqueue_update(km_plan* p, const PassArgs& a, hipStream_t s)
+// label chunks (after the samples are partitioned by chunk, unless
+// `partitioned`).  D8: 8-feature chunks of the pass's rows.
+hipError_t enqueue_update(km_plan* p, const PassArgs& a, int D8, bool partitioned, hipStream_t s)
 {
-    // without a split, the update walks exactly the fused pass's tiles and blocks
-    if (!p->split) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid), p->lds_upd, s);
-    if (!p->chunked) return launch_plain_pass(p->D8, MODE_UPDATE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
+    // without a split, the update walks exactly the fused pass's blocks and tiles
+    if (!p->split) return launch_plain_pass(D8, MODE_UPDATE, a, dim3(p->grid), p->lds_upd, s);
+    if (!p->chunked) return launch_plain_pass(D8, MODE_UPDATE, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
     // label chunks: partition the samples by chunk, then reduce each chunk's samples
-    hipError_t e = launch_partition(a, reinterpret_cast<int32_t*>(p->ws + p->off_perm),
-                                    reinterpret_cast<int32_t*>(p->ws + p->off_plab),
-                                    reinterpret_cast<int32_t*>(p->ws + p->off_poff),
-                                    reinterpret_cast<int32_t*>(p->ws + p->off_plen), s);
-    if (e != hipSuccess) return e;
-    return launch_part_update(p->D8, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
+    if (!partitioned) {
+        hipError_t e = launch_partition(a, reinterpret_cast<int32_t*>(p->ws + p->off_perm),
+                                        reinterpret_cast<int32_t*>(p->ws + p->off_plab),
+                                        reinterpret_cast<int32_t*>(p->ws + p->off_poff),
+                                        reinterpret_cast<int32_t*>(p->ws + p->off_plen), s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_part_update(D8, a, dim3(p->grid_upd, p->nch), p->lds_upd, s);
+}
+
+// The reduce from stored labels and its finalize.  Rows of more than 128
+// features are reduced and finalized in 128-feature slices (the sums of a
+// feature depend on that feature's column only); the counts come with the
+// first slice, the objective and the stop decision with the last.
+hipError_t enqueue_reduce_finalize(km_plan* p, const PassArgs& a, const FinArgs& f, hipStream_t s)
+{
+    hipError_t e;
+    if (!p->wide) {
+        if ((e = enqueue_update(p, a, p->D8, false, s)) != hipSuccess) return e;
+        return launch_finalize(f, s);
+    }
+    for (int sl = 0; sl < p->nsl; ++sl) {
+        const int c0 = sl * p->dsl, w = std::min(p->dsl, p->d - c0);
+        PassArgs as = a;
+        as.X = a.X + c0;
+        as.d = w;
+        if ((e = enqueue_update(p, as, p->D8s(sl), sl > 0, s)) != hipSuccess) return e;
+        FinArgs fs = f;
+        fs.d = w;
+        fs.C_old = f.C_old ? f.C_old + c0 : nullptr;
+        fs.C_new = f.C_new ? f.C_new + c0 : nullptr;
+        fs.Cp_out = f.Cp_out ? f.Cp_out + c0 : nullptr;
+        fs.S_out = f.S_out ? f.S_out + c0 : nullptr;
+        fs.counts = sl == 0 ? f.counts : nullptr;
+        fs.want_J = sl == p->nsl - 1 ? f.want_J : 0;
+        if ((e = launch_finalize(fs, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Mixed path: the screening MFMA pass (the plan's format), the BF16 refining
@@ -358,11 +396,13 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     if (k < 1 || (int64_t)k > n) return fail(KM_EINVAL, "k = %d outside [1, n]", k);
     if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3)
         return fail(KM_EINVAL, "unknown precision %d", (int)prec);
-    if (d > 8 * kMaxD8Plain) return fail(KM_ENOTSUP, "this build supports d <= %d (got %d)", 8 * kMaxD8Plain, d);
+    if (prec != KM_FP32 && d > 16 * kMaxD16Mix)
+        return fail(KM_ENOTSUP, "BF16 and FP8 distances support d <= %d (got %d)", 16 * kMaxD16Mix, d);
     if (prec != KM_FP32 && ((int64_t)k + kMixCK - 1) / kMixCK * kMixCK > 16384)
         return fail(KM_ENOTSUP, "BF16 and FP8 distances support k <= 16384 (got %d)", k);
-    if (plain_lds_bytes(k, d, MODE_FUSED) > 80 * 1024 &&
-        ((int64_t)k + chunk_labels(k, d) - 1) / chunk_labels(k, d) > kPartMaxChunks)
+    const int dsl = std::min<int>(d, kSliceD);   // features per reduce slice
+    if (plain_lds_bytes(k, dsl, MODE_FUSED) > 80 * 1024 &&
+        ((int64_t)k + chunk_labels(k, dsl) - 1) / chunk_labels(k, dsl) > kPartMaxChunks)
         return fail(KM_ENOTSUP, "k = %d needs more than %d label chunks at d = %d", k, kPartMaxChunks, d);
 
     int dev = 0;
@@ -377,6 +417,10 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     p->n = n; p->d = d; p->k = k; p->prec = prec; p->device = dev; p->num_cu = ncu;
     p->D8 = (d + 7) / 8;
     p->D = 8 * p->D8;
+    p->wide = d > kSliceD;
+    p->dsl = dsl;
+    p->nsl = (d + dsl - 1) / dsl;
+    const int D8u = (dsl + 7) / 8;   // chunks of a full reduce slice
     const int64_t ntiles = (n + plain_tile(p->D8) - 1) / plain_tile(p->D8);
 
     // The per-label record (k x d FP64 + counts) lives in LDS.  The assign and
@@ -385,21 +429,22 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     // reduce over the whole record up to 80 KiB and, above it, over label
     // chunks of at most 44 KiB: the samples are partitioned by chunk, then a
     // 2-D grid of (point range, label chunk) blocks reduces each chunk.
-    p->lds_fused = plain_lds_bytes(k, d, MODE_FUSED);
+    p->lds_fused = plain_lds_bytes(k, dsl, MODE_FUSED);
     p->chunked = p->lds_fused > 80 * 1024;
-    p->kc = p->chunked ? chunk_labels(k, d) : k;
+    p->kc = p->chunked ? chunk_labels(k, dsl) : k;
     p->nch = (k + p->kc - 1) / p->kc;
     p->nsub = p->chunked ? (int)((n + kPartRows - 1) / kPartRows) : 0;
 
     // One resident wave of blocks for the persistent passes, at most 4 per CU.
-    const int per_cu_assign = plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
-    const int per_cu_fused = p->chunked ? 0 : plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused);
-    if (per_cu_assign < 1 || (!p->chunked && per_cu_fused < 1)) {
+    // Wide rows: the streaming assign, never fused with the reduce.
+    const int per_cu_assign = p->wide ? wide_blocks_per_cu() : plain_blocks_per_cu(p->D8, MODE_ASSIGN, 0);
+    const int per_cu_fused = (p->chunked || p->wide) ? 0 : plain_blocks_per_cu(p->D8, MODE_FUSED, p->lds_fused);
+    if (per_cu_assign < 1 || (!p->chunked && !p->wide && per_cu_fused < 1)) {
         delete p;
         return fail(KM_EHIP, "occupancy query for the per-sample pass failed");
     }
     int per_cu = std::min(per_cu_assign, 4);
-    p->split = p->chunked || per_cu_fused < per_cu;
+    p->split = p->chunked || p->wide || per_cu_fused < per_cu;
     // A stand-alone update lists kUpdTiles tiles per step; the update that
     // must walk the fused pass's blocks (no split) keeps its LDS and lists one.
     p->upd_tiles = p->split ? kUpdTiles : 1;
@@ -408,13 +453,13 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     // and adds its chunk's samples; every row is still read once).
     if (p->split && !p->chunked) {
         int c = 1;
-        while (c < 4 && plain_lds_bytes((k + c - 1) / c, d, MODE_UPDATE, p->upd_tiles) > 53 * 1024) ++c;
+        while (c < 4 && plain_lds_bytes((k + c - 1) / c, dsl, MODE_UPDATE, p->upd_tiles) > 53 * 1024) ++c;
         p->kc = (k + c - 1) / c;
         p->nch = (k + p->kc - 1) / p->kc;
     }
-    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, d) : plain_lds_bytes(p->kc, d, MODE_UPDATE, p->upd_tiles);
-    int per_cu_upd = p->chunked ? part_update_blocks_per_cu(p->D8, p->lds_upd)
-                                : plain_blocks_per_cu(p->D8, MODE_UPDATE, p->lds_upd);
+    p->lds_upd = p->chunked ? part_update_lds_bytes(p->kc, dsl) : plain_lds_bytes(p->kc, dsl, MODE_UPDATE, p->upd_tiles);
+    int per_cu_upd = p->chunked ? part_update_blocks_per_cu(D8u, p->lds_upd)
+                                : plain_blocks_per_cu(D8u, MODE_UPDATE, p->lds_upd);
     if (per_cu_upd < 1) {
         delete p;
         return fail(KM_EHIP, "occupancy query for the update pass failed");
@@ -456,7 +501,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     size_t off = 0;
     p->off_ctrl = off; off = align256(off + sizeof(Ctrl));
     p->off_cp = off;   off = align256(off + (size_t)k * p->D * sizeof(float));
-    p->off_pS = off;   off = align256(off + (size_t)p->GS() * k * d * sizeof(double));
+    p->off_pS = off;   off = align256(off + (size_t)p->GS() * k * dsl * sizeof(double));
     p->off_pcnt = off; off = align256(off + (size_t)p->GS() * k * sizeof(int32_t));
     p->off_pJ = off;   off = align256(off + (size_t)p->grid * sizeof(double));
     p->off_pch = off;  off = align256(off + (size_t)std::max(p->grid, 3 * p->grid_mfma + p->grid_rc) * sizeof(int32_t));
@@ -580,13 +625,11 @@ km_status enqueue_label_reduce(km_plan* plan, const float* X, const int32_t* lab
             return fail(KM_EINVAL, "%lld labels lie outside [0, %d)", (long long)bad, plan->k);
     }
     PassArgs a = pass_args(plan, X, nullptr, const_cast<int32_t*>(labels));
-    e = enqueue_update(plan, a, stream);
-    if (e != hipSuccess) return hip_fail(e, "update pass launch");
     FinArgs f = fin_args(plan);
     f.C_old = C_old; f.ld_old = plan->d; f.C_new = C_new; f.ld_new = plan->d; f.Cp_out = nullptr;
     f.counts = counts; f.want_J = 0; f.S_out = S_out;
-    e = launch_finalize(f, stream);
-    if (e != hipSuccess) return hip_fail(e, "finalize launch");
+    e = enqueue_reduce_finalize(plan, a, f, stream);
+    if (e != hipSuccess) return hip_fail(e, "update / finalize launch");
     return KM_OK;
 }
 
@@ -625,6 +668,7 @@ km_status kmeans_assign_metric(km_plan* plan, const float* X, km_layout layout, 
     if (layout != KM_ROW_MAJOR && layout != KM_FEATURE_MAJOR) return fail(KM_EINVAL, "unknown layout %d", (int)layout);
     if (metric != KM_METRIC_L1 && metric != KM_METRIC_SQEUCLIDEAN) return fail(KM_EINVAL, "unknown metric %d", (int)metric);
     if (plan->mixed) return fail(KM_ENOTSUP, "kmeans_assign_metric needs an FP32 plan");
+    if (plan->wide) return fail(KM_ENOTSUP, "kmeans_assign_metric supports d <= %d (got %d)", kSliceD, plan->d);
     if ((st = set_device(plan)) != KM_OK) return st;
     hipError_t e = launch_pad_centroids(C, plan->k, plan->d, plan->D, cp_of(plan), nullptr, stream);
     if (e != hipSuccess) return hip_fail(e, "pad_centroids launch");
@@ -820,19 +864,19 @@ km_status enqueue_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels
         if (plan->mixed) {
             e = enqueue_mixed_assign(plan, X, labels, a.ctrl, t, 1, stream);
             if (e != hipSuccess) return hip_fail(e, "mixed assign launch");
-            e = enqueue_update(plan, a, stream);
-            if (e != hipSuccess) return hip_fail(e, "update pass launch");
+            e = enqueue_reduce_finalize(plan, a, f, stream);
+            if (e != hipSuccess) return hip_fail(e, "update / finalize launch");
         } else if (!plan->split) {
             e = timed_pass(plan, MODE_FUSED, a, dim3(plan->grid), plan->lds_fused, stream);
             if (e != hipSuccess) return hip_fail(e, "fused pass launch");
+            e = launch_finalize(f, stream);
+            if (e != hipSuccess) return hip_fail(e, "finalize launch");
         } else {
             e = timed_pass(plan, MODE_ASSIGN, a, dim3(plan->grid), 0, stream);
             if (e != hipSuccess) return hip_fail(e, "assign pass launch");
-            e = enqueue_update(plan, a, stream);
-            if (e != hipSuccess) return hip_fail(e, "update pass launch");
+            e = enqueue_reduce_finalize(plan, a, f, stream);
+            if (e != hipSuccess) return hip_fail(e, "update / finalize launch");
         }
-        e = launch_finalize(f, stream);
-        if (e != hipSuccess) return hip_fail(e, "finalize launch");
     }
     return KM_OK;
 }

@@ -272,7 +272,7 @@ km_status upload(km_batch* B)
         PassArgs& a = pa[i];
         std::memset(&a, 0, sizeof a);
         a.X = x.X; a.Cp = Cp; a.labels = x.labels; a.mindist = nullptr; a.part = pt; a.ctrl = nullptr;
-        a.n = x.n; a.d = x.d; a.k = x.k; a.iter = 0; a.count_changed = 0; a.kc = x.k; a.upd_tiles = kUpdTiles;
+        a.n = x.n; a.d = x.d; a.ldx = x.d; a.k = x.k; a.iter = 0; a.count_changed = 0; a.kc = x.k; a.upd_tiles = kUpdTiles;
         FinArgs& f = fa[i];
         std::memset(&f, 0, sizeof f);
         f.part = pt; f.G = B->nslots[i]; f.GJ = B->nslots[i]; f.GC = B->nslots[i];

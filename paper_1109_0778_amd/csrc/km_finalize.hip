@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
         if (a.C_new) a.C_new[(size_t)j * a.ld_new + f] = v;
         if (a.Cp_out) a.Cp_out[(size_t)j * a.D + f] = v;
         if (a.counts && f == 0) a.counts[j] = c;
-        if (a.S_out) a.S_out[e] = S;
+        if (a.S_out) a.S_out[(size_t)j * a.ld_S + f] = S;
         const double co = (double)old;
         term = (double)c * co * co - 2.0 * co * S;
     }

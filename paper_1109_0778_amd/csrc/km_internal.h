@@ -44,8 +44,9 @@ struct PassArgs {
     Partials part;
     const Ctrl* ctrl;     // early-exit control (tolerance mode), or nullptr
     int64_t n;
-    int32_t d;
+    int32_t d;            // features of the pass (a slice of the row when rows are reduced in slices)
     int32_t k;
+    int32_t ldx;          // row stride of X (the full row length)
     int32_t iter;         // Lloyd iteration index (0 outside kmeans_lloyd)
     int32_t count_changed;// assign passes: count labels that differ from the stored ones
     int32_t kc;           // update passes: labels per chunk; block y owns labels [y*kc, y*kc+kc)
@@ -92,7 +93,8 @@ struct FinArgs {
     double* Jterm;                        // [ceil(k*d/64)] (jmode 1)
     const double* sum_xn2;                // (jmode 1)
     int32_t GC;                           // changed partial slots in part.changed
-    double* S_out;                        // [k*d] combined FP64 sums, or nullptr
+    double* S_out;                        // [k x ld_S] combined FP64 sums, or nullptr
+    int32_t ld_S;                         // row stride of S_out
 };
 
 // Launchers (return the launch status).
@@ -161,6 +163,11 @@ struct MetricArgs {
     int32_t d, k;
 };
 hipError_t launch_assign_metric(int D8, int metric, int layout, const MetricArgs& a, int grid, hipStream_t s);
+// Rows of more than 128 features: streaming assign with the plain path's
+// canonical distance (the per-label reduce then runs over 128-feature slices).
+constexpr int kSliceD = 128;
+hipError_t launch_assign_wide(const PassArgs& a, int grid, hipStream_t s);
+int wide_blocks_per_cu();
 
 // Samples per lane in the plain pass.  One: measured on MI355X at d = 64,
 // k = 64, two samples per lane (sharing each SGPR centroid operand) ran 18%

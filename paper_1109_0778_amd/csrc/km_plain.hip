@@ -240,7 +240,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
             const bool valid = gp < n;
             // the previous label is fetched with the row, not after the sweep
             old[r] = (valid && a.count_changed && a.iter != 0) ? a.labels[gp] : -1;
-            load_row<D8>(a.X + (valid ? gp : 0) * d, d, valid, x[r]);
+            load_row<D8>(a.X + (valid ? gp : 0) * a.ldx, d, valid, x[r]);
         }
         float best[R];
         int bj[R];
@@ -272,8 +272,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
             int lt[TILE / 64];
 #pragma unroll
             for (int g = 0; g < TILE / 64; ++g) lt[g] = lb[g * 64 + lane];
-            const float* Xt = a.X + t * TILE * (int64_t)d;
-            accumulate_step<D8, TILE>([&](int pos) { return Xt + pos * d; }, d, lt, TILE,
+            const float* Xt = a.X + t * TILE * (int64_t)a.ldx;
+            accumulate_step<D8, TILE>([&](int pos) { return Xt + pos * a.ldx; }, d, lt, TILE,
                                       wlist + wave * list_bufs(D8) * TILE, S, cnt, lane, wave);
         }
     } else if constexpr (UPD) {
@@ -311,8 +311,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int64_t t_first, in
                         lab[g] = L[g] - j0;   // chunk-local label
                 }
                 // the step's samples are consecutive (one tile, or contiguous tiles)
-                const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)d;
-                auto row_of = [&](int pos) { return Xs + pos * d; };
+                const float* Xs = a.X + tile_of(st, 0) * TILE * (int64_t)a.ldx;
+                auto row_of = [&](int pos) { return Xs + pos * a.ldx; };
                 accumulate_step<D8, UT * TILE>(row_of, d, lab, UT * TILE, wlist + wave * list_bufs(D8) * UT * TILE,
                                                S, cnt, lane, wave);
             }
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void part_update_kernel(PassArgs a)
             for (int u = 0; u < B; ++u) {
                 int r = __builtin_amdgcn_readlane(ri, u);
                 r = r >= 0 ? r : first;
-                const float* row = a.X + (int64_t)r * d;
+                const float* row = a.X + (int64_t)r * a.ldx;
 #pragma unroll
                 for (int m = 0; m < FPL; ++m) v[u][m] = row[fc[m]];
             }
