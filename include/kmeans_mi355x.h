@@ -29,10 +29,11 @@
  *     device array per GPU that the library's code object holds.
  *   - On any error nothing is enqueued, outputs are untouched, the status is
  *     returned and km_last_error() describes it.  No exception crosses the ABI.
- *   - Shape limits: 1 <= k <= n < 2^31, 1 <= d <= 1024 (the FP32 path
- *     currently supports d <= 128 and returns KM_ENOTSUP above that; a
- *     per-label record k * d * 8 bytes above 80 KiB is reduced over label
- *     chunks of 44 KiB, at most 16384 of them, KM_ENOTSUP beyond).
+ *   - Shape limits: 1 <= k <= n < 2^31, 1 <= d <= 1024.  Rows of more than
+ *     128 features are assigned by a streaming pass (same distance, operation
+ *     for operation) and reduced in 128-feature slices; a per-label record
+ *     k * min(d, 128) * 8 bytes above 80 KiB is reduced over label chunks of
+ *     44 KiB, at most 16384 of them (KM_ENOTSUP beyond).
  *   - Inputs must be finite; NaN/Inf are not checked on the hot path.
  *   - A plan is not thread-safe; distinct plans are independent.  Calls that
  *     share one plan (one workspace) must be ordered on one stream.
@@ -55,8 +56,10 @@
  * J = sum_i |x_i|^2 + sum_j (cnt_j |c_j|^2 - 2 c_j . S_j).  FP8 scales each
  * feature by a power of two s_f >= max_i |x_if| / 448 (exact) and keeps an
  * e4m3 copy of X in the workspace, made once per call; both keep a BF16 copy
- * of X (n x 16 ceil(d/16) x 2 bytes) made once per call; d <= 128 and
- * k <= 16384 for both (KM_ENOTSUP otherwise).
+ * of X (n x 16 ceil(d/16) x 2 bytes) made once per call; k <= 16384 for both
+ * (KM_ENOTSUP otherwise).  Above 128 features the matrix-core operands are
+ * streamed from memory through the contraction instead of being held in
+ * registers and LDS.
  */
 #ifndef KMEANS_MI355X_H
 #define KMEANS_MI355X_H

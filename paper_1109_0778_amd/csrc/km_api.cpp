@@ -224,6 +224,7 @@ hipError_t enqueue_reduce_finalize(km_plan* p, const PassArgs& a, const FinArgs&
         if ((e = enqueue_update(p, a, p->D8, false, s)) != hipSuccess) return e;
         return launch_finalize(f, s);
     }
+    int jt = 0;
     for (int sl = 0; sl < p->nsl; ++sl) {
         const int c0 = sl * p->dsl, w = std::min(p->dsl, p->d - c0);
         PassArgs as = a;
@@ -238,6 +239,11 @@ hipError_t enqueue_reduce_finalize(km_plan* p, const PassArgs& a, const FinArgs&
         fs.S_out = f.S_out ? f.S_out + c0 : nullptr;
         fs.counts = sl == 0 ? f.counts : nullptr;
         fs.want_J = sl == p->nsl - 1 ? f.want_J : 0;
+        // (mixed plans) each slice's objective terms go to their own Jterm
+        // entries, and the last slice's objective sums all of them
+        fs.jt_off = jt;
+        jt += finalize_blocks(p->k, w);
+        fs.nJterm = jt;
         if ((e = launch_finalize(fs, s)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -279,6 +285,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.IB = p->IB;
     m.gamma_terms = 2 * p->DP + 8;
     m.D8 = p->D8;
+    m.DP = p->DP;
     m.labels = labels;
     m.rq = reinterpret_cast<int32_t*>(ws + p->off_rq);
     m.rq_count = reinterpret_cast<int32_t*>(ws + p->off_rqc);
@@ -345,7 +352,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     r.nreg = G;
     r.labels = labels; r.changed_part = changed + p->mfma_passes() * G;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
-    return launch_recheck(p->D8, r, G, s);
+    return p->wide ? launch_recheck_wide(r, G, s) : launch_recheck(p->D8, r, G, s);
 }
 
 // Run-level prep of the mixed path (once per call, amortised over its
@@ -396,8 +403,6 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
     if (k < 1 || (int64_t)k > n) return fail(KM_EINVAL, "k = %d outside [1, n]", k);
     if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3)
         return fail(KM_EINVAL, "unknown precision %d", (int)prec);
-    if (prec != KM_FP32 && d > 16 * kMaxD16Mix)
-        return fail(KM_ENOTSUP, "BF16 and FP8 distances support d <= %d (got %d)", 16 * kMaxD16Mix, d);
     if (prec != KM_FP32 && ((int64_t)k + kMixCK - 1) / kMixCK * kMixCK > 16384)
         return fail(KM_ENOTSUP, "BF16 and FP8 distances support k <= 16384 (got %d)", k);
     const int dsl = std::min<int>(d, kSliceD);   // features per reduce slice
@@ -511,7 +516,7 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->off_poff = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
         p->off_plen = off; off = align256(off + (size_t)p->nsub * p->nch * sizeof(int32_t));
     }
-    p->off_jt = off;   off = align256(off + (size_t)finalize_blocks(k, d) * sizeof(double));
+    p->off_jt = off;   off = align256(off + (size_t)(finalize_blocks(k, d) + p->nsl) * sizeof(double));
     if (p->mixed) {
         p->off_xs = off;   off = align256(off + sizeof(XStats));
         p->off_pxm = off;  off = align256(off + kXStatBlocks * sizeof(float));

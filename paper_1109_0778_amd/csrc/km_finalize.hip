@@ -20,7 +20,7 @@ __device__ __forceinline__ void objective_wave(const FinArgs& a, int lane)
 #pragma unroll 8
         for (int b = lane; b < a.GJ; b += 64) J += a.part.J[b];
     } else {
-        const int nb = finalize_blocks(a.k, a.d);
+        const int nb = a.nJterm > 0 ? a.nJterm : finalize_blocks(a.k, a.d);
 #pragma unroll 8
         for (int b = lane; b < nb; b += 64) J += a.Jterm[b];
     }
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64 * kFinWaves) void finalize_kernel(FinArgs a)
     if (a.jmode == 1) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
-        if (lane == 0) a.Jterm[blockIdx.x] = term;
+        if (lane == 0) a.Jterm[a.jt_off + blockIdx.x] = term;
     }
 }
 

@@ -95,6 +95,8 @@ struct FinArgs {
     int32_t GC;                           // changed partial slots in part.changed
     double* S_out;                        // [k x ld_S] combined FP64 sums, or nullptr
     int32_t ld_S;                         // row stride of S_out
+    int32_t jt_off;                       // (jmode 1) this launch's first block in Jterm
+    int32_t nJterm;                       // (jmode 1) Jterm entries the objective sums (0: this launch's)
 };
 
 // Launchers (return the launch status).
@@ -220,7 +222,8 @@ constexpr int kCandSlots = kCandCap + 8;        // room for 8 appends
 // aligned and rounded up to a multiple of 8.
 constexpr int kRqHead = 4;
 constexpr int kRqInts = kRqHead + (2 * kCandCap + 7) / 8 * 8;
-constexpr int kMaxD16Mix = 8;                   // mixed path: d <= 128
+constexpr int kMaxD16Mix = 8;                   // operands held in registers / LDS up to d = 128
+constexpr int kMaxD16Wide = 64;                 // beyond: operands streamed from memory, up to d = 1024
 constexpr int kXStatBlocks = 256;
 constexpr int kFmaxBlocks = 1024;               // FP8 per-feature maxima
 constexpr int kRecheckSplit = 8;                // recheck blocks per MFMA block's queue region
@@ -254,6 +257,7 @@ struct MixArgs {
     int32_t IB;                 // index bits in a key
     int32_t gamma_terms;        // m of the gamma_m accumulation bound
     int32_t D8;                 // chunks of the canonical FP32 distance
+    int32_t DP;                 // padded operand width (16 * ceil(d / 16))
     int32_t* labels;
     int32_t* rq;                // [nreg][rq_per_block][rq_ints] recheck entries, one region per block
     int32_t* rq_count;          // [2][nreg] entries queued in each region, then full scans among them
@@ -287,6 +291,8 @@ struct RecheckArgs {
     int32_t iter;
     int32_t count_changed;
 };
+// Exact recheck of the mixed path for rows of more than 128 features.
+hipError_t launch_recheck_wide(const RecheckArgs& a, int G, hipStream_t s);
 
 hipError_t launch_prep_x(const float* X, int64_t n, int32_t d, float* part_max, double* part_sum,
                          XStats* xs, hipStream_t s);

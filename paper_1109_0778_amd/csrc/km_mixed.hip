@@ -146,7 +146,7 @@ __global__ void prep_x_combine_kernel(const float* part_max, const double* part_
 __global__ __launch_bounds__(256) void prep_fmax_kernel(const float* __restrict__ X, int64_t n, int32_t d,
                                                         int32_t DP, float* part_fmax)
 {
-    __shared__ uint32_t smax[16 * kMaxD16Mix];
+    __shared__ uint32_t smax[16 * kMaxD16Wide];
     const int tid = threadIdx.x;
     for (int f = tid; f < DP; f += 256) smax[f] = 0u;
     __syncthreads();
@@ -202,23 +202,38 @@ __device__ __forceinline__ uint32_t fp8_of(float v)
     return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
 }
 
-// Eight features of one row per thread: a row takes G adjacent lanes (G =
-// DP / 8 rounded up to a power of two, at most 16; lanes past DP / 8 idle), so
-// the row is read and written coalesced and its sums are completed by an xor
-// tree across those lanes.  f0: the thread's first feature; x[8]: its
-// features (zero past d); the result: the thread holds a chunk of a row.
+// Eight features of one row per thread and chunk: a row takes G adjacent
+// lanes (G = DP / 8 rounded up to a power of two, at most 16; lanes past
+// DP / 8 idle), lane g holding chunks g, g + G, ... (one chunk up to DP =
+// 128), so the row is read and written coalesced and its sums are completed
+// by an xor tree across those lanes.
 __host__ __device__ constexpr int row_lanes_q(int DP)
 {
     return DP / 8 <= 2 ? 2 : DP / 8 <= 4 ? 4 : DP / 8 <= 8 ? 8 : 16;
 }
+__host__ __device__ constexpr int row_chunks_q(int DP) { return DP / 8 <= 16 ? 1 : (DP / 8 + 15) / 16; }
 
-__device__ __forceinline__ bool row_chunk(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
+// Relative upward margin that makes sqrt of an FP32 sum of squares of a row
+// (8 C sequential FMA terms per lane, then a log2 G-level tree) an upper
+// bound of the exact norm: half the sum's relative error plus the rounding
+// of the square root and of the product, with room to spare.
+__host__ __device__ inline float norm_margin(int DP)
+{
+    const int C = row_chunks_q(DP), G = row_lanes_q(DP);
+    const int lg = G <= 2 ? 1 : G <= 4 ? 2 : G <= 8 ? 3 : 4;
+    const float m = (float)((8 * C + lg) / 2 + 4) * 5.9604645e-8f;
+    return m > 1e-6f ? m : 1e-6f;
+}
+
+// Row i and chunk (lane g, pass c) of the calling thread; x[8]: the chunk's
+// features (zero past d).  Returns whether the thread holds a live chunk.
+__device__ __forceinline__ bool row_chunk(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP, int c,
                                           int64_t& i, int& f0, float (&x)[8])
 {
     const int G = row_lanes_q(DP);
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     i = t / G;
-    f0 = 8 * (int)(t - i * G);
+    f0 = 8 * ((int)(t - i * G) + G * c);
     const bool live = i < n && f0 < DP;
     const float* row = X + (live ? i : 0) * d;
     if ((d & 7) == 0) {
@@ -251,48 +266,58 @@ __device__ __forceinline__ T row_sum(T v, int cpr)
 __global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
                                                       const float* __restrict__ fscale, uint8_t* Xq, float2* xst)
 {
-    int64_t i;
-    int f0;
-    float x[8];
-    const bool live = row_chunk(X, n, d, DP, i, f0, x);
     const float* inv = fscale + DP;
     float s2 = 0.0f, l1 = 0.0f;
-    uint32_t w[2] = {0u, 0u};
+    int64_t i = 0;
+    bool live0 = false;
+    for (int c = 0; c < row_chunks_q(DP); ++c) {
+        int f0;
+        float x[8];
+        const bool live = row_chunk(X, n, d, DP, c, i, f0, x);
+        if (c == 0) live0 = live;
+        uint32_t w[2] = {0u, 0u};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float xt = x[q] * inv[f0 + q < DP ? f0 + q : DP - 1];   // idle lanes: a valid index
-        s2 = __builtin_fmaf(x[q], x[q], s2);
-        l1 += fabsf(xt);
-        w[q >> 2] |= fp8_of(xt) << (8 * (q & 3));
+        for (int q = 0; q < 8; ++q) {
+            const float xt = x[q] * inv[f0 + q < DP ? f0 + q : DP - 1];   // idle lanes: a valid index
+            s2 = __builtin_fmaf(x[q], x[q], s2);
+            l1 += fabsf(xt);
+            w[q >> 2] |= fp8_of(xt) << (8 * (q & 3));
+        }
+        if (live) *reinterpret_cast<uint2*>(Xq + i * DP + f0) = make_uint2(w[0], w[1]);
     }
     s2 = row_sum(s2, row_lanes_q(DP));
     l1 = row_sum(l1, row_lanes_q(DP));
-    if (!live) return;
-    *reinterpret_cast<uint2*>(Xq + i * DP + f0) = make_uint2(w[0], w[1]);
-    if (f0 == 0) xst[i] = make_float2(sqrtf(s2) * (1.0f + 1e-6f), l1 * (1.0f + 1e-5f));
+    const int G = row_lanes_q(DP);
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (live0 && t % G == 0) xst[i] = make_float2(sqrtf(s2) * (1.0f + norm_margin(DP)), l1 * (1.0f + 1e-5f));
 }
 
 // Once per call: the BF16 copy of X the BF16 MFMA passes read (rounded to
 // nearest even, zero padded to DP features) and an upper bound of |x| per
-// sample.  One thread per sample.
+// sample.
 __global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
                                                            int32_t DP, __bf16* Xb, float* xn)
 {
-    int64_t i;
-    int f0;
-    float x[8];
-    const bool live = row_chunk(X, n, d, DP, i, f0, x);
     float s2 = 0.0f;
-    bf16x8 w;
+    int64_t i = 0;
+    bool live0 = false;
+    for (int c = 0; c < row_chunks_q(DP); ++c) {
+        int f0;
+        float x[8];
+        const bool live = row_chunk(X, n, d, DP, c, i, f0, x);
+        if (c == 0) live0 = live;
+        bf16x8 w;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        s2 = __builtin_fmaf(x[q], x[q], s2);
-        w[q] = (__bf16)x[q];
+        for (int q = 0; q < 8; ++q) {
+            s2 = __builtin_fmaf(x[q], x[q], s2);
+            w[q] = (__bf16)x[q];
+        }
+        if (live) *reinterpret_cast<bf16x8*>(Xb + i * DP + f0) = w;
     }
     s2 = row_sum(s2, row_lanes_q(DP));
-    if (!live) return;
-    *reinterpret_cast<bf16x8*>(Xb + i * DP + f0) = w;
-    if (f0 == 0) xn[i] = sqrtf(s2) * (1.0f + 1e-6f);
+    const int G = row_lanes_q(DP);
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (live0 && t % G == 0) xn[i] = sqrtf(s2) * (1.0f + norm_margin(DP));
 }
 
 // ------------------------------------------------------ per-iteration prep
@@ -334,7 +359,7 @@ __device__ __forceinline__ void prep_c_body(const float* __restrict__ Cp, int32_
         __syncthreads();
     }
     if (tid == 0) {
-        const float m = smax[0] * (1.0f + 1e-5f);
+        const float m = smax[0] * (1.0f + fmaxf(1e-5f, (float)(d + 4) * 5.9604645e-8f));
         cs->K = K;
         cs->cn2max = m;
         cs->cmax = sqrtf(m) * (1.0f + 1e-6f);
@@ -394,7 +419,7 @@ __global__ __launch_bounds__(256) void prep_c_rows_kernel(const float* __restric
     }
 }
 
-__global__ __launch_bounds__(64) void prep_c_stats_kernel(const float* __restrict__ part_cn2, int nb,
+__global__ __launch_bounds__(64) void prep_c_stats_kernel(const float* __restrict__ part_cn2, int nb, int32_t d,
                                                           const XStats* __restrict__ xs, CStats* cs,
                                                           const Ctrl* ctrl, int32_t iter)
 {
@@ -405,7 +430,7 @@ __global__ __launch_bounds__(64) void prep_c_stats_kernel(const float* __restric
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if (lane == 0) {
-        const float mm = m * (1.0f + 1e-5f);
+        const float mm = m * (1.0f + fmaxf(1e-5f, (float)(d + 4) * 5.9604645e-8f));
         cs->K = xs->K;
         cs->cn2max = mm;
         cs->cmax = sqrtf(mm) * (1.0f + 1e-6f);
@@ -520,7 +545,7 @@ __global__ __launch_bounds__(256) void prep_c_fp8_kernel(const float* __restrict
         const float r = pow2_scale(samax[0], kFp8Max);
         sr[0] = 1.0f / r;                   // exact
         sr[1] = 0.5f / r;
-        const float m = smax[0] * (1.0f + 1e-5f);
+        const float m = smax[0] * (1.0f + fmaxf(1e-5f, (float)(d + 4) * 5.9604645e-8f));
         cs->cn2max = m;
         cs->cmax = sqrtf(m) * (1.0f + 1e-6f);
     }
@@ -564,7 +589,7 @@ __global__ __launch_bounds__(256) void prep_c_fp8_kernel(const float* __restrict
         cs->K = K;
         cs->inv2r = inv2r;
         cs->inv_r = inv_r;
-        cs->cl1 = smax[0] * (1.0f + 1e-5f);
+        cs->cl1 = smax[0] * (1.0f + fmaxf(1e-5f, (float)(d + 4) * 5.9604645e-8f));
         cs->pad[0] = cs->pad[1] = 0.0f;
     }
 }
@@ -607,9 +632,14 @@ template <int D16, int FMT, int STAGE>
 __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
                                           int region, unsigned char* smem)
 {
+    // D16 = 0: rows of more than 128 features; the operands are streamed
+    // from memory (L2) through the MFMA chain instead of being held in
+    // registers (samples) and staged in LDS (centroids)
+    constexpr bool WIDE = D16 == 0;
     constexpr bool F8 = FMT == FMT_FP8;
     constexpr int ES = F8 ? 1 : 2;         // operand bytes per feature
     constexpr int DP = 16 * D16;
+    const int DPr = WIDE ? a.DP : DP;      // operand row width
     constexpr int ROWB = DP * ES + 16;     // padded LDS row: conflict-free reads
     constexpr int NB = mix_nb(STAGE);
     constexpr int TILE = mix_tile(STAGE);   // samples per block per tile
@@ -618,7 +648,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     constexpr int CAP = kCandCap;
     constexpr int SLOTS = kCandSlots;
     constexpr int RQI = kRqInts;
-    constexpr int PF = (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
+    constexpr int PF = WIDE ? 1 : (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
     unsigned char* Abuf = smem;                                                   // [2][CK][ROWB]
     float* bbuf = reinterpret_cast<float*>(smem + 2 * CHB);                       // [2][CK]
     uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + 2 * kMixCK);              // [waves][NB][SLOTS][64]
@@ -690,8 +720,9 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
 
     for (int64_t t = t_first; t < t_last; t += t_step) {
         // --- B fragments and the band of this wave's samples
-        bf16x8 bfr[NB][F8 ? 1 : D16];
-        long bq[NB][F8 ? D16 : 1];
+        bf16x8 bfr[NB][(F8 || WIDE) ? 1 : D16];
+        long bq[NB][(F8 && !WIDE) ? D16 : 1];
+        const unsigned char* brow[NB];     // WIDE: this lane's half of the sample's operand row
         float W[NB];
         int64_t pidx[NB];
         uint32_t mfix[NB];   // stage 3: the screen's smallest key of the sample
@@ -703,9 +734,13 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
             pidx[nb] = p;
             const bool valid = p < n;
             if constexpr (F8) {
-                const uint8_t* qrow = a.Xq + (valid ? p : 0) * DP + 8 * h;
+                const uint8_t* qrow = a.Xq + (valid ? p : 0) * DPr + 8 * h;
+                if constexpr (WIDE) {
+                    brow[nb] = qrow;       // an invalid sample's keys are never used
+                } else {
 #pragma unroll
-                for (int s = 0; s < D16; ++s) bq[nb][s] = valid ? *reinterpret_cast<const long*>(qrow + 16 * s) : 0l;
+                    for (int s = 0; s < D16; ++s) bq[nb][s] = valid ? *reinterpret_cast<const long*>(qrow + 16 * s) : 0l;
+                }
                 const float2 st = valid ? a.xst[p] : make_float2(0.0f, 0.0f);
                 const float xn = st.x;
                 const float u = a.u;
@@ -720,13 +755,17 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 W[nb] = (2.0f * B + 2.01f * gcan * r * r * inv2r) * 1.001f;
             } else {
                 float xn;
-                if (a.Xb != nullptr) {
+                if (WIDE || a.Xb != nullptr) {
                     // the run's BF16 copy: one 16-byte load per 16 features
-                    const bf16x8* xr = reinterpret_cast<const bf16x8*>(a.Xb + (valid ? p : 0) * DP + 8 * h);
+                    const bf16x8* xr = reinterpret_cast<const bf16x8*>(a.Xb + (valid ? p : 0) * DPr + 8 * h);
+                    if constexpr (WIDE) {
+                        brow[nb] = reinterpret_cast<const unsigned char*>(xr);
+                    } else {
 #pragma unroll
-                    for (int s = 0; s < D16; ++s) bfr[nb][s] = xr[2 * s];
+                        for (int s = 0; s < D16; ++s) bfr[nb][s] = xr[2 * s];
+                    }
                     xn = valid ? a.xn[p] : 0.0f;
-                } else {
+                } else if constexpr (!WIDE) {
                     const float* row = a.X + (valid ? p : 0) * d;
                     float s2 = 0.0f;
 #pragma unroll
@@ -807,6 +846,27 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 // raised wave priority while the MFMA chain issues keeps the
                 // matrix pipe fed while other waves run their epilogues
                 __builtin_amdgcn_s_setprio(1);
+                if constexpr (WIDE) {
+                    // centroid and sample operands straight from memory, one
+                    // 16-feature step at a time
+                    const unsigned char* ag = static_cast<const unsigned char*>(a.Ab) +
+                                              ((size_t)(c * kMixCK + tt * 32 + col) * DPr + 8 * h) * ES;
+                    for (int s = 0; s < DPr / 16; ++s) {
+                        if constexpr (F8) {
+                            const long af = *reinterpret_cast<const long*>(ag + 16 * s);
+#pragma unroll
+                            for (int nb = 0; nb < NB; ++nb)
+                                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(
+                                    af, *reinterpret_cast<const long*>(brow[nb] + 16 * s), acc[nb], 0, 0, 0);
+                        } else {
+                            const bf16x8 af = *reinterpret_cast<const bf16x8*>(ag + 32 * s);
+#pragma unroll
+                            for (int nb = 0; nb < NB; ++nb)
+                                acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    af, *reinterpret_cast<const bf16x8*>(brow[nb] + 32 * s), acc[nb], 0, 0, 0);
+                        }
+                    }
+                }
 #pragma unroll
                 for (int s = 0; s < D16; ++s) {
                     if constexpr (F8) {
@@ -824,7 +884,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 __builtin_amdgcn_s_setprio(0);
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
-                if constexpr (SCREEN && D16 > 5) {
+                if constexpr (SCREEN && (WIDE || D16 > 5)) {
                     // the two smallest keys of the chunk so far (lm <= lm2),
                     // one key at a time (3 VALU operations per key): at 96 or
                     // more features the MFMA chain outlasts the epilogue
@@ -1294,7 +1354,7 @@ hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t
                            static_cast<__bf16*>(Ab), bias, part_cn2, ctrl, iter);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(prep_c_stats_kernel, dim3(1), dim3(64), 0, s, part_cn2, nb, xs, cs, ctrl, iter);
+        hipLaunchKernelGGL(prep_c_stats_kernel, dim3(1), dim3(64), 0, s, part_cn2, nb, d, xs, cs, ctrl, iter);
         return hipGetLastError();
     }
     if (fmt == FMT_FP8)
@@ -1308,6 +1368,7 @@ hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t
 
 size_t mfma_lds_bytes(int fmt, int D16, int stage)
 {
+    // (D16 = 0, rows of more than 128 features: the centroid operands are not staged)
     const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
     return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
            (stage == 1 || stage == 2 ? 0 : (size_t)kMixWaves * mix_nb(stage) * kCandSlots * 64 * sizeof(uint32_t));
@@ -1338,7 +1399,7 @@ static hipError_t launch_mfma_fs(int D16, const MixArgs& a, int grid, hipStream_
     case 6: return launch_mfma_d16<6, FMT, STAGE>(a, grid, s);
     case 7: return launch_mfma_d16<7, FMT, STAGE>(a, grid, s);
     case 8: return launch_mfma_d16<8, FMT, STAGE>(a, grid, s);
-    default: return hipErrorInvalidValue;
+    default: return D16 <= kMaxD16Wide ? launch_mfma_d16<0, FMT, STAGE>(a, grid, s) : hipErrorInvalidValue;
     }
 }
 
@@ -1382,7 +1443,7 @@ static int occ_mfma_fs(int D16)
     case 6: return occ_mfma<6, FMT, STAGE>();
     case 7: return occ_mfma<7, FMT, STAGE>();
     case 8: return occ_mfma<8, FMT, STAGE>();
-    default: return -1;
+    default: return D16 <= kMaxD16Wide ? occ_mfma<0, FMT, STAGE>() : -1;
     }
 }
 

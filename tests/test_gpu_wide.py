@@ -2,7 +2,8 @@
 path: the streaming assign and the reduce over 128-feature slices, against
 the FP64 oracle (needs an MI355X).
 
-Bar: as for the narrow rows, with the canonical form's bound
+Bar (BF16 and FP8 plans: labels and centroids equal the FP32 path's, as
+at d <= 128): as for the narrow rows, with the canonical form's bound
 gamma = (2 + 8 + ceil(log2 P)) 2^-24 (P = ceil(d / 8) chunks): a label can
 differ from the oracle's only where the top-2 margin (d2 - d1) / (d1 + d2)
 is below gamma (1.01e-6 at d = 1024, so the band is max(1e-6, gamma));
@@ -133,10 +134,32 @@ def test_wide_class_sums_and_gda():
     assert np.all(np.abs(S.cpu().numpy() - S_o) <= 2.0 * (c_o[:, None] - 1) * 2.0 ** -53 * absum)
 
 
-def test_wide_mixed_plans_rejected_cleanly():
+@pytest.mark.parametrize("n,d,k,prec", [(3000, 129, 50, "bf16"), (4001, 256, 200, "bf16"), (2500, 1000, 20, "bf16"),
+                                         (2000, 1024, 130, "bf16"), (3000, 136, 40, "fp8"), (2500, 1024, 150, "fp8"),
+                                         (1500, 520, 300, "fp8")])
+def test_wide_mixed_equals_fp32(n, d, k, prec):
+    """BF16 / FP8 MFMA distances with the exact recheck at d > 128: labels and
+    centroids equal the FP32 path's every iteration, and the FP32 path is
+    held to the oracle stepwise."""
     torch = _torch()
     from paper_1109_0778_amd import binding as B
-    for prec in ("bf16", "fp8"):
-        with pytest.raises(B.KMeansError) as ei:
-            B.Plan(1000, 129, 10, prec)
-        assert ei.value.status == B.KM_ENOTSUP
+    say(f"wide mixed n={n} d={d} k={k} {prec}")
+    X, C = datagen.blobs(n, d, k, max(2, k // 3), 1.5, seed=n + 3 * d + k)
+    p32 = B.Plan(n, d, k)
+    pm = B.Plan(n, d, k, prec)
+    Ct = C.copy()
+    for t in range(3):
+        g32 = run_lloyd(torch, B, X, Ct, 1, plan=p32)
+        gm = run_lloyd(torch, B, X, Ct, 1, plan=pm)
+        assert np.array_equal(gm["labels"], g32["labels"]), f"t={t}: labels differ from FP32"
+        assert np.array_equal(gm["C"], g32["C"]) and np.array_equal(gm["counts"], g32["counts"])
+        _, _, J = check_labels_wide(g32["labels"], Ct, X)
+        # the mixed objective comes from the FP64 identity (within 1e-9 of the
+        # oracle's), the FP32 path's from FP32 distances (within 1e-6)
+        assert abs(gm["J"][0] - J) <= 1e-9 * J
+        assert abs(g32["J"][0] - J) <= 1e-6 * J
+        Co, _ = oracle.update(X, g32["labels"], Ct.astype(np.float64))
+        check_centroids(g32["C"], Co, X, f"t={t}")
+        Ct = g32["C"]
+    rc, full = pm.recheck_count()
+    say(f"  last iteration: {rc} rechecks, {full} full scans")
