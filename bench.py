@@ -577,8 +577,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="Lloyd iterations per timed run (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=3, help="untimed Lloyd iterations before the runs")
     ap.add_argument("--runs", type=int, default=10, help="timed runs; the mean of the last five is reported")
-    ap.add_argument("--workload", default="bf16", choices=["bf16", "plain", "fp8", "small", "batched"],
-                    help="headline workload (batched: only the 512-instance workload, for profiling)")
+    ap.add_argument("--workload", default="bf16", choices=["bf16", "plain", "fp8", "small", "batched", "spade"],
+                    help="headline workload (batched, spade: only that workload, for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the error-vs-oracle reports")
     ap.add_argument("--no-plain-workload", action="store_true", help="skip n=2^20, d=64, k=64")
@@ -612,6 +612,12 @@ def main():
     from paper_1109_0778_amd import binding as B
     from paper_1109_0778_amd import datagen
 
+    if args.workload == "spade":
+        rep = spade_report(B, torch, args.runs)
+        rep.update({"metric": "SPADE density step, ms per call", "n_gpus": 1, "higher_is_better": False,
+                    "data": "synthetic"})
+        print(json.dumps(rep), flush=True)
+        return
     if args.workload == "batched":
         rep = batched_report(B, torch, datagen.BATCH_ITERS)
         rep.update({"metric": "instance-iterations/s of the batched workload", "n_gpus": 1,

@@ -50,6 +50,9 @@ constexpr int kSpBMin = 32;             // fewest candidates per batch (while ro
 constexpr int kSpMaxD8Reg = 8;          // d <= 64: the sample row lives in registers
 constexpr int kSpCG = 8;                // wide rows: candidates per pass over a sample row
 constexpr int kSpSelThreads = 1024;     // the first batch's selection block
+// Samples per lane: rows of at most 32 features take two (each candidate
+// operand read from LDS then feeds two samples' FP64 chains), wider rows one.
+__host__ __device__ constexpr int sp_rows(int D8) { return D8 > 0 && D8 <= 4 ? 2 : 1; }
 
 struct SpadeCtrl {
     int64_t cursor;       // every row below is decided or a candidate of the current batch
@@ -189,21 +192,6 @@ __global__ __launch_bounds__(kSpSelThreads) void spade_first_select_kernel(Spade
     select_batch<kSpSelThreads>(a, 0, 64, nullptr, wsum, &s_found);
 }
 
-// Distance of one candidate row (wave-uniform operands) to the lane's
-// sample, features in increasing order.
-template <int D, int METRIC, typename RP>
-__device__ __forceinline__ double cand_dist(const double (&x)[D], RP row)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int f = 0; f < D; ++f) {
-        const double diff = row[f] - x[f];
-        if constexpr (METRIC == 0) acc = acc + __builtin_fabs(diff);
-        else acc = acc + diff * diff;
-    }
-    return acc;
-}
-
 // Count bookkeeping: ballot of "within either width" over the wave, one LDS
 // atomic per wave and candidate.
 __device__ __forceinline__ void count_within(bool within, int lane, int32_t* cnt_s, int c)
@@ -220,18 +208,24 @@ __device__ __forceinline__ void count_within(bool within, int lane, int32_t* cnt
 // chunks of 8 features, kSpCG candidates at a time, each sum still in
 // feature order.
 template <int D8, int METRIC>
-__device__ __forceinline__ void batch_rows(const SpadeArgs& a, int buf, int nc, int64_t j, int32_t* cnt_s,
+__device__ __forceinline__ void batch_rows(const SpadeArgs& a, int buf, int nc, int64_t j0, int32_t* cnt_s,
                                            double* cs)
 {
     const int tid = threadIdx.x, lane = tid & 63;
-    const bool valid = j < a.n;
     const double apprx = a.apprx, kern = a.kern;
     if constexpr (D8 > 0) {
         constexpr int D = 8 * D8;
-        double x[D];
-        const float* row = a.X + (valid ? j : 0) * a.d;
+        constexpr int RR = sp_rows(D8);
+        double x[RR][D];
+        bool valid[RR];
 #pragma unroll
-        for (int f = 0; f < D; ++f) x[f] = (valid && f < a.d) ? (double)row[f] : 0.0;
+        for (int r = 0; r < RR; ++r) {
+            const int64_t j = j0 + r * 256;
+            valid[r] = j < a.n;
+            const float* row = a.X + (valid[r] ? j : 0) * a.d;
+#pragma unroll
+            for (int f = 0; f < D; ++f) x[r][f] = (valid[r] && f < a.d) ? (double)row[f] : 0.0;
+        }
         const double* cg = a.crow + (size_t)buf * kSpB * a.DP;
 #pragma unroll
         for (int g = 0; g < kSpW; ++g) {
@@ -241,16 +235,40 @@ __device__ __forceinline__ void batch_rows(const SpadeArgs& a, int buf, int nc, 
             __syncthreads();                 // the previous chunk is no longer read
             for (int e = tid; e < (c1 - c0) * D; e += 256) cs[e] = cg[(size_t)c0 * D + e];
             __syncthreads();
-            uint64_t word = 0;
+            uint64_t word[RR];
+#pragma unroll
+            for (int r = 0; r < RR; ++r) word[r] = 0;
             for (int c = c0; c < c1; ++c) {
-                const double dist = cand_dist<D, METRIC>(x, cs + (c - c0) * D);
-                const bool nr = dist < apprx;
-                word |= (uint64_t)nr << (c - c0);
-                count_within(valid && (nr || dist < kern), lane, cnt_s, c);
+                const double* cr = cs + (c - c0) * D;
+                double acc[RR];
+#pragma unroll
+                for (int r = 0; r < RR; ++r) acc[r] = 0.0;
+#pragma unroll
+                for (int f = 0; f < D; ++f) {
+                    const double cv = cr[f];
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+                        const double diff = cv - x[r][f];
+                        if constexpr (METRIC == 0) acc[r] = acc[r] + __builtin_fabs(diff);
+                        else acc[r] = acc[r] + diff * diff;
+                    }
+                }
+                int within = 0;
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    const bool nr = acc[r] < apprx;
+                    word[r] |= (uint64_t)nr << (c - c0);
+                    within += (int)__popcll(__ballot(valid[r] && (nr || acc[r] < kern)));
+                }
+                if (lane == 0 && within) atomicAdd(&cnt_s[c], within);
             }
-            if (valid) a.near[(size_t)j * kSpW + g] = word;
+#pragma unroll
+            for (int r = 0; r < RR; ++r)
+                if (valid[r]) a.near[(size_t)(j0 + r * 256) * kSpW + g] = word[r];
         }
     } else {
+        const int64_t j = j0;
+        const bool valid = j < a.n;
         cdouble* crow = (cdouble*)(a.crow + (size_t)buf * kSpB * a.DP);
         const float* row = a.X + (valid ? j : 0) * a.d;
         const int d = a.d, DP = a.DP;
@@ -313,7 +331,8 @@ __global__ __launch_bounds__(256) void spade_batch_kernel(SpadeArgs a)
     const int cur = b & 1, prev = cur ^ 1;
     const int nc = ctrl->final_ ? 0 : ctrl->nc[cur];
     const int tid = threadIdx.x, lane = tid & 63;
-    const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+    constexpr int RR = sp_rows(D8);
+    const int64_t j0 = (int64_t)blockIdx.x * (256 * RR) + tid;   // this thread's samples: j0 + 256 r
     for (int c = tid; c < kSpB; c += 256) cnt_s[c] = 0;
 
     // claims of batch b - 1 (its masks are still in near[])
@@ -322,15 +341,19 @@ __global__ __launch_bounds__(256) void spade_batch_kernel(SpadeArgs a)
         const uint64_t* vp = ctrl->vis[prev];
         const int32_t* candp = a.cand + prev * kSpB;
         const int32_t* cntp = a.cnt + prev * kSpB;
-        if (j < a.n && a.owner[j] == INT_MAX) {
 #pragma unroll
-            for (int w = 0; w < kSpW; ++w) {
-                const uint64_t m = a.near[(size_t)j * kSpW + w] & vp[w];
-                if (m) {
-                    const int c = w * 64 + __builtin_ctzll(m);
-                    a.owner[j] = candp[c];
-                    a.dens[j] = cntp[c];
-                    break;
+        for (int r = 0; r < RR; ++r) {
+            const int64_t j = j0 + r * 256;
+            if (j < a.n && a.owner[j] == INT_MAX) {
+#pragma unroll
+                for (int w = 0; w < kSpW; ++w) {
+                    const uint64_t m = a.near[(size_t)j * kSpW + w] & vp[w];
+                    if (m) {
+                        const int c = w * 64 + __builtin_ctzll(m);
+                        a.owner[j] = candp[c];
+                        a.dens[j] = cntp[c];
+                        break;
+                    }
                 }
             }
         }
@@ -350,7 +373,7 @@ __global__ __launch_bounds__(256) void spade_batch_kernel(SpadeArgs a)
     }
     __syncthreads();
 
-    if (nc > 0) batch_rows<D8, METRIC>(a, cur, nc, j, cnt_s, cs);
+    if (nc > 0) batch_rows<D8, METRIC>(a, cur, nc, j0, cnt_s, cs);
     __syncthreads();
     for (int c = tid; c < nc; c += 256)
         if (cnt_s[c]) atomicAdd(&a.cnt[cur * kSpB + c], cnt_s[c]);
@@ -528,7 +551,8 @@ km_status spade_densities(const float* X, int64_t n, int32_t d, double apprx_wid
     a.dens = densities;
     a.visited = visited;
     const int D8 = (d + 7) / 8;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    const int rows_per_block = 256 * sp_rows(D8 <= kSpMaxD8Reg ? D8 : 0);
+    const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block));
     hipError_t e;
     hipLaunchKernelGGL(spade_init_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 2048)), dim3(256), 0,
                        stream, a);
