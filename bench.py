@@ -292,7 +292,7 @@ def _batched_run(B, torch, inst, C0, iters, precision, schedule=None):
     if schedule is None:
         choice, tune_ms = autotune.tune_batch(batch, use_cache=False)
     else:
-        batch.set_schedule(*schedule)
+        autotune._apply(batch, *schedule)
         choice, tune_ms = tuple(schedule), {}
     batch.use_graphs(True)
     B.kmeans_lloyd_batched(batch, iters)            # capture + warm-up
@@ -372,8 +372,10 @@ def batched_report(B, torch, iters, per_instance_sample=32):
             "labels_and_centroids_equal_fp32_batched": bool(same),
             "per_instance_launches_value": len(inst) * iters / el_single,
             "speedup_vs_per_instance_launches": el_single / el16,
-            "schedule": {"tiles_per_block": ch16[0], "order": ch16[1], "candidates_ms": tm16},
-            "schedule_fp32": {"tiles_per_block": ch32[0], "order": ch32[1], "candidates_ms": tm32},
+            "schedule": {"tiles_per_block": ch16[0], "order": ch16[1], "class_tiles_per_block": ch16[2],
+                         "candidates_ms": tm16},
+            "schedule_fp32": {"tiles_per_block": ch32[0], "order": ch32[1], "class_tiles_per_block": ch32[2],
+                              "candidates_ms": tm32},
             "graph": True}
 
 

@@ -244,6 +244,22 @@ km_status km_batch_set_workspace(km_batch *batch, void *ws, size_t bytes);
  * workspace again afterwards).  The autotuner in the Python package picks these.
  */
 km_status km_batch_set_schedule(km_batch *batch, int32_t tiles_per_block, int32_t order);
+/*
+ * Per-class schedules.  Instances fall into shape classes: (8-feature chunks
+ * of d, LDS bucket of the FP32 fused pass's per-label record), listed in
+ * increasing order; the partition does not depend on the precision, so class
+ * c names the same instances in an FP32 and a BF16 batch of one instance set.  km_batch_num_classes counts them (0 for NULL);
+ * km_batch_class_info describes class `cls` (HOST outputs, each may be NULL:
+ * its chunk count, LDS bucket in bytes, number of instances, and the tiles
+ * per block it currently uses); km_batch_set_class_schedule gives class `cls`
+ * its own tiles per block (0: the batch-wide value of km_batch_set_schedule,
+ * which keeps setting the order).  Both setters change the workspace size:
+ * bind a workspace again afterwards.
+ */
+int32_t km_batch_num_classes(const km_batch *batch);
+km_status km_batch_class_info(const km_batch *batch, int32_t cls, int32_t *d8, int32_t *lds_bytes,
+                              int32_t *instances, int32_t *tiles_per_block);
+km_status km_batch_set_class_schedule(km_batch *batch, int32_t cls, int32_t tiles_per_block);
 /* As km_plan_use_graphs, for kmeans_lloyd_batched (graph keyed by iterations). */
 km_status km_batch_use_graphs(km_batch *batch, int32_t enable);
 void km_batch_destroy(km_batch *batch);

@@ -25,7 +25,8 @@ EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_plan_use_graphs", "km_plan_set_validate", "km_batch_create", "km_batch_workspace_bytes", "km_batch_set_workspace",
            "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched",
            "spade_workspace_bytes", "spade_densities", "spade_stats", "km_class_sums", "nb_train",
-           "gda_workspace_bytes", "gda_train", "kmeans_assign_metric"]
+           "gda_workspace_bytes", "gda_train", "kmeans_assign_metric", "km_batch_num_classes",
+           "km_batch_class_info", "km_batch_set_class_schedule"]
 LAYOUTS = {"row": 0, "feature": 1}
 METRICS = {"l1": 0, "sqeuclidean": 1}
 
@@ -110,6 +111,12 @@ def lib():
         L.gda_workspace_bytes.argtypes = [P]
         L.gda_train.restype = I32
         L.gda_train.argtypes = [P, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.km_batch_num_classes.restype = I32
+        L.km_batch_num_classes.argtypes = [P]
+        L.km_batch_class_info.restype = I32
+        L.km_batch_class_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 4
+        L.km_batch_set_class_schedule.restype = I32
+        L.km_batch_set_class_schedule.argtypes = [P, I32, I32]
         L.kmeans_assign_metric.restype = I32
         L.kmeans_assign_metric.argtypes = [P, P, I32, I32, P, P, P, P, P]
         _lib = L
@@ -323,6 +330,20 @@ class Batch:
 
     def use_graphs(self, enable: bool = True):
         _check(lib().km_batch_use_graphs(self._h, int(bool(enable))))
+
+    def classes(self):
+        """[(d8, lds_bytes, instances, tiles_per_block)] of the shape classes."""
+        out = []
+        for c in range(int(lib().km_batch_num_classes(self._h))):
+            v = [ctypes.c_int32(0) for _ in range(4)]
+            _check(lib().km_batch_class_info(self._h, c, *[ctypes.byref(x) for x in v]))
+            out.append(tuple(int(x.value) for x in v))
+        return out
+
+    def set_class_schedule(self, cls: int, tiles_per_block: int):
+        """km_batch_set_class_schedule, then a workspace of the new size is bound."""
+        _check(lib().km_batch_set_class_schedule(self._h, int(cls), int(tiles_per_block)))
+        self._bind()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

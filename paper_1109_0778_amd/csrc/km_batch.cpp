@@ -60,8 +60,13 @@ struct km_batch {
     std::vector<km_instance> inst;
     int device = 0;
     bool mixed = false;    // BF16 MFMA distances + exact FP32 recheck
-    int tpb = 16;          // tiles per block
+    int tpb = 16;          // tiles per block (classes without their own value)
     int order = 1;         // 0: instance order, 1: decreasing work per block
+    // shape classes of the per-sample pass, (D8, LDS bucket), in key order,
+    // and a tiles-per-block value per class (0: tpb)
+    std::vector<std::pair<int, size_t>> classes;
+    std::map<std::pair<int, size_t>, int> class_tpb;
+    std::vector<int> tpb_inst;             // tiles per block of each instance (its class's)
     // derived layout
     std::vector<int> nslots;
     std::vector<size_t> off_cp, off_S, off_cnt, off_J, off_ch;
@@ -152,10 +157,25 @@ size_t lds_bucket(size_t lds)
 }
 
 // Work tables and workspace layout for the current schedule.
+// Schedule class of an instance: (D8, LDS bucket of the fused pass's per-label
+// record).  The same partition for every precision, so a schedule tuned for
+// one batch applies unchanged to the same instances at another precision.
+std::pair<int, size_t> class_of(const km_batch*, const km_instance& x)
+{
+    return std::make_pair(d8_of(x.d), lds_bucket(plain_lds_bytes(x.k, x.d, MODE_FUSED)));
+}
+
 void layout(km_batch* B)
 {
     const int m = (int)B->inst.size();
     B->nslots.assign(m, 0);
+    B->tpb_inst.assign(m, B->tpb);
+    B->classes.clear();
+    for (const km_instance& x : B->inst) {
+        const auto key = class_of(B, x);
+        if (std::find(B->classes.begin(), B->classes.end(), key) == B->classes.end()) B->classes.push_back(key);
+    }
+    std::sort(B->classes.begin(), B->classes.end());
     B->off_cp.assign(m, 0); B->off_S.assign(m, 0); B->off_cnt.assign(m, 0);
     B->off_J.assign(m, 0); B->off_ch.assign(m, 0);
     std::map<std::pair<int, size_t>, std::vector<BatchWork>> by_group;
@@ -166,16 +186,20 @@ void layout(km_batch* B)
         const km_instance& x = B->inst[i];
         const int D8 = d8_of(x.d);
         const int64_t tiles = (x.n + kBlock - 1) / kBlock;
-        const int nb = (int)((tiles + B->tpb - 1) / B->tpb);
+        // kernel group: the pass's own LDS record size (update mode for the
+        // mixed batch); the schedule class may differ from it
+        const auto key = std::make_pair(D8, lds_bucket(plain_lds_bytes(x.k, x.d, B->mixed ? MODE_UPDATE : MODE_FUSED)));
+        const auto ct = B->class_tpb.find(class_of(B, x));
+        const int tpb = (ct != B->class_tpb.end() && ct->second > 0) ? ct->second : B->tpb;
+        B->tpb_inst[i] = tpb;
+        const int nb = (int)((tiles + tpb - 1) / tpb);
         B->nslots[i] = nb;
-        const size_t lds = lds_bucket(plain_lds_bytes(x.k, x.d, B->mixed ? MODE_UPDATE : MODE_FUSED));
-        auto key = std::make_pair(D8, lds);
         for (int b = 0; b < nb; ++b) {
             BatchWork w;
             w.inst = i;
             w.slot = b;
-            w.t0 = (int64_t)b * B->tpb;
-            w.t1 = std::min<int64_t>(tiles, w.t0 + B->tpb);
+            w.t0 = (int64_t)b * tpb;
+            w.t1 = std::min<int64_t>(tiles, w.t0 + tpb);
             by_group[key].push_back(w);
             costs[key].push_back((double)(w.t1 - w.t0) * x.k * x.d);
         }
@@ -189,9 +213,9 @@ void layout(km_batch* B)
     }
     emit_groups(by_group, costs, B->order, B->work, B->groups);
     if (B->mixed) {
-        // MFMA rows of 2 * tpb 128-sample tiles (the same samples as a pass row),
-        // one queue region per row; recheck rows: kBatchRecheckSplit per region
-        const int tpm = 2 * B->tpb;
+        // MFMA rows of 2 * tpb 128-sample tiles (the same samples as a pass row
+        // of the instance's class), one queue region per row; recheck rows:
+        // kBatchRecheckSplit per region
         std::map<std::pair<int, size_t>, std::vector<BatchWork>> by_m, by_r;
         std::map<std::pair<int, size_t>, std::vector<double>> c_m, c_r;
         B->nreg.assign(m, 0);
@@ -202,6 +226,7 @@ void layout(km_batch* B)
         for (int i = 0; i < m; ++i) {
             const km_instance& x = B->inst[i];
             const int D16 = d16_of(x.d), kpad = kpad_of(x.k);
+            const int tpm = 2 * B->tpb_inst[i];
             const int64_t mt = (x.n + kMixTile - 1) / kMixTile;
             const int nr = (int)((mt + tpm - 1) / tpm);
             B->nreg[i] = nr;
@@ -307,7 +332,7 @@ km_status upload(km_batch* B)
         mm.labels = x.labels;
         mm.rq = reinterpret_cast<int32_t*>(ws + B->off_rq[i]);
         mm.rq_count = reinterpret_cast<int32_t*>(ws + B->off_rqc[i]);
-        mm.rq_per_block = (int64_t)2 * B->tpb * kMixTile;
+        mm.rq_per_block = (int64_t)2 * B->tpb_inst[i] * kMixTile;
         mm.nreg = nr;
         mm.changed_part = chg;
         mm.ctrl = nullptr; mm.iter = 0; mm.count_changed = 0;
@@ -483,6 +508,41 @@ km_status km_batch_set_schedule(km_batch* batch, int32_t tiles_per_block, int32_
     if (tiles_per_block < 1 || (order != 0 && order != 1)) return berr(KM_EINVAL, "bad schedule");
     batch->tpb = tiles_per_block;
     batch->order = order;
+    batch->drop_graph();
+    batch->ws = nullptr;   // layout changes: a workspace must be bound again
+    layout(batch);
+    return KM_OK;
+}
+
+int32_t km_batch_num_classes(const km_batch* batch)
+{
+    return batch ? (int32_t)batch->classes.size() : 0;
+}
+
+km_status km_batch_class_info(const km_batch* batch, int32_t cls, int32_t* d8, int32_t* lds_bytes,
+                              int32_t* instances, int32_t* tiles_per_block)
+{
+    km_set_error(KM_OK, "");
+    if (!batch) return berr(KM_EINVAL, "batch is NULL");
+    if (cls < 0 || cls >= (int32_t)batch->classes.size()) return berr(KM_EINVAL, "class %d out of range", cls);
+    const auto key = batch->classes[cls];
+    int cnt = 0, tpb = batch->tpb;
+    for (size_t i = 0; i < batch->inst.size(); ++i)
+        if (class_of(batch, batch->inst[i]) == key) { ++cnt; tpb = batch->tpb_inst[i]; }
+    if (d8) *d8 = key.first;
+    if (lds_bytes) *lds_bytes = (int32_t)key.second;
+    if (instances) *instances = cnt;
+    if (tiles_per_block) *tiles_per_block = tpb;
+    return KM_OK;
+}
+
+km_status km_batch_set_class_schedule(km_batch* batch, int32_t cls, int32_t tiles_per_block)
+{
+    km_set_error(KM_OK, "");
+    if (!batch) return berr(KM_EINVAL, "batch is NULL");
+    if (cls < 0 || cls >= (int32_t)batch->classes.size()) return berr(KM_EINVAL, "class %d out of range", cls);
+    if (tiles_per_block < 0) return berr(KM_EINVAL, "bad tiles_per_block %d", tiles_per_block);
+    batch->class_tpb[batch->classes[cls]] = tiles_per_block;
     batch->drop_graph();
     batch->ws = nullptr;   // layout changes: a workspace must be bound again
     layout(batch);

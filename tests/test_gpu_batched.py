@@ -156,6 +156,47 @@ def test_batched_bf16_equals_fp32_batch(tpb, order):
             np.testing.assert_allclose(b["obj_hist"].cpu().numpy(), a["obj_hist"].cpu().numpy(), rtol=1e-6)
 
 
+def test_batched_per_class_schedules():
+    """Per-class tiles per block: the classes cover every instance, the values
+    are applied, BF16 and FP32 batches given the same per-class schedule agree
+    bit for bit, and the results stay oracle-valid (stepwise, one iteration)."""
+    torch, B = _torch(), _bind()
+    inst32, host = make_batch(torch, B, SHAPES, seed0=400, iters=2)
+    inst16, _ = make_batch(torch, B, SHAPES, seed0=400, iters=2)
+    b32 = B.Batch(inst32)
+    b16 = B.Batch(inst16, precision="bf16")
+    cl = b32.classes()
+    assert cl == b16.classes() and len(cl) > 1
+    assert sum(c[2] for c in cl) == len(SHAPES)
+    assert [c[0] for c in cl] == sorted(c[0] for c in cl)
+    for b in (b32, b16):
+        b.set_schedule(4, 1)
+        for c in range(len(cl)):
+            b.set_class_schedule(c, (1, 64, 3, 0, 16)[c % 5])
+    got = b32.classes()
+    assert [g[3] for g in got] == [(1, 64, 3, 4, 16)[c % 5] for c in range(len(cl))]
+    b16.use_graphs(True)
+    Cs = [C.copy() for _, C in host]
+    for t in range(2):
+        B.kmeans_lloyd_batched(b32, 1)
+        B.kmeans_lloyd_batched(b16, 1)
+        torch.cuda.synchronize()
+        for i, ((X, _), a, b) in enumerate(zip(host, inst32, inst16)):
+            assert torch.equal(a["labels"], b["labels"]), f"instance {i} t={t}"
+            assert torch.equal(a["C"], b["C"]) and torch.equal(a["counts"], b["counts"]), f"instance {i} t={t}"
+            lab = a["labels"].cpu().numpy()
+            check_labels(lab, Cs[i], X, f"class schedule instance {i} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(a["counts"].cpu().numpy(), cnto)
+            Cg = a["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"class schedule instance {i} t={t}")
+            Cs[i] = Cg
+    with pytest.raises(B.KMeansError):
+        b32.set_class_schedule(len(cl), 2)
+    with pytest.raises(B.KMeansError):
+        b32.set_class_schedule(0, -1)
+
+
 def test_batched_rejects_bad_instances():
     torch, B = _torch(), _bind()
     dev = torch.device("cuda")
