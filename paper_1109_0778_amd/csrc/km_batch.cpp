@@ -77,6 +77,7 @@ struct km_batch {
     // mixed path
     std::vector<int> nreg;                 // MFMA queue regions per instance
     std::vector<size_t> off_xs, off_ab, off_bias, off_cs, off_rq, off_rqc, off_chg, off_jt, off_xpm, off_xps;
+    std::vector<size_t> off_xb, off_xn;    // run-level BF16 copy of X and |x| bounds
     std::vector<int> nxb;
     std::vector<BatchWork> mwork, rwork, xwork;   // MFMA rows, recheck rows, statistics rows
     std::vector<Group> mgroups, rgroups;
@@ -222,6 +223,7 @@ void layout(km_batch* B)
         B->off_xs.assign(m, 0); B->off_ab.assign(m, 0); B->off_bias.assign(m, 0); B->off_cs.assign(m, 0);
         B->off_rq.assign(m, 0); B->off_rqc.assign(m, 0); B->off_chg.assign(m, 0); B->off_jt.assign(m, 0);
         B->off_xpm.assign(m, 0); B->off_xps.assign(m, 0); B->nxb.assign(m, 0);
+        B->off_xb.assign(m, 0); B->off_xn.assign(m, 0);
         B->xwork.clear();
         for (int i = 0; i < m; ++i) {
             const km_instance& x = B->inst[i];
@@ -260,6 +262,8 @@ void layout(km_batch* B)
             B->nxb[i] = nx;
             for (int b = 0; b < nx; ++b)
                 B->xwork.push_back(BatchWork{i, b, (int64_t)b * kPrepXRows, std::min<int64_t>(x.n, (int64_t)(b + 1) * kPrepXRows)});
+            B->off_xb[i] = off;   off = al256(off + (size_t)x.n * 16 * D16 * sizeof(__bf16));
+            B->off_xn[i] = off;   off = al256(off + (size_t)x.n * sizeof(float));
             B->off_xpm[i] = off;  off = al256(off + (size_t)nx * sizeof(float));
             B->off_xps[i] = off;  off = al256(off + (size_t)nx * sizeof(double));
         }
@@ -324,7 +328,8 @@ km_status upload(km_batch* B)
         mm.bias = reinterpret_cast<const float*>(ws + B->off_bias[i]);
         mm.cs = reinterpret_cast<const CStats*>(ws + B->off_cs[i]);
         mm.Xq = nullptr; mm.xst = nullptr;
-        mm.Xb = nullptr; mm.xn = nullptr;    // converts X in the pass (no run-level copy)
+        mm.Xb = reinterpret_cast<const __bf16*>(ws + B->off_xb[i]);   // the run's BF16 copy, written with the run-level statistics
+        mm.xn = reinterpret_cast<const float*>(ws + B->off_xn[i]);
         mm.u = 0.00390625f;                  // BF16 unit roundoff 2^-8
         mm.IB = ib_of(kpad);
         mm.gamma_terms = 2 * 16 * D16 + 8;

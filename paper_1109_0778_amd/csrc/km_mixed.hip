@@ -225,13 +225,13 @@ __host__ __device__ inline float norm_margin(int DP)
     return m > 1e-6f ? m : 1e-6f;
 }
 
-// Row i and chunk (lane g, pass c) of the calling thread; x[8]: the chunk's
-// features (zero past d).  Returns whether the thread holds a live chunk.
-__device__ __forceinline__ bool row_chunk(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP, int c,
-                                          int64_t& i, int& f0, float (&x)[8])
+// Row i and chunk (lane g, pass c) of thread t (G consecutive threads per
+// row, rows below n live); x[8]: the chunk's features (zero past d).
+// Returns whether the thread holds a live chunk.
+__device__ __forceinline__ bool row_chunk_at(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP, int c,
+                                             int64_t t, int64_t& i, int& f0, float (&x)[8])
 {
     const int G = row_lanes_q(DP);
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     i = t / G;
     f0 = 8 * ((int)(t - i * G) + G * c);
     const bool live = i < n && f0 < DP;
@@ -254,6 +254,12 @@ __device__ __forceinline__ bool row_chunk(const float* __restrict__ X, int64_t n
         }
     }
     return live;
+}
+
+__device__ __forceinline__ bool row_chunk(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP, int c,
+                                          int64_t& i, int& f0, float (&x)[8])
+{
+    return row_chunk_at(X, n, d, DP, c, (int64_t)blockIdx.x * 256 + threadIdx.x, i, f0, x);
 }
 
 template <typename T>
@@ -295,8 +301,9 @@ __global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ 
 // Once per call: the BF16 copy of X the BF16 MFMA passes read (rounded to
 // nearest even, zero padded to DP features) and an upper bound of |x| per
 // sample.
-__global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
-                                                           int32_t DP, __bf16* Xb, float* xn)
+// Thread t's share (G threads per row; rows of index n or more are idle).
+__device__ __forceinline__ void quant_bf16_at(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
+                                              __bf16* Xb, float* xn, int64_t t)
 {
     float s2 = 0.0f;
     int64_t i = 0;
@@ -304,7 +311,7 @@ __global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restri
     for (int c = 0; c < row_chunks_q(DP); ++c) {
         int f0;
         float x[8];
-        const bool live = row_chunk(X, n, d, DP, c, i, f0, x);
+        const bool live = row_chunk_at(X, n, d, DP, c, t, i, f0, x);
         if (c == 0) live0 = live;
         bf16x8 w;
 #pragma unroll
@@ -316,8 +323,13 @@ __global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restri
     }
     s2 = row_sum(s2, row_lanes_q(DP));
     const int G = row_lanes_q(DP);
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (live0 && t % G == 0) xn[i] = sqrtf(s2) * (1.0f + norm_margin(DP));
+}
+
+__global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
+                                                           int32_t DP, __bf16* Xb, float* xn)
+{
+    quant_bf16_at(X, n, d, DP, Xb, xn, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------------ per-iteration prep
@@ -485,6 +497,13 @@ __global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchWork* __re
     if (tid == 0) {
         b.xpart_max[w.slot] = smax[0];
         b.xpart_sum[w.slot] = ssum[0];
+    }
+    // the BF16 copy of rows [t0, t1) and their |x| bounds, as quant_x_bf16_kernel
+    // (t0 is a multiple of 256, so the G threads of a row share a wave)
+    if (b.m.Xb != nullptr) {
+        const int G = row_lanes_q(b.DP);
+        for (int64_t base = w.t0 * G; base < w.t1 * G; base += 256)
+            quant_bf16_at(X, w.t1, d, b.DP, const_cast<__bf16*>(b.m.Xb), const_cast<float*>(b.m.xn), base + tid);
     }
 }
 
