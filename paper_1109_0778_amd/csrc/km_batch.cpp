@@ -50,9 +50,12 @@ struct Group {
     int D8;               // D8 (pass, recheck) or D16 (MFMA pass)
     size_t lds;
     int first, count;     // range in the work table
+    double cost = 0.0;    // estimated work (sum over its rows)
+    int lane = 0;         // side stream it is launched on
 };
 
 constexpr int kBatchRecheckSplit = 2;   // recheck blocks per queue region
+constexpr int km_side_streams = 4;      // side streams a phase's groups are spread over
 
 }  // namespace
 
@@ -84,7 +87,7 @@ struct km_batch {
     size_t off_bm = 0, off_mwork = 0, off_rwork = 0, off_xwork = 0;
     // side streams: the launches of one phase (one per shape class) are
     // forked onto them and joined back, so classes overlap (graph branches)
-    static constexpr int kSide = 4;
+    static constexpr int kSide = km_side_streams;
     hipStream_t side[kSide] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
     unsigned char* ws = nullptr;
@@ -144,8 +147,21 @@ void emit_groups(std::map<std::pair<int, size_t>, std::vector<BatchWork>>& by, s
         g.lds = kv.first.second;
         g.first = (int)out.size();
         g.count = (int)v.size();
+        for (double c : costs[kv.first]) g.cost += c;
         groups.push_back(g);
         out.insert(out.end(), v.begin(), v.end());
+    }
+    // launch order and side streams: largest group first, each group onto the
+    // least loaded stream (longest-processing-time rule), so the long groups
+    // of a phase start together instead of queueing behind short ones
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
+    double load[km_side_streams] = {};
+    for (Group& g : groups) {
+        int best = 0;
+        for (int q = 1; q < km_side_streams; ++q)
+            if (load[q] < load[best]) best = q;
+        g.lane = best;
+        load[best] += g.cost;
     }
 }
 
@@ -202,7 +218,8 @@ void layout(km_batch* B)
             w.t0 = (int64_t)b * tpb;
             w.t1 = std::min<int64_t>(tiles, w.t0 + tpb);
             by_group[key].push_back(w);
-            costs[key].push_back((double)(w.t1 - w.t0) * x.k * x.d);
+            // the update after a BF16 assign reads rows; the fused pass also forms distances
+            costs[key].push_back((double)(w.t1 - w.t0) * (B->mixed ? x.d : (double)x.k * x.d));
         }
         const int chunks = finalize_blocks(x.k, x.d);
         for (int c = 0; c < chunks; ++c) B->fwork.push_back(BatchFinWork{i, c});
@@ -402,7 +419,7 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
         }
         return ee;
     };
-    auto lane_of = [&](int g) { return B->side[g % km_batch::kSide]; };
+    auto lane_of = [&](const Group& G) { return B->side[G.lane]; };
     if (B->mixed && (e = launch_batch_prep_x(xwork, (int)B->xwork.size(), bm, m, s)) != hipSuccess)
         return bhip(e, "batch prep_x launch");
     for (int32_t t = 0; t < iters; ++t) {
@@ -412,14 +429,14 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
             if ((e = fork(nm)) != hipSuccess) return bhip(e, "batch fork");
             for (int g = 0; g < nm; ++g) {
                 const Group& G = B->mgroups[g];
-                if ((e = launch_batch_mfma(G.D8, mwork + G.first, G.count, bm, t, lane_of(g))) != hipSuccess)
+                if ((e = launch_batch_mfma(G.D8, mwork + G.first, G.count, bm, t, lane_of(G))) != hipSuccess)
                     return bhip(e, "batch MFMA launch");
             }
             if ((e = join(nm)) != hipSuccess) return bhip(e, "batch join");
             if ((e = fork(nr)) != hipSuccess) return bhip(e, "batch fork");
             for (int g = 0; g < nr; ++g) {
                 const Group& G = B->rgroups[g];
-                if ((e = launch_batch_recheck(G.D8, rwork + G.first, G.count, bm, t, lane_of(g))) != hipSuccess)
+                if ((e = launch_batch_recheck(G.D8, rwork + G.first, G.count, bm, t, lane_of(G))) != hipSuccess)
                     return bhip(e, "batch recheck launch");
             }
             if ((e = join(nr)) != hipSuccess) return bhip(e, "batch join");
@@ -429,7 +446,7 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
         for (int g = 0; g < np; ++g) {
             const Group& G = B->groups[g];
             if ((e = launch_batch_pass(G.D8, B->mixed ? MODE_UPDATE : MODE_FUSED, work + G.first, G.count, pa, t,
-                                       G.lds, lane_of(g))) != hipSuccess)
+                                       G.lds, lane_of(G))) != hipSuccess)
                 return bhip(e, "batch pass launch");
         }
         if ((e = join(np)) != hipSuccess) return bhip(e, "batch join");

@@ -302,10 +302,15 @@ __global__ __launch_bounds__(256) void quant_x_kernel(const float* __restrict__ 
 // nearest even, zero padded to DP features) and an upper bound of |x| per
 // sample.
 // Thread t's share (G threads per row; rows of index n or more are idle).
+// With STATS, the row's first thread also folds the row into the running
+// statistics: mx = max FP32 |x|^2, sm += FP64 |x|^2.
+template <bool STATS = false>
 __device__ __forceinline__ void quant_bf16_at(const float* __restrict__ X, int64_t n, int32_t d, int32_t DP,
-                                              __bf16* Xb, float* xn, int64_t t)
+                                              __bf16* Xb, float* xn, int64_t t, float* mx = nullptr,
+                                              double* sm = nullptr)
 {
     float s2 = 0.0f;
+    double s64 = 0.0;
     int64_t i = 0;
     bool live0 = false;
     for (int c = 0; c < row_chunks_q(DP); ++c) {
@@ -317,13 +322,21 @@ __device__ __forceinline__ void quant_bf16_at(const float* __restrict__ X, int64
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             s2 = __builtin_fmaf(x[q], x[q], s2);
+            if constexpr (STATS) s64 += (double)x[q] * (double)x[q];
             w[q] = (__bf16)x[q];
         }
         if (live) *reinterpret_cast<bf16x8*>(Xb + i * DP + f0) = w;
     }
     s2 = row_sum(s2, row_lanes_q(DP));
     const int G = row_lanes_q(DP);
-    if (live0 && t % G == 0) xn[i] = sqrtf(s2) * (1.0f + norm_margin(DP));
+    if constexpr (STATS) s64 = row_sum(s64, G);
+    if (live0 && t % G == 0) {
+        xn[i] = sqrtf(s2) * (1.0f + norm_margin(DP));
+        if constexpr (STATS) {
+            *mx = fmaxf(*mx, s2);
+            *sm += s64;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void quant_x_bf16_kernel(const float* __restrict__ X, int64_t n, int32_t d,
@@ -462,9 +475,10 @@ __global__ __launch_bounds__(256) void batch_prep_c_kernel(const BatchMix* __res
                 const_cast<CStats*>(b.m.cs), nullptr, 0);
 }
 
-// Batched run-level statistics: row b of the work table covers rows
-// [t0, t1) of one instance (fixed order per thread, then a fixed tree) and
-// writes partial slot `slot`; a one-wave combine per instance follows.
+// Batched run-level prep: row b of the work table covers rows [t0, t1) of one
+// instance, writes their BF16 copy and |x| bounds, and its statistics (fixed
+// order per thread, then a fixed tree) to partial slot `slot`; a one-wave
+// combine per instance follows.
 __global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchWork* __restrict__ work,
                                                            const BatchMix* __restrict__ bm)
 {
@@ -477,13 +491,13 @@ __global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchWork* __re
     const int tid = threadIdx.x;
     float mx = 0.0f;
     double sm = 0.0;
-    for (int64_t i = w.t0 + tid; i < w.t1; i += 256) {
-        float s32;
-        double s64;
-        row_norm2(X + i * d, d, s32, s64);
-        mx = fmaxf(mx, s32);
-        sm += s64;
-    }
+    // the BF16 copy of rows [t0, t1) and their |x| bounds, as quant_x_bf16_kernel,
+    // with the statistics from the same reads (t0 is a multiple of 256, so the
+    // G threads of a row share a wave; each row's first thread adds the row)
+    const int G = row_lanes_q(b.DP);
+    for (int64_t base = w.t0 * G; base < w.t1 * G; base += 256)
+        quant_bf16_at<true>(X, w.t1, d, b.DP, const_cast<__bf16*>(b.m.Xb), const_cast<float*>(b.m.xn), base + tid,
+                            &mx, &sm);
     smax[tid] = mx;
     ssum[tid] = sm;
     __syncthreads();
@@ -497,13 +511,6 @@ __global__ __launch_bounds__(256) void batch_prep_x_kernel(const BatchWork* __re
     if (tid == 0) {
         b.xpart_max[w.slot] = smax[0];
         b.xpart_sum[w.slot] = ssum[0];
-    }
-    // the BF16 copy of rows [t0, t1) and their |x| bounds, as quant_x_bf16_kernel
-    // (t0 is a multiple of 256, so the G threads of a row share a wave)
-    if (b.m.Xb != nullptr) {
-        const int G = row_lanes_q(b.DP);
-        for (int64_t base = w.t0 * G; base < w.t1 * G; base += 256)
-            quant_bf16_at(X, w.t1, d, b.DP, const_cast<__bf16*>(b.m.Xb), const_cast<float*>(b.m.xn), base + tid);
     }
 }
 
