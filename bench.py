@@ -83,7 +83,10 @@ def measured_traffic(key):
     except (OSError, ValueError, KeyError):
         return None
     for e in entries:
-        if e.get("key") == key and e.get("source_sha256") == src_sha256(e["source"]):
+        if e.get("key") != key:
+            continue
+        srcs = e.get("sources", {e.get("source"): e.get("source_sha256")})
+        if all(src_sha256(f) == h for f, h in srcs.items()):
             return e.get("bytes_per_launch")
     return None
 
@@ -312,13 +315,7 @@ def _batched_run(B, torch, inst, C0, iters, precision, schedule=None):
     return el, choice, tune_ms, out
 
 
-def batched_report(B, torch, iters, per_instance_sample=32):
-    """The 512-instance workload with BF16 MFMA distances (and the FP32 batch
-    beside it): autotuned schedule, one graph launch for all iterations of all
-    instances, timed; the FP32 batch re-run at the BF16 schedule must give the
-    same labels and centroids; next to them the same instances through
-    single-instance FP32 kmeans_lloyd calls (a sample, extrapolated)."""
-    import numpy as np
+def batched_instances(torch, iters):
     from paper_1109_0778_amd import datagen
     dev = torch.device("cuda", 0)
     inst, shapes = [], []
@@ -329,6 +326,27 @@ def batched_report(B, torch, iters, per_instance_sample=32):
                      "labels": torch.empty(shp.n, dtype=torch.int32, device=dev),
                      "counts": torch.empty(shp.k, dtype=torch.int64, device=dev),
                      "obj_hist": torch.zeros(iters, dtype=torch.float64, device=dev)})
+    return inst, shapes
+
+
+def batched_fixed(B, torch, iters, schedule):
+    """The BF16 batch alone at a given (tiles per block, order): one graph
+    launch to capture and warm up, one timed (for counter runs: every batch
+    kernel is dispatched 2 x iters times, the run-level prep twice)."""
+    inst, _ = batched_instances(torch, iters)
+    C0 = [t["C"].clone() for t in inst]
+    el, ch, _, _ = _batched_run(B, torch, inst, C0, iters, "bf16", schedule=schedule)
+    return {"precision": "bf16", "schedule": list(ch), "iterations": iters, "ms_per_round": el * 1e3 / iters}
+
+
+def batched_report(B, torch, iters, per_instance_sample=32):
+    """The 512-instance workload with BF16 MFMA distances (and the FP32 batch
+    beside it): autotuned schedule, one graph launch for all iterations of all
+    instances, timed; the FP32 batch re-run at the BF16 schedule must give the
+    same labels and centroids; next to them the same instances through
+    single-instance FP32 kmeans_lloyd calls (a sample, extrapolated)."""
+    import numpy as np
+    inst, shapes = batched_instances(torch, iters)
     C0 = [t["C"].clone() for t in inst]
     el32, ch32, tm32, _ = _batched_run(B, torch, inst, C0, iters, "fp32")
     el16, ch16, tm16, res16 = _batched_run(B, torch, inst, C0, iters, "bf16")
@@ -365,7 +383,8 @@ def batched_report(B, torch, iters, per_instance_sample=32):
             "dist_evals_per_s": evals * iters / el16,
             "roofline": roof("hbm", nbytes, ms_round, HBM_PEAK_GBPS, "GB/s",
                              kernel="one round of every instance (all launches of one iteration)",
-                             traffic=None, bytes_per_round=nbytes, flops_per_round=flops,
+                             traffic=measured_traffic("batched_round:bf16"), bytes_per_round=nbytes,
+                             flops_per_round=flops,
                              mfma_frac_of_round=flops / (ms_round * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"]),
             "fp32_batched_value": len(inst) * iters / el32,
             "speedup_vs_fp32_batched": el32 / el16,
@@ -590,6 +609,9 @@ def main():
                     help="skip SPADE, naive Bayes, GDA and the metric / layout comparison")
     ap.add_argument("--cpu-rows", type=int, default=1 << 22,
                     help="samples in the oracle's timed iteration (default: all 2^22 of the headline input)")
+    ap.add_argument("--batched-schedule", default=None, metavar="T,O",
+                    help="with --workload batched: only the BF16 batch at tiles per block T and order O "
+                         "(no autotuning, no FP32 batch; for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (PMC calibration)")
     args = ap.parse_args()
@@ -619,6 +641,10 @@ def main():
         rep.update({"metric": "SPADE density step, ms per call", "n_gpus": 1, "higher_is_better": False,
                     "data": "synthetic"})
         print(json.dumps(rep), flush=True)
+        return
+    if args.workload == "batched" and args.batched_schedule:
+        t_, o_ = (int(v) for v in args.batched_schedule.split(","))
+        print(json.dumps(batched_fixed(B, torch, datagen.BATCH_ITERS, (t_, o_, []))), flush=True)
         return
     if args.workload == "batched":
         rep = batched_report(B, torch, datagen.BATCH_ITERS)
