@@ -442,7 +442,7 @@ def spade_report(B, torch, runs):
             "row_evals_per_s": float(nvis) * n / (ms * 1e-3),
             "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": FP64_LANE_OPS / 1e12,
                          "unit": "T FP64 op/s", "frac": ops / (ms * 1e-3) / FP64_LANE_OPS,
-                         "kernel": "spade_densities, whole call (select + rows + mark launches of every batch)",
+                         "kernel": "spade_densities, whole call (one launch per batch: claims, rows, resolve and selection)",
                          "ops_per_call": ops, "formed_ops_per_call": float(cands) * n * 2 * d, "traffic": None}}
 
 
