@@ -737,6 +737,36 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     }
     uint4 pr[PF];
     float pb = 0.0f;
+    // The next chunk is prefetched one part per 32-row tile: part tt is loaded
+    // at the start of tile tt and stored to the other buffer at the start of
+    // tile tt + 1 (the last part after the tiles), so only PFH registers stay
+    // live across a tile.
+    constexpr int NTT = kMixCK / 32;                 // 32-row tiles per chunk
+    constexpr int PFH = (PF + NTT - 1) / NTT;       // prefetch uint4 per thread per tile
+    uint4 prh[PFH];
+#define KM_LOAD_PART(c_, hf_)                                                             \
+    {                                                                                     \
+        const uint4* src_ = reinterpret_cast<const uint4*>(                               \
+            static_cast<const unsigned char*>(a.Ab) + (size_t)(c_) * kMixCK * DP * ES);   \
+        _Pragma("unroll") for (int i_ = 0; i_ < PFH; ++i_) {                              \
+            const int q_ = (hf_) * PFH + i_;                                              \
+            const int e_ = tid + q_ * 64 * kMixWaves;                                     \
+            prh[i_] = (q_ < PF && e_ < kMixCK * V) ? src_[e_] : make_uint4(0, 0, 0, 0);   \
+        }                                                                                 \
+        if ((hf_) == 0) pb = (tid < kMixCK) ? a.bias[(size_t)(c_) * kMixCK + tid] : 0.0f; \
+    }
+#define KM_STORE_PART(buf_, hf_)                                                          \
+    {                                                                                     \
+        _Pragma("unroll") for (int i_ = 0; i_ < PFH; ++i_) {                              \
+            const int q_ = (hf_) * PFH + i_;                                              \
+            const int e_ = tid + q_ * 64 * kMixWaves;                                     \
+            if (q_ < PF && e_ < kMixCK * V) {                                             \
+                const int row_ = e_ / V, qq_ = e_ - row_ * V;                             \
+                *reinterpret_cast<uint4*>(Abuf + (buf_) * CHB + row_ * ROWB + qq_ * 16) = prh[i_]; \
+            }                                                                             \
+        }                                                                                 \
+        if ((hf_) == 0 && tid < kMixCK) bbuf[(buf_) * kMixCK + tid] = pb;                \
+    }
     int cur = 0;
     if (t_first < t_last) {
         KM_LOAD_CHUNK(0)
@@ -844,7 +874,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         // next tile) is fetched into registers while this one is computed
         for (int c = 0; c < nchunks; ++c) {
             const bool pref = nchunks > 1 && (c + 1 < nchunks || t + t_step < t_last);
-            if (pref) KM_LOAD_CHUNK(c + 1 < nchunks ? c + 1 : 0)
+            const int cnext = c + 1 < nchunks ? c + 1 : 0;
             const unsigned char* Ab_c = Abuf + cur * CHB;
             const float* bb_c = bbuf + cur * kMixCK;
             // screen: the two smallest keys of this chunk, indexed within the
@@ -855,6 +885,10 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
             for (int nb = 0; nb < NB; ++nb) { lm[nb] = 0xffffffffu; lm2[nb] = 0xffffffffu; }
 #pragma unroll
             for (int tt = 0; tt < kMixCK / 32; ++tt) {
+                if (pref) {
+                    if (tt > 0) KM_STORE_PART(cur ^ 1, tt - 1)
+                    KM_LOAD_PART(cnext, tt)
+                }
                 f32x16 acc[NB];
                 {
                     float bvv[16];
@@ -869,9 +903,10 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                         for (int i = 0; i < 16; ++i) acc[nb][i] = bvv[i];
                 }
                 const unsigned char* arow = Ab_c + (tt * 32 + col) * ROWB + 8 * ES * h;
-                // raised wave priority while the MFMA chain issues keeps the
-                // matrix pipe fed while other waves run their epilogues
-                __builtin_amdgcn_s_setprio(1);
+                // candidate-list stages raise the wave's priority while its MFMA
+                // chain issues (the matrix pipe stays fed while other waves run
+                // their longer epilogues); the screens measured faster without
+                if constexpr (!SCREEN) __builtin_amdgcn_s_setprio(1);
                 if constexpr (WIDE) {
                     // centroid and sample operands straight from memory, one
                     // 16-feature step at a time
@@ -893,21 +928,38 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                         }
                     }
                 }
+                if constexpr (F8) {
+                    long an = D16 > 0 ? *reinterpret_cast<const long*>(arow) : 0l;
 #pragma unroll
-                for (int s = 0; s < D16; ++s) {
-                    if constexpr (F8) {
-                        const long af = *reinterpret_cast<const long*>(arow + 16 * s);
+                    for (int s = 0; s < D16; ++s) {
+                        const long af = an;
+                        if (s + 1 < D16) an = *reinterpret_cast<const long*>(arow + 16 * (s + 1));
 #pragma unroll
                         for (int nb = 0; nb < NB; ++nb)
                             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(af, bq[nb][s], acc[nb], 0, 0, 0);
-                    } else {
-                        const bf16x8 af = *reinterpret_cast<const bf16x8*>(arow + 32 * s);
+                    }
+                } else if constexpr (!WIDE) {
+                    // the next step's centroid fragment is read while this step's MFMAs run
+                    bf16x8 an = *reinterpret_cast<const bf16x8*>(arow);
+#pragma unroll
+                    for (int s = 0; s < D16; ++s) {
+                        const bf16x8 af = an;
+                        if (s + 1 < D16) an = *reinterpret_cast<const bf16x8*>(arow + 32 * (s + 1));
 #pragma unroll
                         for (int nb = 0; nb < NB; ++nb)
                             acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfr[nb][s], acc[nb], 0, 0, 0);
                     }
+                    // schedule: fragment 0's LDS read, then per step the next
+                    // fragment's read ahead of this step's MFMAs
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+                    for (int s = 0; s + 1 < D16; ++s) {
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);
+                    }
+                    __builtin_amdgcn_sched_group_barrier(0x008, NB, 0);
                 }
-                __builtin_amdgcn_s_setprio(0);
+                if constexpr (!SCREEN) __builtin_amdgcn_s_setprio(0);
                 // epilogue: keys, running minimum, candidate list
                 const uint32_t j0 = (uint32_t)(c * kMixCK + tt * 32 + 4 * h);
                 if constexpr (SCREEN && (WIDE || D16 > 5)) {
@@ -915,16 +967,13 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                     // one key at a time (3 VALU operations per key): at 96 or
                     // more features the MFMA chain outlasts the epilogue
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        uint32_t mm = lm[nb], mm2 = lm2[nb];
+                    for (int i = 0; i < 16; ++i) {
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) {
+                        for (int nb = 0; nb < NB; ++nb) {
                             const uint32_t key = (__float_as_uint(acc[nb][i]) & ~ibm) | (uint32_t)(tt * 32 + 8 * (i >> 2) + (i & 3));
-                            mm2 = med3_u32(mm, mm2, key);
-                            mm = min(mm, key);
+                            lm2[nb] = med3_u32(lm[nb], lm2[nb], key);
+                            lm[nb] = min(lm[nb], key);
                         }
-                        lm[nb] = mm;
-                        lm2[nb] = mm2;
                     }
                     continue;
                 } else if constexpr (SCREEN) {
@@ -1033,7 +1082,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
                 }
             }
             if (pref) {
-                KM_STORE_CHUNK(cur ^ 1)
+                KM_STORE_PART(cur ^ 1, NTT - 1)
                 __syncthreads();     // next buffer complete; this one no longer read
                 cur ^= 1;
             }
@@ -1132,6 +1181,8 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
 
 #undef KM_LOAD_CHUNK
 #undef KM_STORE_CHUNK
+#undef KM_LOAD_PART
+#undef KM_STORE_PART
     // changed-label partial of this block (fixed order)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) changed += __shfl_xor(changed, off);
