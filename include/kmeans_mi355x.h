@@ -239,20 +239,22 @@ size_t km_batch_workspace_bytes(const km_batch *batch);
 km_status km_batch_set_workspace(km_batch *batch, void *ws, size_t bytes);
 /*
  * Schedule: each instance's tiles of 256 samples are split into blocks of
- * `tiles_per_block` tiles (>= 1); order 0 launches blocks in instance order,
- * order 1 by decreasing work per block.  Changes the workspace size (bind a
- * workspace again afterwards).  The autotuner in the Python package picks these.
+ * `tiles_per_block` tiles (1 to 2^20, else KM_EINVAL); order 0 launches blocks
+ * in instance order, order 1 by decreasing work per block.  Changes the
+ * workspace size (bind a workspace again afterwards).  The autotuner in the
+ * Python package picks these.
  */
 km_status km_batch_set_schedule(km_batch *batch, int32_t tiles_per_block, int32_t order);
 /*
  * Per-class schedules.  Instances fall into shape classes: (8-feature chunks
  * of d, LDS bucket of the FP32 fused pass's per-label record), listed in
  * increasing order; the partition does not depend on the precision, so class
- * c names the same instances in an FP32 and a BF16 batch of one instance set.  km_batch_num_classes counts them (0 for NULL);
+ * c names the same instances in an FP32 and a BF16 batch of one instance set.
+ * km_batch_num_classes counts them (0 for NULL);
  * km_batch_class_info describes class `cls` (HOST outputs, each may be NULL:
  * its chunk count, LDS bucket in bytes, number of instances, and the tiles
  * per block it currently uses); km_batch_set_class_schedule gives class `cls`
- * its own tiles per block (0: the batch-wide value of km_batch_set_schedule,
+ * its own tiles per block (1 to 2^20; 0: the batch-wide value of km_batch_set_schedule,
  * which keeps setting the order).  Both setters change the workspace size:
  * bind a workspace again afterwards.
  */

@@ -56,6 +56,7 @@ struct Group {
 
 constexpr int kBatchRecheckSplit = 2;   // recheck blocks per queue region
 constexpr int km_side_streams = 4;      // side streams a phase's groups are spread over
+constexpr int32_t kMaxTilesPerBlock = 1 << 20;   // schedule bound (keeps 2 x tiles in int range)
 
 }  // namespace
 
@@ -70,6 +71,7 @@ struct km_batch {
     std::vector<std::pair<int, size_t>> classes;
     std::map<std::pair<int, size_t>, int> class_tpb;
     std::vector<int> tpb_inst;             // tiles per block of each instance (its class's)
+    std::vector<int64_t> rq_rows;          // recheck queue entries per region of each instance
     // derived layout
     std::vector<int> nslots;
     std::vector<size_t> off_cp, off_S, off_cnt, off_J, off_ch;
@@ -241,6 +243,7 @@ void layout(km_batch* B)
         B->off_rq.assign(m, 0); B->off_rqc.assign(m, 0); B->off_chg.assign(m, 0); B->off_jt.assign(m, 0);
         B->off_xpm.assign(m, 0); B->off_xps.assign(m, 0); B->nxb.assign(m, 0);
         B->off_xb.assign(m, 0); B->off_xn.assign(m, 0);
+        B->rq_rows.assign(m, 0);
         B->xwork.clear();
         for (int i = 0; i < m; ++i) {
             const km_instance& x = B->inst[i];
@@ -249,6 +252,8 @@ void layout(km_batch* B)
             const int64_t mt = (x.n + kMixTile - 1) / kMixTile;
             const int nr = (int)((mt + tpm - 1) / tpm);
             B->nreg[i] = nr;
+            // a region holds at most its samples: no more than the instance's
+            B->rq_rows[i] = std::min<int64_t>(tpm, mt) * kMixTile;
             for (int r = 0; r < nr; ++r) {
                 BatchWork w;
                 w.inst = i;
@@ -271,7 +276,7 @@ void layout(km_batch* B)
             B->off_ab[i] = off;   off = al256(off + (size_t)kpad * 16 * D16 * sizeof(__bf16));
             B->off_bias[i] = off; off = al256(off + (size_t)kpad * sizeof(float));
             B->off_cs[i] = off;   off = al256(off + sizeof(CStats));
-            B->off_rq[i] = off;   off = al256(off + (size_t)nr * tpm * kMixTile * kRqInts * sizeof(int32_t));
+            B->off_rq[i] = off;   off = al256(off + (size_t)nr * B->rq_rows[i] * kRqInts * sizeof(int32_t));
             B->off_rqc[i] = off;  off = al256(off + 2 * (size_t)nr * sizeof(int32_t));
             B->off_chg[i] = off;  off = al256(off + (size_t)(1 + kBatchRecheckSplit) * nr * sizeof(int32_t));
             B->off_jt[i] = off;   off = al256(off + (size_t)finalize_blocks(x.k, x.d) * sizeof(double));
@@ -354,7 +359,7 @@ km_status upload(km_batch* B)
         mm.labels = x.labels;
         mm.rq = reinterpret_cast<int32_t*>(ws + B->off_rq[i]);
         mm.rq_count = reinterpret_cast<int32_t*>(ws + B->off_rqc[i]);
-        mm.rq_per_block = (int64_t)2 * B->tpb_inst[i] * kMixTile;
+        mm.rq_per_block = B->rq_rows[i];
         mm.nreg = nr;
         mm.changed_part = chg;
         mm.ctrl = nullptr; mm.iter = 0; mm.count_changed = 0;
@@ -527,7 +532,8 @@ km_status km_batch_set_schedule(km_batch* batch, int32_t tiles_per_block, int32_
 {
     km_set_error(KM_OK, "");
     if (!batch) return berr(KM_EINVAL, "batch is NULL");
-    if (tiles_per_block < 1 || (order != 0 && order != 1)) return berr(KM_EINVAL, "bad schedule");
+    if (tiles_per_block < 1 || tiles_per_block > kMaxTilesPerBlock || (order != 0 && order != 1))
+        return berr(KM_EINVAL, "bad schedule (tiles per block in [1, %d], order 0 or 1)", kMaxTilesPerBlock);
     batch->tpb = tiles_per_block;
     batch->order = order;
     batch->drop_graph();
@@ -563,7 +569,8 @@ km_status km_batch_set_class_schedule(km_batch* batch, int32_t cls, int32_t tile
     km_set_error(KM_OK, "");
     if (!batch) return berr(KM_EINVAL, "batch is NULL");
     if (cls < 0 || cls >= (int32_t)batch->classes.size()) return berr(KM_EINVAL, "class %d out of range", cls);
-    if (tiles_per_block < 0) return berr(KM_EINVAL, "bad tiles_per_block %d", tiles_per_block);
+    if (tiles_per_block < 0 || tiles_per_block > kMaxTilesPerBlock)
+        return berr(KM_EINVAL, "bad tiles_per_block %d (0, or 1 to %d)", tiles_per_block, kMaxTilesPerBlock);
     batch->class_tpb[batch->classes[cls]] = tiles_per_block;
     batch->drop_graph();
     batch->ws = nullptr;   // layout changes: a workspace must be bound again

@@ -195,6 +195,18 @@ def test_batched_per_class_schedules():
         b32.set_class_schedule(len(cl), 2)
     with pytest.raises(B.KMeansError):
         b32.set_class_schedule(0, -1)
+    with pytest.raises(B.KMeansError):
+        b32.set_class_schedule(0, (1 << 20) + 1)
+    with pytest.raises(B.KMeansError):
+        b32.set_schedule((1 << 20) + 1, 0)
+    # a schedule far longer than any instance: one block and one queue region each
+    b16.set_schedule(1 << 20, 1)
+    for c in range(len(cl)):
+        b16.set_class_schedule(c, 0)
+    B.kmeans_lloyd_batched(b16, 1)
+    torch.cuda.synchronize()
+    for i, ((X, _), t) in enumerate(zip(host, inst16)):
+        check_labels(t["labels"].cpu().numpy(), Cs[i], X, f"long schedule instance {i}")
 
 
 def test_batched_rejects_bad_instances():
