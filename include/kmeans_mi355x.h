@@ -209,7 +209,10 @@ km_status kmeans_lloyd_static(km_plan *plan, const float *X, float *C, int32_t *
  * advanced together, every iteration of all of them in one launch of the
  * per-sample pass per shape class plus one finalize launch (and, with graphs
  * enabled, one graph launch for the whole call).  Each instance is the same
- * computation as kmeans_lloyd with a fixed iteration count.
+ * computation as kmeans_lloyd with a fixed iteration count.  Instances of
+ * more than 128 features run the single-instance path (a plan of their own,
+ * its workspace inside the batch's) on a stream of the batch, forked from and
+ * joined back to the caller's stream within the same call.
  */
 typedef struct {
     const float *X;     /* [n x d] FP32 samples (device, 16-byte aligned)       */
@@ -225,8 +228,9 @@ typedef struct km_batch km_batch;
 
 /*
  * Create a batch over `count` instances (host array, copied).  Validates every
- * instance like km_plan_create (KM_EINVAL), needs d <= 128 and a per-label
- * record k * d * 8 bytes of at most 80 KiB (KM_ENOTSUP otherwise).  Precision
+ * instance like km_plan_create (KM_EINVAL, 1 <= d <= 1024); an instance of at
+ * most 128 features needs a per-label record k * d * 8 bytes of at most 80 KiB
+ * (KM_ENOTSUP otherwise), a wider one whatever km_plan_create accepts.  Precision
  * KM_FP32 (direct-form FP32 distances) or KM_BF16 (BF16 MFMA distances with
  * the proven-band FP32 recheck, labels equal to the FP32 batch's); KM_ENOTSUP
  * for KM_FP8_E4M3.  Queries the device.

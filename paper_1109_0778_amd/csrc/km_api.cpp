@@ -888,6 +888,18 @@ km_status enqueue_lloyd(km_plan* plan, const float* X, float* C, int32_t* labels
 
 }  // namespace
 
+namespace km {
+
+km_status plan_enqueue_fixed(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
+                             double* obj_hist, int32_t iters, hipStream_t stream)
+{
+    km_status st = check_plan(plan);
+    if (st != KM_OK) return st;
+    return enqueue_lloyd(plan, X, C, labels, counts, obj_hist, iters, -1.0, stream);
+}
+
+}  // namespace km
+
 extern "C" {
 
 km_status km_plan_enable_timing(km_plan* plan, int32_t cap)

@@ -61,7 +61,15 @@ constexpr int32_t kMaxTilesPerBlock = 1 << 20;   // schedule bound (keeps 2 x ti
 }  // namespace
 
 struct km_batch {
-    std::vector<km_instance> inst;
+    std::vector<km_instance> inst;         // instances of at most 128 features (the class schedule)
+    // instances of more than 128 features: each runs the single-instance
+    // path through a plan of its own, on a stream of its own, inside the
+    // same call (and graph)
+    std::vector<km_instance> wide;
+    std::vector<km_plan*> wplan;
+    std::vector<size_t> off_wide;
+    hipStream_t wstream = nullptr;
+    hipEvent_t ev_wfork = nullptr, ev_wjoin = nullptr;
     int device = 0;
     bool mixed = false;    // BF16 MFMA distances + exact FP32 recheck
     int tpb = 16;          // tiles per block (classes without their own value)
@@ -112,6 +120,10 @@ struct km_batch {
             if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
         }
         if (ev_fork) (void)hipEventDestroy(ev_fork);
+        for (km_plan* p : wplan) km_plan_destroy(p);
+        if (wstream) (void)hipStreamDestroy(wstream);
+        if (ev_wfork) (void)hipEventDestroy(ev_wfork);
+        if (ev_wjoin) (void)hipEventDestroy(ev_wjoin);
     }
 };
 
@@ -297,6 +309,11 @@ void layout(km_batch* B)
         B->off_rwork = off; off = al256(off + B->rwork.size() * sizeof(BatchWork));
         B->off_xwork = off; off = al256(off + B->xwork.size() * sizeof(BatchWork));
     }
+    B->off_wide.assign(B->wide.size(), 0);
+    for (size_t w = 0; w < B->wide.size(); ++w) {
+        B->off_wide[w] = off;
+        off = al256(off + km_plan_workspace_bytes(B->wplan[w]));
+    }
     B->off_pa = off;    off = al256(off + (size_t)m * sizeof(PassArgs));
     B->off_fa = off;    off = al256(off + (size_t)m * sizeof(FinArgs));
     B->off_work = off;  off = al256(off + B->work.size() * sizeof(BatchWork));
@@ -304,9 +321,21 @@ void layout(km_batch* B)
     B->total = off;
 }
 
-// Device tables: per-instance PassArgs / FinArgs pointing into the workspace.
+// hipMemcpy that skips empty tables (a batch may hold no instance of some kind).
+hipError_t h2d(void* dst, const void* src, size_t bytes, hipMemcpyKind kind)
+{
+    return bytes == 0 ? hipSuccess : hipMemcpy(dst, src, bytes, kind);
+}
+
+// Device tables: per-instance PassArgs / FinArgs pointing into the workspace;
+// the wide instances' plans get their workspace slices.
 km_status upload(km_batch* B)
 {
+    for (size_t w = 0; w < B->wide.size(); ++w) {
+        const km_status st = km_plan_set_workspace(B->wplan[w], B->ws + B->off_wide[w],
+                                                   km_plan_workspace_bytes(B->wplan[w]));
+        if (st != KM_OK) return st;
+    }
     const int m = (int)B->inst.size();
     std::vector<PassArgs> pa(m);
     std::vector<FinArgs> fa(m);
@@ -376,20 +405,20 @@ km_status upload(km_batch* B)
         b.nxb = B->nxb[i];
     }
     hipError_t e;
-    if ((e = hipMemcpy(ws + B->off_pa, pa.data(), pa.size() * sizeof(PassArgs), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(ws + B->off_fa, fa.data(), fa.size() * sizeof(FinArgs), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(ws + B->off_work, B->work.data(), B->work.size() * sizeof(BatchWork),
+    if ((e = h2d(ws + B->off_pa, pa.data(), pa.size() * sizeof(PassArgs), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = h2d(ws + B->off_fa, fa.data(), fa.size() * sizeof(FinArgs), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = h2d(ws + B->off_work, B->work.data(), B->work.size() * sizeof(BatchWork),
                        hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(ws + B->off_fwork, B->fwork.data(), B->fwork.size() * sizeof(BatchFinWork),
+        (e = h2d(ws + B->off_fwork, B->fwork.data(), B->fwork.size() * sizeof(BatchFinWork),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bhip(e, "hipMemcpy(batch tables)");
     if (B->mixed &&
-        ((e = hipMemcpy(ws + B->off_bm, bm.data(), bm.size() * sizeof(BatchMix), hipMemcpyHostToDevice)) != hipSuccess ||
-         (e = hipMemcpy(ws + B->off_mwork, B->mwork.data(), B->mwork.size() * sizeof(BatchWork),
+        ((e = h2d(ws + B->off_bm, bm.data(), bm.size() * sizeof(BatchMix), hipMemcpyHostToDevice)) != hipSuccess ||
+         (e = h2d(ws + B->off_mwork, B->mwork.data(), B->mwork.size() * sizeof(BatchWork),
                         hipMemcpyHostToDevice)) != hipSuccess ||
-         (e = hipMemcpy(ws + B->off_rwork, B->rwork.data(), B->rwork.size() * sizeof(BatchWork),
+         (e = h2d(ws + B->off_rwork, B->rwork.data(), B->rwork.size() * sizeof(BatchWork),
                         hipMemcpyHostToDevice)) != hipSuccess ||
-         (e = hipMemcpy(ws + B->off_xwork, B->xwork.data(), B->xwork.size() * sizeof(BatchWork),
+         (e = h2d(ws + B->off_xwork, B->xwork.data(), B->xwork.size() * sizeof(BatchWork),
                         hipMemcpyHostToDevice)) != hipSuccess))
         return bhip(e, "hipMemcpy(batch mixed tables)");
     return KM_OK;
@@ -403,8 +432,27 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
     const BatchWork* work = reinterpret_cast<const BatchWork*>(ws + B->off_work);
     const BatchFinWork* fwork = reinterpret_cast<const BatchFinWork*>(ws + B->off_fwork);
     const int m = (int)B->inst.size();
-    hipError_t e = launch_batch_pad(fa, nullptr, m, s);
-    if (e != hipSuccess) return bhip(e, "batch pad launch");
+    hipError_t e = hipSuccess;
+    // wide instances: all their iterations on the wide stream, forked from s
+    // here and joined back at the end, overlapping the class launches
+    if (!B->wide.empty()) {
+        if ((e = hipEventRecord(B->ev_wfork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(B->wstream, B->ev_wfork, 0)) != hipSuccess)
+            return bhip(e, "wide fork");
+        for (size_t w = 0; w < B->wide.size(); ++w) {
+            const km_instance& x = B->wide[w];
+            const km_status st = plan_enqueue_fixed(B->wplan[w], x.X, x.C, x.labels, x.counts, x.obj_hist, iters,
+                                                    B->wstream);
+            if (st != KM_OK) return st;
+        }
+        if ((e = hipEventRecord(B->ev_wjoin, B->wstream)) != hipSuccess) return bhip(e, "wide join");
+    }
+    auto join_wide = [&]() -> km_status {
+        if (!B->wide.empty() && (e = hipStreamWaitEvent(s, B->ev_wjoin, 0)) != hipSuccess) return bhip(e, "wide join");
+        return KM_OK;
+    };
+    if (m == 0) return join_wide();
+    if ((e = launch_batch_pad(fa, nullptr, m, s)) != hipSuccess) return bhip(e, "batch pad launch");
     const BatchMix* bm = reinterpret_cast<const BatchMix*>(ws + B->off_bm);
     const BatchWork* mwork = reinterpret_cast<const BatchWork*>(ws + B->off_mwork);
     const BatchWork* rwork = reinterpret_cast<const BatchWork*>(ws + B->off_rwork);
@@ -460,7 +508,7 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
         if (B->mixed && (e = launch_batch_objective(fa, m, t, s)) != hipSuccess)
             return bhip(e, "batch objective launch");
     }
-    return KM_OK;
+    return join_wide();
 }
 
 }  // namespace
@@ -483,7 +531,7 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
         if (!x.X || !x.C || !x.labels) return berr(KM_EINVAL, "instance %d: X, C and labels must be non-NULL", i);
         if ((reinterpret_cast<uintptr_t>(x.X) | reinterpret_cast<uintptr_t>(x.C)) & 15u)
             return berr(KM_EINVAL, "instance %d: X and C must be 16-byte aligned", i);
-        if (x.d > 8 * kMaxD8Plain) return berr(KM_ENOTSUP, "instance %d: batched Lloyd supports d <= 128", i);
+        if (x.d > 8 * kMaxD8Plain) continue;   // a wide instance: checked by its plan
         if (plain_lds_bytes(x.k, x.d, MODE_FUSED) > 80 * 1024)
             return berr(KM_ENOTSUP, "instance %d: k*d too large for a batched per-label record", i);
         if (prec == KM_BF16 && kpad_of(x.k) > 16384)
@@ -494,9 +542,30 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
     if (e != hipSuccess) return bhip(e, "hipGetDevice");
     km_batch* B = new (std::nothrow) km_batch();
     if (!B) return berr(KM_EINVAL, "out of host memory");
-    B->inst.assign(inst, inst + count);
     B->device = dev;
     B->mixed = prec == KM_BF16;
+    for (int32_t i = 0; i < count; ++i) {
+        if (inst[i].d <= 8 * kMaxD8Plain) {
+            B->inst.push_back(inst[i]);
+            continue;
+        }
+        km_plan* p = nullptr;
+        const km_status st = km_plan_create(inst[i].n, inst[i].d, inst[i].k, prec, &p);
+        if (st != KM_OK) {
+            const std::string why = km_last_error();
+            delete B;
+            return berr(st, "instance %d (d = %d): %s", i, inst[i].d, why.c_str());
+        }
+        B->wide.push_back(inst[i]);
+        B->wplan.push_back(p);
+    }
+    if (!B->wide.empty() &&
+        ((e = hipStreamCreateWithFlags(&B->wstream, hipStreamNonBlocking)) != hipSuccess ||
+         (e = hipEventCreateWithFlags(&B->ev_wfork, hipEventDisableTiming)) != hipSuccess ||
+         (e = hipEventCreateWithFlags(&B->ev_wjoin, hipEventDisableTiming)) != hipSuccess)) {
+        delete B;
+        return bhip(e, "wide stream / event creation");
+    }
     for (int i = 0; i < km_batch::kSide; ++i) {
         if ((e = hipStreamCreateWithFlags(&B->side[i], hipStreamNonBlocking)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&B->ev_join[i], hipEventDisableTiming)) != hipSuccess) {

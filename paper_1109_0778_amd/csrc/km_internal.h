@@ -1,6 +1,8 @@
 // Internal declarations shared by the host API and the gfx950 kernels.
 #pragma once
 
+#include "kmeans_mi355x.h"
+
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
@@ -333,6 +335,11 @@ struct BatchMix {
     int32_t nxb;
 };
 constexpr int kPrepXRows = 4096;    // rows per block of the batched run-level statistics
+// T fixed Lloyd iterations of a single-instance plan, enqueued on `stream`
+// (no graph of its own, no host synchronisation); the batched call runs its
+// instances of more than 128 features through it.
+km_status plan_enqueue_fixed(km_plan* plan, const float* X, float* C, int32_t* labels, int64_t* counts,
+                             double* obj_hist, int32_t iters, hipStream_t stream);
 hipError_t launch_batch_prep_x(const BatchWork* xwork, int nxwork, const BatchMix* bm, int ninst, hipStream_t s);
 hipError_t launch_batch_prep_c(const BatchMix* bm, int ninst, hipStream_t s);
 hipError_t launch_batch_mfma(int D16, const BatchWork* work, int nwork, const BatchMix* bm, int iter, hipStream_t s);

@@ -209,6 +209,57 @@ def test_batched_per_class_schedules():
         check_labels(t["labels"].cpu().numpy(), Cs[i], X, f"long schedule instance {i}")
 
 
+WIDE_SHAPES = [(3000, 16, 20), (2500, 129, 17), (4000, 300, 40), (700, 64, 9), (1500, 1024, 12)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_wide_instances(prec):
+    """Instances of more than 128 features in a batch run the single-instance
+    path inside the call: stepwise against the oracle (every instance, two
+    iterations), the wide ones equal to kmeans_lloyd on their own bit for bit,
+    graph replays equal to direct launches, and a batch of wide instances only."""
+    torch, B = _torch(), _bind()
+    inst, host = make_batch(torch, B, WIDE_SHAPES, seed0=600, iters=2)
+    inst2, _ = make_batch(torch, B, WIDE_SHAPES, seed0=600, iters=2)
+    batch = B.Batch(inst, precision=prec)
+    b2 = B.Batch(inst2, precision=prec)
+    b2.use_graphs(True)
+    Cs = [C.copy() for _, C in host]
+    for t in range(2):
+        B.kmeans_lloyd_batched(batch, 1)
+        B.kmeans_lloyd_batched(b2, 1)
+        torch.cuda.synchronize()
+        for i, ((X, _), ti, tj) in enumerate(zip(host, inst, inst2)):
+            say(f"{prec} t={t} instance {i} shape {X.shape} k={Cs[i].shape[0]}")
+            lab = ti["labels"].cpu().numpy()
+            check_labels(lab, Cs[i], X, f"{prec} wide batch instance {i} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(ti["counts"].cpu().numpy(), cnto)
+            Cg = ti["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"{prec} wide batch instance {i} t={t}")
+            assert torch.equal(ti["C"], tj["C"]) and torch.equal(ti["labels"], tj["labels"]), f"graph, instance {i}"
+            Cs[i] = Cg
+    # the wide instances alone, through kmeans_lloyd from the same C_0
+    for i, (n, d, k) in enumerate(WIDE_SHAPES):
+        if d <= 128:
+            continue
+        X, C0 = host[i]
+        plan = B.Plan(n, d, k, prec)
+        Xg, Cg = torch.from_numpy(X).cuda(), torch.from_numpy(C0).cuda()
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        B.kmeans_lloyd(plan, Xg, Cg, lab, None, None, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(Cg, inst[i]["C"]) and torch.equal(lab, inst[i]["labels"]), f"instance {i} alone"
+    # wide instances only
+    only, ohost = make_batch(torch, B, [s_ for s_ in WIDE_SHAPES if s_[1] > 128], seed0=700, iters=1)
+    ob = B.Batch(only, precision=prec)
+    assert ob.classes() == []
+    B.kmeans_lloyd_batched(ob, 1)
+    torch.cuda.synchronize()
+    for i, ((X, C0), ti) in enumerate(zip(ohost, only)):
+        check_labels(ti["labels"].cpu().numpy(), C0, X, f"{prec} wide-only instance {i}")
+
+
 def test_batched_rejects_bad_instances():
     torch, B = _torch(), _bind()
     dev = torch.device("cuda")
