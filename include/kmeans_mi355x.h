@@ -232,8 +232,10 @@ typedef struct km_batch km_batch;
  * most 128 features needs a per-label record k * d * 8 bytes of at most 80 KiB
  * (KM_ENOTSUP otherwise), a wider one whatever km_plan_create accepts.  Precision
  * KM_FP32 (direct-form FP32 distances) or KM_BF16 (BF16 MFMA distances with
- * the proven-band FP32 recheck, labels equal to the FP32 batch's); KM_ENOTSUP
- * for KM_FP8_E4M3.  Queries the device.
+ * the proven-band FP32 recheck, labels equal to the FP32 batch's), or
+ * KM_FP8_E4M3, where every instance runs the single-instance FP8 path (a plan
+ * each, on the batch's stream, within the call; no batched FP8 kernels).
+ * Queries the device.
  */
 km_status km_batch_create(const km_instance *inst, int32_t count, km_precision prec,
                           km_batch **out);

@@ -522,7 +522,10 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
     *out = nullptr;
     if (!inst || count < 1) return berr(KM_EINVAL, "need at least one instance");
     if (prec != KM_FP32 && prec != KM_BF16 && prec != KM_FP8_E4M3) return berr(KM_EINVAL, "unknown precision %d", (int)prec);
-    if (prec == KM_FP8_E4M3) return berr(KM_ENOTSUP, "batched Lloyd supports FP32 and BF16 distances");
+    // FP8 batches run every instance through its own FP8 plan (the FP8 screen
+    // needs a BF16 screen and refine of its open samples; there are no
+    // batched FP8 kernels)
+    const bool via_plans = prec == KM_FP8_E4M3;
     for (int32_t i = 0; i < count; ++i) {
         const km_instance& x = inst[i];
         if (x.n < 1 || x.n >= ((int64_t)1 << 31)) return berr(KM_EINVAL, "instance %d: n outside [1, 2^31)", i);
@@ -531,7 +534,7 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
         if (!x.X || !x.C || !x.labels) return berr(KM_EINVAL, "instance %d: X, C and labels must be non-NULL", i);
         if ((reinterpret_cast<uintptr_t>(x.X) | reinterpret_cast<uintptr_t>(x.C)) & 15u)
             return berr(KM_EINVAL, "instance %d: X and C must be 16-byte aligned", i);
-        if (x.d > 8 * kMaxD8Plain) continue;   // a wide instance: checked by its plan
+        if (via_plans || x.d > 8 * kMaxD8Plain) continue;   // checked by its plan
         if (plain_lds_bytes(x.k, x.d, MODE_FUSED) > 80 * 1024)
             return berr(KM_ENOTSUP, "instance %d: k*d too large for a batched per-label record", i);
         if (prec == KM_BF16 && kpad_of(x.k) > 16384)
@@ -545,7 +548,7 @@ km_status km_batch_create(const km_instance* inst, int32_t count, km_precision p
     B->device = dev;
     B->mixed = prec == KM_BF16;
     for (int32_t i = 0; i < count; ++i) {
-        if (inst[i].d <= 8 * kMaxD8Plain) {
+        if (!via_plans && inst[i].d <= 8 * kMaxD8Plain) {
             B->inst.push_back(inst[i]);
             continue;
         }

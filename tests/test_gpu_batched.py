@@ -270,9 +270,44 @@ def test_batched_rejects_bad_instances():
     with pytest.raises(B.KMeansError) as e:
         B.Batch([good, bad])
     assert e.value.status == B.KM_EINVAL
-    with pytest.raises(B.KMeansError) as e:
-        B.Batch([good], precision="fp8")
+    big = {"X": torch.zeros(300, 64, device=dev), "C": torch.zeros(200, 64, device=dev),
+           "labels": torch.zeros(300, dtype=torch.int32, device=dev)}
+    with pytest.raises(B.KMeansError) as e:          # a 200 x 64 FP64 record does not fit 80 KiB
+        B.Batch([good, big])
     assert e.value.status == B.KM_ENOTSUP
+    with pytest.raises(B.KMeansError) as e:
+        B.Batch([good, bad], precision="fp8")
+    assert e.value.status == B.KM_EINVAL
+
+
+def test_batched_fp8_through_plans():
+    """FP8 batches: every instance through its own FP8 plan in the call; stepwise
+    against the oracle and equal to kmeans_lloyd with the same plan bit for bit."""
+    torch, B = _torch(), _bind()
+    shapes = [(3000, 32, 20), (2500, 64, 70), (1500, 200, 12)]
+    inst, host = make_batch(torch, B, shapes, seed0=800, iters=2)
+    batch = B.Batch(inst, precision="fp8")
+    assert batch.classes() == []
+    Cs = [C.copy() for _, C in host]
+    for t in range(2):
+        B.kmeans_lloyd_batched(batch, 1)
+        torch.cuda.synchronize()
+        for i, ((X, _), ti) in enumerate(zip(host, inst)):
+            lab = ti["labels"].cpu().numpy()
+            check_labels(lab, Cs[i], X, f"fp8 batch instance {i} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(ti["counts"].cpu().numpy(), cnto)
+            Cg = ti["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"fp8 batch instance {i} t={t}")
+            Cs[i] = Cg
+    for i, (n, d, k) in enumerate(shapes):
+        X, C0 = host[i]
+        plan = B.Plan(n, d, k, "fp8")
+        Xg, Cg = torch.from_numpy(X).cuda(), torch.from_numpy(C0).cuda()
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        B.kmeans_lloyd(plan, Xg, Cg, lab, None, None, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(Cg, inst[i]["C"]) and torch.equal(lab, inst[i]["labels"]), f"instance {i} alone"
 
 
 @pytest.mark.slow
