@@ -82,25 +82,28 @@ def _apply(batch, tpb, order, class_tpb):
 
 
 def tune_batch(batch, reps: int = 2, use_cache: bool = True, verbose: bool = False,
-               per_class: bool = True):
+               per_class: bool = True, timer=None, arch: str | None = None):
     """Pick (tiles_per_block, order), then per-class tiles per block, for
     `batch` and apply them.  The instances' centroids are restored afterwards.
+    `timer(batch) -> ms` times the batch's current schedule (default: one
+    Lloyd iteration, HIP events, `reps` repetitions after a warm-up).
     Returns ((tiles_per_block, order, [per-class tiles per block]), {candidate: ms})."""
-    import torch
-
-    key = f"{_arch()}:{getattr(batch, 'precision', 'fp32')}:{signature(batch.instances)}"
+    key = f"{arch or _arch()}:{getattr(batch, 'precision', 'fp32')}:{signature(batch.instances)}"
     db = _load() if use_cache else {}
     if key in db and ("class_tpb" in db[key] or not per_class):
         tpb, order = db[key]["choice"]
         ctpb = db[key].get("class_tpb", []) if per_class else []
         _apply(batch, tpb, order, ctpb)
         return (tpb, order, ctpb), db[key].get("ms", {})
+    if timer is None:
+        import torch
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        timer = lambda b: _time(b, reps, start, end)   # noqa: E731
     saved = [t["C"].clone() for t in batch.instances]
     times = {}
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for tpb, order in CANDIDATES:
         batch.set_schedule(tpb, order)
-        times[f"{tpb},{order}"] = _time(batch, reps, start, end)
+        times[f"{tpb},{order}"] = timer(batch)
         if verbose:
             print(f"tiles_per_block={tpb} order={order}: {times[f'{tpb},{order}']:.3f} ms", flush=True)
     best = min(times, key=times.get)
@@ -116,7 +119,7 @@ def tune_batch(batch, reps: int = 2, use_cache: bool = True, verbose: bool = Fal
                 if v == tpb:
                     continue
                 batch.set_class_schedule(c, v)
-                t = _time(batch, reps, start, end)
+                t = timer(batch)
                 times[f"class{c}:{v}"] = t
                 if verbose:
                     print(f"class {c} (D8={d8}, lds={lds}, {cnt} instances) tiles_per_block={v}: {t:.3f} ms",
