@@ -260,6 +260,26 @@ def test_batched_wide_instances(prec):
         check_labels(ti["labels"].cpu().numpy(), C0, X, f"{prec} wide-only instance {i}")
 
 
+def test_batched_optional_outputs():
+    """counts and obj_hist are optional for every kind of instance (class
+    schedule, wide, FP8 through plans): labels and centroids are unchanged
+    by leaving them out."""
+    torch, B = _torch(), _bind()
+    shapes = [(2000, 16, 10), (1500, 200, 8)]
+    for prec in ("fp32", "bf16", "fp8"):
+        full, host = make_batch(torch, B, shapes, seed0=900, iters=2)
+        bare, _ = make_batch(torch, B, shapes, seed0=900, iters=2)
+        for t in bare:
+            del t["counts"], t["obj_hist"]
+        bf, bb = B.Batch(full, precision=prec), B.Batch(bare, precision=prec)
+        B.kmeans_lloyd_batched(bf, 2)
+        B.kmeans_lloyd_batched(bb, 2)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(full, bare)):
+            assert torch.equal(a["labels"], b["labels"]) and torch.equal(a["C"], b["C"]), f"{prec} instance {i}"
+            assert int(a["counts"].sum()) == shapes[i][0]
+
+
 def test_batched_rejects_bad_instances():
     torch, B = _torch(), _bind()
     dev = torch.device("cuda")
