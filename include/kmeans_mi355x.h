@@ -252,7 +252,9 @@ km_status km_batch_set_workspace(km_batch *batch, void *ws, size_t bytes);
  */
 km_status km_batch_set_schedule(km_batch *batch, int32_t tiles_per_block, int32_t order);
 /*
- * Per-class schedules.  Instances fall into shape classes: (8-feature chunks
+ * Per-class schedules.  Instances of at most 128 features in FP32 and BF16
+ * batches fall into shape classes (wider instances and FP8 batches, which run
+ * per-instance plans, have none): (8-feature chunks
  * of d, LDS bucket of the FP32 fused pass's per-label record), listed in
  * increasing order; the partition does not depend on the precision, so class
  * c names the same instances in an FP32 and a BF16 batch of one instance set.
