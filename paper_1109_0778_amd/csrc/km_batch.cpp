@@ -6,7 +6,11 @@
 // per iteration one centroid-prep launch (a block per instance), the MFMA
 // pass per operand width and the exact recheck per feature width over their
 // own work tables, the update pass per shape class, the finalize and the
-// objective; the |x| statistics once per call.
+// objective; the BF16 copy of X and the |x| statistics once per call.
+// Instances of more than 128 features, and every instance of an FP8 batch,
+// run the single-instance launch sequence of a plan of their own on a side
+// stream of the batch, forked from and joined back to the caller's stream
+// within the call.
 #include "kmeans_mi355x.h"
 #include "km_internal.h"
 
