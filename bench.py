@@ -287,9 +287,13 @@ def workload_desc(w):
             f"seed {w.seed}, init={w.init}, {w.iters} iterations")
 
 
-def _batched_run(B, torch, inst, C0, iters, precision, schedule=None):
+PERSIST_SCHEDULE = (32, 1, [])
+
+
+def _batched_run(B, torch, inst, C0, iters, precision, schedule=None, persistent=False):
     """Autotune (or set) the schedule, capture the iterations as one graph,
-    reset the centroids and time one graph launch."""
+    reset the centroids and time one graph launch (with `persistent`, the
+    persistent launch at the given schedule)."""
     from paper_1109_0778_amd import autotune
     batch = B.Batch(inst, precision=precision)
     if schedule is None:
@@ -297,6 +301,8 @@ def _batched_run(B, torch, inst, C0, iters, precision, schedule=None):
     else:
         autotune._apply(batch, *schedule)
         choice, tune_ms = tuple(schedule), {}
+    if persistent:
+        batch.use_persistent(True)
     batch.use_graphs(True)
     B.kmeans_lloyd_batched(batch, iters)            # capture + warm-up
     torch.cuda.synchronize()
@@ -349,6 +355,11 @@ def batched_report(B, torch, iters, per_instance_sample=32):
     inst, shapes = batched_instances(torch, iters)
     C0 = [t["C"].clone() for t in inst]
     el32, ch32, tm32, _ = _batched_run(B, torch, inst, C0, iters, "fp32")
+    # the persistent launch at its best measured schedule (32 tiles per block),
+    # beside the per-class launches at that same schedule (identical results)
+    el32p, _, _, res32p = _batched_run(B, torch, inst, C0, iters, "fp32", schedule=PERSIST_SCHEDULE, persistent=True)
+    el32c, _, _, res32c = _batched_run(B, torch, inst, C0, iters, "fp32", schedule=PERSIST_SCHEDULE)
+    same_p = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(res32c, res32p))
     el16, ch16, tm16, res16 = _batched_run(B, torch, inst, C0, iters, "bf16")
     _, _, _, res32s = _batched_run(B, torch, inst, C0, iters, "fp32", schedule=ch16)
     same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(res16, res32s))
@@ -374,7 +385,8 @@ def batched_report(B, torch, iters, per_instance_sample=32):
     el_single *= len(inst) / per_instance_sample
     ms_round = el16 * 1e3 / iters
     log(f"batched: {len(inst)} instances x {iters} iterations: BF16 {el16 * 1e3:.1f} ms (schedule {ch16}), "
-        f"FP32 {el32 * 1e3:.1f} ms (schedule {ch32}); identical to FP32 at the same schedule: {same}; "
+        f"FP32 {el32 * 1e3:.1f} ms (schedule {ch32}), FP32 persistent launch {el32p * 1e3:.1f} ms (identical: "
+        f"{same_p}); BF16 identical to FP32 at the same schedule: {same}; "
         f"per-instance FP32 launches, extrapolated: {el_single * 1e3:.1f} ms")
     return {"workload": f"batched: {len(inst)} instances, n log-uniform [1e3, 2e5] (total {pts}), d in {{16,32,64}}, "
                         f"k uniform [4,128], blobs = k, sigma 1, seeds 0..{len(inst) - 1}, {iters} iterations",
@@ -387,6 +399,13 @@ def batched_report(B, torch, iters, per_instance_sample=32):
                              flops_per_round=flops,
                              mfma_frac_of_round=flops / (ms_round * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"]),
             "fp32_batched_value": len(inst) * iters / el32,
+            "fp32_persistent": {"value": len(inst) * iters / el32p, "ms_per_round": el32p * 1e3 / iters,
+                                "schedule": list(PERSIST_SCHEDULE[:2]),
+                                "class_schedule_ms_per_round_same_schedule": el32c * 1e3 / iters,
+                                "vs_best_class_schedule": el32 / el32p,
+                                "identical_to_class_schedule": bool(same_p),
+                                "launch": "one persistent kernel per 32 iterations: device queue, per-instance "
+                                          "completion tickets, graph-captured"},
             "speedup_vs_fp32_batched": el32 / el16,
             "labels_and_centroids_equal_fp32_batched": bool(same),
             "per_instance_launches_value": len(inst) * iters / el_single,

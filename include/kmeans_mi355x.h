@@ -270,6 +270,22 @@ int32_t km_batch_num_classes(const km_batch *batch);
 km_status km_batch_class_info(const km_batch *batch, int32_t cls, int32_t *d8, int32_t *lds_bytes,
                               int32_t *instances, int32_t *tiles_per_block);
 km_status km_batch_set_class_schedule(km_batch *batch, int32_t cls, int32_t tiles_per_block);
+/*
+ * Persistent launch (FP32 batches whose instances of at most 128 features all
+ * have d <= 64; KM_ENOTSUP otherwise): kmeans_lloyd_batched then runs one
+ * kernel per 32 iterations.  Its resident blocks take (iteration, work row)
+ * items from a device queue in iteration order and run the fused pass; the
+ * block that finishes an instance's last row of an iteration finalizes that
+ * instance (the same combine order as the per-class launches, so results are
+ * identical at the same schedule) and publishes its next iteration, so each
+ * instance advances on its own completion ticket instead of a global
+ * per-iteration barrier.  Waits are bounded: a wait past its bound sets an
+ * abort flag, every block exits, and km_batch_persistent_status (synchronous)
+ * reports it (*aborted = 1; the results of that call are then invalid).
+ * Changes the workspace size (bind a workspace again afterwards).
+ */
+km_status km_batch_use_persistent(km_batch *batch, int32_t enable);
+km_status km_batch_persistent_status(km_batch *batch, int32_t *aborted);
 /* As km_plan_use_graphs, for kmeans_lloyd_batched (graph keyed by iterations). */
 km_status km_batch_use_graphs(km_batch *batch, int32_t enable);
 void km_batch_destroy(km_batch *batch);

@@ -26,7 +26,8 @@ EXPORTS = ["km_plan_create", "km_plan_workspace_bytes", "km_plan_set_workspace",
            "km_batch_set_schedule", "km_batch_use_graphs", "km_batch_destroy", "kmeans_lloyd_batched",
            "spade_workspace_bytes", "spade_densities", "spade_stats", "km_class_sums", "nb_train",
            "gda_workspace_bytes", "gda_train", "kmeans_assign_metric", "km_batch_num_classes",
-           "km_batch_class_info", "km_batch_set_class_schedule"]
+           "km_batch_class_info", "km_batch_set_class_schedule", "km_batch_use_persistent",
+           "km_batch_persistent_status"]
 LAYOUTS = {"row": 0, "feature": 1}
 METRICS = {"l1": 0, "sqeuclidean": 1}
 
@@ -117,6 +118,10 @@ def lib():
         L.km_batch_class_info.argtypes = [P, I32] + [ctypes.POINTER(I32)] * 4
         L.km_batch_set_class_schedule.restype = I32
         L.km_batch_set_class_schedule.argtypes = [P, I32, I32]
+        L.km_batch_use_persistent.restype = I32
+        L.km_batch_use_persistent.argtypes = [P, I32]
+        L.km_batch_persistent_status.restype = I32
+        L.km_batch_persistent_status.argtypes = [P, ctypes.POINTER(I32)]
         L.kmeans_assign_metric.restype = I32
         L.kmeans_assign_metric.argtypes = [P, P, I32, I32, P, P, P, P, P]
         _lib = L
@@ -330,6 +335,18 @@ class Batch:
 
     def use_graphs(self, enable: bool = True):
         _check(lib().km_batch_use_graphs(self._h, int(bool(enable))))
+
+    def use_persistent(self, enable: bool = True):
+        """km_batch_use_persistent, then a workspace of the new size is bound."""
+        _check(lib().km_batch_use_persistent(self._h, int(bool(enable))))
+        self._bind()
+
+    def persistent_aborted(self) -> bool:
+        """km_batch_persistent_status (synchronous): whether a wait of the last
+        persistent launch exceeded its bound."""
+        v = ctypes.c_int32(0)
+        _check(lib().km_batch_persistent_status(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def classes(self):
         """[(d8, lds_bytes, instances, tiles_per_block)] of the shape classes."""

@@ -105,6 +105,14 @@ struct km_batch {
     hipStream_t side[kSide] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
     unsigned char* ws = nullptr;
+    // persistent FP32 mode: one launch per kPersistIters iterations
+    bool persistent = false;
+    std::vector<size_t> off_ring;          // per instance: kPersistIters + 1 padded centroid buffers
+    std::vector<int64_t> ring_stride;      // floats between buffers
+    std::vector<BatchWork> pwork;          // every work row, decreasing work
+    size_t off_pring = 0, off_pstride = 0, off_pnsl = 0, off_pdone = 0, off_pready = 0, off_pctrl = 0, off_pwork = 0;
+    size_t p_lds = 0;
+    int p_grid = 1;
     // graph
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -313,6 +321,33 @@ void layout(km_batch* B)
         B->off_rwork = off; off = al256(off + B->rwork.size() * sizeof(BatchWork));
         B->off_xwork = off; off = al256(off + B->xwork.size() * sizeof(BatchWork));
     }
+    if (B->persistent) {
+        // the queue's rows: every class's, by decreasing work (t1 - t0) k d
+        B->pwork = B->work;
+        std::stable_sort(B->pwork.begin(), B->pwork.end(), [&](const BatchWork& a, const BatchWork& b) {
+            const km_instance& xa = B->inst[a.inst];
+            const km_instance& xb = B->inst[b.inst];
+            return (double)(a.t1 - a.t0) * xa.k * xa.d > (double)(b.t1 - b.t0) * xb.k * xb.d;
+        });
+        B->off_ring.assign(m, 0);
+        B->ring_stride.assign(m, 0);
+        B->p_lds = 0;
+        for (int i = 0; i < m; ++i) {
+            const km_instance& x = B->inst[i];
+            const size_t one = al256((size_t)x.k * 8 * d8_of(x.d) * sizeof(float));
+            B->ring_stride[i] = (int64_t)(one / sizeof(float));
+            B->off_ring[i] = off;
+            off = al256(off + one * (kPersistIters + 1));
+            B->p_lds = std::max(B->p_lds, plain_lds_bytes(x.k, x.d, MODE_FUSED));
+        }
+        B->off_pring = off;  off = al256(off + (size_t)m * sizeof(float*));
+        B->off_pstride = off; off = al256(off + (size_t)m * sizeof(int64_t));
+        B->off_pnsl = off;   off = al256(off + (size_t)m * sizeof(int32_t));
+        B->off_pdone = off;  off = al256(off + (size_t)m * sizeof(int32_t));
+        B->off_pready = off; off = al256(off + (size_t)m * sizeof(int32_t));
+        B->off_pctrl = off;  off = al256(off + sizeof(PersistCtrl));
+        B->off_pwork = off;  off = al256(off + B->pwork.size() * sizeof(BatchWork));
+    }
     B->off_wide.assign(B->wide.size(), 0);
     for (size_t w = 0; w < B->wide.size(); ++w) {
         B->off_wide[w] = off;
@@ -425,6 +460,21 @@ km_status upload(km_batch* B)
          (e = h2d(ws + B->off_xwork, B->xwork.data(), B->xwork.size() * sizeof(BatchWork),
                         hipMemcpyHostToDevice)) != hipSuccess))
         return bhip(e, "hipMemcpy(batch mixed tables)");
+    if (B->persistent) {
+        std::vector<float*> ring(m);
+        std::vector<int32_t> nsl(m);
+        for (int i = 0; i < m; ++i) {
+            ring[i] = reinterpret_cast<float*>(ws + B->off_ring[i]);
+            nsl[i] = B->nslots[i];
+        }
+        if ((e = h2d(ws + B->off_pring, ring.data(), ring.size() * sizeof(float*), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = h2d(ws + B->off_pstride, B->ring_stride.data(), B->ring_stride.size() * sizeof(int64_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = h2d(ws + B->off_pnsl, nsl.data(), nsl.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = h2d(ws + B->off_pwork, B->pwork.data(), B->pwork.size() * sizeof(BatchWork),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+            return bhip(e, "hipMemcpy(persistent tables)");
+    }
     return KM_OK;
 }
 
@@ -456,6 +506,28 @@ km_status enqueue_batch(km_batch* B, int32_t iters, hipStream_t s)
         return KM_OK;
     };
     if (m == 0) return join_wide();
+    if (B->persistent) {
+        PersistArgs p;
+        p.work = reinterpret_cast<const BatchWork*>(ws + B->off_pwork);
+        p.nwork = (int32_t)B->pwork.size();
+        p.insts = pa;
+        p.fins = fa;
+        p.ring = reinterpret_cast<float* const*>(ws + B->off_pring);
+        p.ring_stride = reinterpret_cast<const int64_t*>(ws + B->off_pstride);
+        p.nslots = reinterpret_cast<const int32_t*>(ws + B->off_pnsl);
+        p.done = reinterpret_cast<int32_t*>(B->ws + B->off_pdone);
+        p.ready = reinterpret_cast<int32_t*>(B->ws + B->off_pready);
+        p.ctrl = reinterpret_cast<PersistCtrl*>(B->ws + B->off_pctrl);
+        p.spin_limit = (int64_t)1 << 24;
+        for (int32_t t0 = 0; t0 < iters; t0 += kPersistIters) {
+            p.it0 = t0;
+            p.iters = std::min(kPersistIters, iters - t0);
+            if ((e = launch_persist_reset(p, m, s)) != hipSuccess) return bhip(e, "persistent reset launch");
+            if ((e = launch_batch_persistent(p, B->p_grid, B->p_lds, s)) != hipSuccess)
+                return bhip(e, "persistent launch");
+        }
+        return join_wide();
+    }
     if ((e = launch_batch_pad(fa, nullptr, m, s)) != hipSuccess) return bhip(e, "batch pad launch");
     const BatchMix* bm = reinterpret_cast<const BatchMix*>(ws + B->off_bm);
     const BatchWork* mwork = reinterpret_cast<const BatchWork*>(ws + B->off_mwork);
@@ -651,6 +723,50 @@ km_status km_batch_set_class_schedule(km_batch* batch, int32_t cls, int32_t tile
     batch->drop_graph();
     batch->ws = nullptr;   // layout changes: a workspace must be bound again
     layout(batch);
+    return KM_OK;
+}
+
+km_status km_batch_use_persistent(km_batch* batch, int32_t enable)
+{
+    km_set_error(KM_OK, "");
+    if (!batch) return berr(KM_EINVAL, "batch is NULL");
+    if (enable) {
+        if (batch->mixed || batch->inst.empty() && batch->wide.empty())
+            return berr(KM_ENOTSUP, "the persistent launch runs FP32 batches");
+        for (const km_instance& x : batch->inst)
+            if (d8_of(x.d) > 8) return berr(KM_ENOTSUP, "the persistent launch takes instances of d <= 64");
+        if (!batch->wplan.empty() && batch->inst.empty())
+            return berr(KM_ENOTSUP, "the persistent launch needs instances of d <= 64");
+    }
+    batch->persistent = enable != 0;
+    batch->drop_graph();
+    batch->ws = nullptr;   // layout changes: a workspace must be bound again
+    layout(batch);
+    if (batch->persistent) {
+        const int per_cu = persistent_blocks_per_cu(batch->p_lds);
+        if (per_cu < 1) {
+            batch->persistent = false;
+            layout(batch);
+            return berr(KM_EHIP, "occupancy query for the persistent launch failed");
+        }
+        int ncu = 0;
+        hipError_t e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, batch->device);
+        if (e != hipSuccess) return bhip(e, "hipDeviceGetAttribute");
+        batch->p_grid = std::max(1, ncu * per_cu);
+    }
+    return KM_OK;
+}
+
+km_status km_batch_persistent_status(km_batch* batch, int32_t* aborted)
+{
+    km_set_error(KM_OK, "");
+    if (!batch || !aborted) return berr(KM_EINVAL, "batch and aborted must be non-NULL");
+    *aborted = 0;
+    if (!batch->persistent || !batch->ws) return KM_OK;
+    PersistCtrl c;
+    hipError_t e = hipMemcpy(&c, batch->ws + batch->off_pctrl, sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bhip(e, "hipMemcpy(persistent control)");
+    *aborted = c.abort;
     return KM_OK;
 }
 

@@ -117,6 +117,41 @@ hipError_t launch_batch_pass(int D8, Mode mode, const BatchWork* work, int nwork
 // instance) forms the objective.  batch_pad pads the instances' centroids at
 // the start of a call.
 struct BatchFinWork { int32_t inst; int32_t chunk; };
+
+// Persistent batched FP32 Lloyd (one launch for up to kPersistIters
+// iterations of every instance).  Resident blocks take items (iteration u,
+// work row w) from a queue in iteration-major order; a block runs the fused
+// pass of its item once the item's instance has published the centroids of
+// iteration u; the block that completes an instance's last item of an
+// iteration combines that instance's partial slots (finalize, same order as
+// batch_finalize_kernel) and publishes iteration u + 1.  Waits are bounded:
+// past `spin_limit` polls the launch sets `abort` and every block exits.
+constexpr int kPersistIters = 32;      // iterations per launch (centroid buffers per instance: + 1)
+struct PersistCtrl {
+    int64_t head;         // next queue index
+    int32_t abort;        // a wait exceeded its bound
+    int32_t pad[13];
+};
+struct PersistArgs {
+    const BatchWork* work;    // [nwork] work rows of one iteration, every instance
+    int32_t nwork;
+    int32_t iters;            // iterations of this launch
+    int32_t it0;              // iteration index of the launch's first iteration
+    const PassArgs* insts;    // [m] per instance (Cp replaced by the ring below)
+    const FinArgs* fins;      // [m] per instance (C_old / Cp_out replaced by the ring)
+    float* const* ring;       // [m] base of kPersistIters + 1 padded centroid buffers
+    const int64_t* ring_stride;  // [m] floats between consecutive buffers
+    const int32_t* nslots;    // [m] partial slots (work rows) per instance per iteration
+    int32_t* done;            // [m] work rows finished in the current iteration
+    int32_t* ready;           // [m] iterations whose centroids are published
+    PersistCtrl* ctrl;
+    int64_t spin_limit;
+};
+hipError_t launch_batch_persistent(const PersistArgs& a, int grid, size_t lds, hipStream_t s);
+int persistent_blocks_per_cu(size_t lds);
+// Reset of a persistent launch (head, abort, done, ready) and the padding of
+// every instance's C into its first ring buffer.
+hipError_t launch_persist_reset(const PersistArgs& a, int ninst, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchFinWork* work, int nwork, const FinArgs* fa, int iter, hipStream_t s);
 hipError_t launch_batch_objective(const FinArgs* fa, int ninst, int iter, hipStream_t s);
 hipError_t launch_batch_pad(const FinArgs* fa, const float* const* C_in, int ninst, hipStream_t s);

@@ -776,4 +776,174 @@ hipError_t launch_plain_pass(int D8, Mode mode, const PassArgs& a, dim3 grid, si
     }
 }
 
+// ------------------------------------------------------ persistent batch
+// One block finalizes one instance: each element sums the instance's partial
+// slots in slot order (as batch_finalize_kernel), divides in FP64, rounds
+// once; wave 0 also reduces the objective partials (lane-strided, xor tree).
+__device__ __forceinline__ void persist_finalize(const FinArgs& a, const float* __restrict__ c_old, float* c_next,
+                                                 int32_t iter)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t kd = (int64_t)a.k * a.d;
+    for (int64_t e = tid; e < kd; e += kBlock) {
+        const int j = (int)(e / a.d);
+        const int f = (int)(e - (int64_t)j * a.d);
+        double S = 0.0;
+        int64_t c = 0;
+        for (int b = 0; b < a.G; ++b) {
+            S += a.part.S[(size_t)b * kd + e];
+            c += a.part.cnt[(size_t)b * a.k + j];
+        }
+        const float old = c_old[(size_t)j * a.D + f];
+        const float v = (c > 0) ? (float)(S / (double)c) : old;
+        a.C_new[(size_t)j * a.ld_new + f] = v;
+        c_next[(size_t)j * a.D + f] = v;
+        if (a.counts && f == 0) a.counts[j] = c;
+    }
+    // the padding columns of the next buffer stay zero
+    for (int64_t e = tid; e < (int64_t)a.k * a.D; e += kBlock) {
+        const int f = (int)(e % a.D);
+        if (f >= a.d) c_next[e] = 0.0f;
+    }
+    if (wave == 0) {
+        double J = 0.0;
+        for (int b = lane; b < a.GJ; b += 64) J += a.part.J[b];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) J += __shfl_xor(J, off);
+        if (lane == 0 && a.obj_hist) a.obj_hist[iter] = J;
+    }
+}
+
+template <int D8>
+__device__ __forceinline__ void persist_pass(const PassArgs& a, const BatchWork& w, unsigned char* smem)
+{
+    pass_body<D8, MODE_FUSED>(a, w.t0, w.t1, 1, w.slot, 0, smem);
+}
+
+__global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PersistArgs p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t s_q;
+    __shared__ int32_t s_flag;
+    const int tid = threadIdx.x;
+    const int64_t total = (int64_t)p.iters * p.nwork;
+    for (;;) {
+        if (tid == 0) {
+            const bool stop = __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            s_q = stop ? total : __hip_atomic_fetch_add(&p.ctrl->head, (int64_t)1, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const int64_t q = s_q;
+        if (q >= total) break;                       // queue drained (or aborted): every wave leaves
+        const int u = (int)(q / p.nwork);
+        const BatchWork w = p.work[q - (int64_t)u * p.nwork];
+        const int i = w.inst;
+        // wait until instance i has published the centroids of iteration u
+        if (tid == 0) {
+            int64_t spins = 0;
+            int ok = 1;
+            while (__hip_atomic_load(&p.ready[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < u) {
+                if (++spins > p.spin_limit ||
+                    __hip_atomic_load(&p.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (!ok) __hip_atomic_store(&p.ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = ok;
+        }
+        __syncthreads();
+        if (!s_flag) break;
+        PassArgs a = p.insts[i];
+        a.Cp = p.ring[i] + (int64_t)u * p.ring_stride[i];
+        a.iter = p.it0 + u;
+        switch ((a.d + 7) / 8) {
+        case 1: persist_pass<1>(a, w, smem); break;
+        case 2: persist_pass<2>(a, w, smem); break;
+        case 3: persist_pass<3>(a, w, smem); break;
+        case 4: persist_pass<4>(a, w, smem); break;
+        case 5: persist_pass<5>(a, w, smem); break;
+        case 6: persist_pass<6>(a, w, smem); break;
+        case 7: persist_pass<7>(a, w, smem); break;
+        default: persist_pass<8>(a, w, smem); break;
+        }
+        __threadfence();                             // every thread's part of the partial slot, then
+        __syncthreads();                             // the count (the last block of a grid pattern)
+        if (tid == 0) {
+            const int32_t old = __hip_atomic_fetch_add(&p.done[i], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = (old == p.nslots[i] - 1);
+        }
+        __syncthreads();
+        if (s_flag) {
+            // the last work row of (instance i, iteration u): finalize it
+            __threadfence();
+            const FinArgs& f = p.fins[i];
+            const float* c_old = p.ring[i] + (int64_t)u * p.ring_stride[i];
+            float* c_next = p.ring[i] + (int64_t)(u + 1) * p.ring_stride[i];
+            persist_finalize(f, c_old, c_next, p.it0 + u);
+            __threadfence();                         // the new centroids, then their publication
+            __syncthreads();
+            if (tid == 0) {
+                __hip_atomic_store(&p.done[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&p.ready[i], u + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();                             // s_q / s_flag are rewritten next round
+    }
+}
+
+// Block per instance (block 0 also resets the queue): done = ready = 0 and C
+// padded into the first ring buffer.
+__global__ __launch_bounds__(256) void persist_reset_kernel(PersistArgs p)
+{
+    const int i = blockIdx.x;
+    if (i == 0 && threadIdx.x == 0) {
+        p.ctrl->head = 0;
+        p.ctrl->abort = 0;
+    }
+    if (threadIdx.x == 0) {
+        p.done[i] = 0;
+        p.ready[i] = 0;
+    }
+    const FinArgs& f = p.fins[i];
+    float* c0 = p.ring[i];
+    const int64_t total = (int64_t)f.k * f.D;
+    for (int64_t e = threadIdx.x; e < total; e += 256) {
+        const int j = (int)(e / f.D);
+        const int fe = (int)(e - (int64_t)j * f.D);
+        c0[e] = (fe < f.d) ? f.C_new[(size_t)j * f.ld_new + fe] : 0.0f;
+    }
+}
+
+hipError_t launch_persist_reset(const PersistArgs& a, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(persist_reset_kernel, dim3(ninst), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(const PersistArgs& a, int grid, size_t lds, hipStream_t s)
+{
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_persistent_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(batch_persistent_kernel, dim3(grid), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(size_t lds)
+{
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_persistent_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -1;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_persistent_kernel, kBlock, lds) != hipSuccess) return -1;
+    return nb;
+}
+
 }  // namespace km
+

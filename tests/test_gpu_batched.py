@@ -280,6 +280,51 @@ def test_batched_optional_outputs():
             assert int(a["counts"].sum()) == shapes[i][0]
 
 
+def test_batched_persistent_launch():
+    """The persistent FP32 launch (device queue, per-instance completion
+    tickets): labels, centroids, counts and objectives equal the per-class
+    launches' at the same schedule, iteration after iteration, over more
+    iterations than one launch holds and with graph replay; stepwise valid
+    against the oracle; no wait ever reaches its bound."""
+    torch, B = _torch(), _bind()
+    shapes = [s_ for s_ in SHAPES if s_[1] <= 64]
+    iters = 40
+    inst, host = make_batch(torch, B, shapes, seed0=1000, iters=iters)
+    inst2, _ = make_batch(torch, B, shapes, seed0=1000, iters=iters)
+    ref, per = B.Batch(inst), B.Batch(inst2)
+    ref.set_schedule(4, 1)
+    per.set_schedule(4, 1)
+    per.use_persistent(True)
+    B.kmeans_lloyd_batched(ref, iters)
+    B.kmeans_lloyd_batched(per, iters)
+    torch.cuda.synchronize()
+    assert not per.persistent_aborted()
+    for i, (a, b) in enumerate(zip(inst, inst2)):
+        assert torch.equal(a["labels"], b["labels"]) and torch.equal(a["C"], b["C"]), f"instance {i}"
+        assert torch.equal(a["counts"], b["counts"]) and torch.equal(a["obj_hist"], b["obj_hist"]), f"instance {i}"
+    # stepwise against the oracle, graph-launched
+    per.use_graphs(True)
+    Cs = [t["C"].cpu().numpy() for t in inst2]
+    for t in range(2):
+        B.kmeans_lloyd_batched(per, 1)
+        torch.cuda.synchronize()
+        assert not per.persistent_aborted()
+        for i, ((X, _), ti) in enumerate(zip(host, inst2)):
+            lab = ti["labels"].cpu().numpy()
+            check_labels(lab, Cs[i], X, f"persistent instance {i} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(ti["counts"].cpu().numpy(), cnto)
+            Cg = ti["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"persistent instance {i} t={t}")
+            Cs[i] = Cg
+    with pytest.raises(B.KMeansError) as e:
+        B.Batch(make_batch(torch, B, [(500, 16, 4)], seed0=1)[0], precision="bf16").use_persistent(True)
+    assert e.value.status == B.KM_ENOTSUP
+    with pytest.raises(B.KMeansError) as e:
+        B.Batch(make_batch(torch, B, [(500, 100, 4)], seed0=1)[0]).use_persistent(True)
+    assert e.value.status == B.KM_ENOTSUP
+
+
 def test_batched_rejects_bad_instances():
     torch, B = _torch(), _bind()
     dev = torch.device("cuda")
