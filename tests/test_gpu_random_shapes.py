@@ -68,3 +68,54 @@ def test_random_shape_stepwise(n, d, k, prec, seed):
             assert torch.equal(labr, lab), f"{prec} labels differ from the FP32 plan's, t={t}"
             assert torch.equal(Cr, Cg), f"{prec} centroids differ from the FP32 plan's, t={t}"
         C = Cn
+
+
+def _batch_shapes(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        d = int(round(math.exp(rng.uniform(0.0, math.log(300.0)))))
+        k = int(round(math.exp(rng.uniform(0.0, math.log(200.0)))))
+        n = max(k, int(round(math.exp(rng.uniform(math.log(max(k, 2)), math.log(20000.0))))))
+        if n * k * d > 4e7 or k * min(d, 128) * 8 > 80 * 1024:
+            continue
+        out.append((n, d, k))
+    return out
+
+
+@pytest.mark.parametrize("prec,persistent", [("fp32", False), ("bf16", False), ("fp8", False), ("fp32", True)])
+def test_random_batch_stepwise(prec, persistent):
+    """A seeded random mix of instances (d up to 300: narrow shape classes and
+    wide instances; FP8 batches through per-instance plans; the persistent
+    FP32 launch over instances of d <= 64), two iterations, every instance
+    checked against the oracle after each."""
+    torch, B = _torch(), _bind()
+    shapes = _batch_shapes(20, 31 + len(prec) + persistent)
+    if persistent:
+        shapes = [s_ for s_ in shapes if s_[1] <= 64] or [(1000, 16, 5)]
+    say(f"random batch {prec} persistent={persistent}: {shapes}")
+    dev = torch.device("cuda")
+    inst, host = [], []
+    for i, (n, d, k) in enumerate(shapes):
+        X, C = datagen.blobs(n, d, k, max(1, min(k, 32)), 1.0, 5000 + i)
+        host.append((X, C))
+        inst.append({"X": torch.from_numpy(X).to(dev), "C": torch.from_numpy(C).to(dev),
+                     "labels": torch.empty(n, dtype=torch.int32, device=dev),
+                     "counts": torch.empty(k, dtype=torch.int64, device=dev)})
+    batch = B.Batch(inst, precision=prec)
+    if persistent:
+        batch.use_persistent(True)
+    Cs = [C.copy() for _, C in host]
+    for t in range(2):
+        B.kmeans_lloyd_batched(batch, 1)
+        torch.cuda.synchronize()
+        if persistent:
+            assert not batch.persistent_aborted()
+        for i, ((X, _), ti) in enumerate(zip(host, inst)):
+            lab = ti["labels"].cpu().numpy()
+            check_labels(lab, Cs[i], X, f"{prec} batch instance {i} {X.shape} t={t}")
+            Co, cnto = oracle.update(X, lab, Cs[i].astype(np.float64))
+            assert np.array_equal(ti["counts"].cpu().numpy(), cnto), f"instance {i} counts t={t}"
+            Cg = ti["C"].cpu().numpy()
+            check_centroids(Cg, Co, X, f"{prec} batch instance {i} t={t}")
+            Cs[i] = Cg
