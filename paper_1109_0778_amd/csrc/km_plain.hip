@@ -607,9 +607,107 @@ size_t part_update_lds_bytes(int kc, int d)
            2 * kWaves * kPartStep * sizeof(int32_t);
 }
 
+// The same partition with four waves per sub-range (1024 samples each): the
+// waves count their chunks separately, one wave forms the block's chunk
+// offsets and each wave's cursors (wave w's samples follow waves 0..w-1's in
+// every chunk), so the permutation is the one-wave kernel's exactly.
+constexpr int kPartWaves = 4;
+__global__ __launch_bounds__(64 * kPartWaves) void partition4_kernel(const int32_t* __restrict__ labels, int64_t n,
+                                                                     int32_t k, int32_t kc, int32_t nch,
+                                                                     int32_t* perm, int32_t* plab, int32_t* poff,
+                                                                     int32_t* pcnt, const Ctrl* ctrl, int32_t iter)
+{
+    constexpr int G = kPartRows / (64 * kPartWaves);      // 64-sample groups per wave
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (ctrl != nullptr && ctrl->stop_iter < iter) return;  // converged earlier
+    int32_t* cntw = reinterpret_cast<int32_t*>(smem);    // [kPartWaves][nch]: counts, then cursors
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kPartRows;
+    const int64_t end = base + kPartRows < n ? base + kPartRows : n;
+    const int64_t wbase = base + (int64_t)wave * 64 * G;
+    for (int c = tid; c < kPartWaves * nch; c += 64 * kPartWaves) cntw[c] = 0;
+    int lb[G], ch[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t i = wbase + g * 64 + lane;
+        lb[g] = i < end ? labels[i] : -1;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) ch[g] = (lb[g] >= 0 && lb[g] < k) ? lb[g] / kc : -1;
+    __syncthreads();
+    int32_t* mine = cntw + wave * nch;
+    const int nbits = nch > 1 ? 32 - __builtin_clz((unsigned)(nch - 1)) : 0;
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int c = ch[g];
+        uint64_t same = __ballot(c >= 0);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (c >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            same &= bit ? m : ~m;
+        }
+        const int rank = (int)__popcll(same & lt), num = (int)__popcll(same);
+        if (c >= 0) {
+            if (rank == 0) __hip_atomic_fetch_add(mine + c, num, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            ch[g] = c | (rank << 16) | (num << 23);
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int carry = 0;
+        for (int c0 = 0; c0 < nch; c0 += 64) {
+            const int c = c0 + lane;
+            int per[kPartWaves];
+            int v = 0;
+#pragma unroll
+            for (int w = 0; w < kPartWaves; ++w) {
+                per[w] = c < nch ? cntw[w * nch + c] : 0;
+                v += per[w];
+            }
+            int incl = v;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int o = __shfl_up(incl, off);
+                if (lane >= off) incl += o;
+            }
+            if (c < nch) {
+                const int start = (int)base + carry + incl - v;
+                poff[(int64_t)blockIdx.x * nch + c] = start;
+                pcnt[(int64_t)blockIdx.x * nch + c] = v;
+                int at = start;
+#pragma unroll
+                for (int w = 0; w < kPartWaves; ++w) {
+                    cntw[w * nch + c] = at;
+                    at += per[w];
+                }
+            }
+            carry += __shfl(incl, 63);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int c = ch[g] >= 0 ? (ch[g] & 0xffff) : -1;
+        const int rank = (ch[g] >> 16) & 127, num = ch[g] >> 23;
+        const int at = c >= 0 ? mine[c] : 0;
+        if (c >= 0) {
+            perm[at + rank] = (int32_t)(wbase + g * 64 + lane);
+            plab[at + rank] = lb[g];
+            if (rank == 0) mine[c] = at + num;
+        }
+    }
+}
+
 hipError_t launch_partition(const PassArgs& a, int32_t* perm, int32_t* plab, int32_t* poff, int32_t* pcnt,
                             hipStream_t s)
 {
+    const size_t lds4 = (size_t)kPartWaves * a.nch * sizeof(int32_t);
+    if (lds4 <= 64 * 1024) {
+        hipLaunchKernelGGL(partition4_kernel, dim3(a.nsub), dim3(64 * kPartWaves), lds4, s, a.labels, a.n, a.k, a.kc,
+                           a.nch, perm, plab, poff, pcnt, a.ctrl, a.iter);
+        return hipGetLastError();
+    }
     const size_t lds = 2 * (size_t)a.nch * sizeof(int32_t);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&partition_kernel),
