@@ -153,6 +153,32 @@ def test_update_parity(n, d, k):
     assert np.all(np.abs(Cn.astype(np.float64) - Co) <= ulp + 1e-300)
 
 
+@pytest.mark.parametrize("k", [176128, 180000])
+def test_update_many_label_chunks(k):
+    """Records far above LDS size: the update partitions each 4096-sample
+    sub-range by label chunk (43 labels of d = 128 per chunk).  k = 176128
+    gives 4096 chunks, the most the four-wave partition's per-wave counts
+    fit in 64 KiB; k = 180000 gives 4187 chunks, which take the one-wave
+    partition.  Random labels leave about a third of the clusters empty."""
+    torch, B = _torch(), _bind()
+    n, d = 200000, 128
+    nch = -(-k // ((44 * 1024) // (8 * d + 4)))
+    assert (nch <= 4096) == (k == 176128)
+    say(f"update n={n} d={d} k={k} ({nch} label chunks)")
+    rng = np.random.default_rng(k)
+    X = (3.0 * rng.standard_normal((n, d))).astype(np.float32)
+    C = rng.standard_normal((k, d)).astype(np.float32)
+    labels = rng.integers(0, k, n).astype(np.int32)
+    Cn, cnt = run_update(torch, B, X, labels, C)
+    Co, cnto = oracle.update(X, labels, C.astype(np.float64))
+    assert np.array_equal(cnt, cnto)
+    empty = cnto == 0
+    assert empty.sum() > k // 4
+    assert np.array_equal(Cn[empty], C[empty])
+    ulp = np.spacing(np.abs(Co).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(Cn.astype(np.float64) - Co) <= ulp + 1e-300)
+
+
 def test_small_workload_end_to_end():
     """The small workload (n=4096, d=8, k=8, 10 iterations, init = first k
     points) end to end against the oracle's own trajectory."""
