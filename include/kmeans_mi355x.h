@@ -75,7 +75,7 @@ extern "C" {
 typedef enum {
     KM_OK = 0,
     KM_EINVAL = -1,      /* bad shape, null or misaligned pointer, bad value */
-    KM_ENOTSUP = -2,     /* valid request this build does not implement      */
+    KM_ENOTSUP = -2,     /* valid request the library does not implement     */
     KM_EHIP = -3,        /* a HIP runtime call failed (message has the text) */
     KM_EWORKSPACE = -4   /* no workspace bound, or it is too small           */
 } km_status;
