@@ -767,10 +767,17 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         }                                                                                 \
         if ((hf_) == 0 && tid < kMixCK) bbuf[(buf_) * kMixCK + tid] = pb;                \
     }
+    // Two chunks (65 to 128 centroids) stay in the two buffers for the whole
+    // block: no reload per tile and no barrier between chunks.
+    const bool res2 = !WIDE && nchunks == 2;
     int cur = 0;
     if (t_first < t_last) {
         KM_LOAD_CHUNK(0)
         KM_STORE_CHUNK(0)
+        if (res2) {
+            KM_LOAD_CHUNK(1)
+            KM_STORE_CHUNK(1)
+        }
     }
     __syncthreads();
 
@@ -873,10 +880,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         // --- sweep over the centroids; the next chunk (possibly chunk 0 of the
         // next tile) is fetched into registers while this one is computed
         for (int c = 0; c < nchunks; ++c) {
-            const bool pref = nchunks > 1 && (c + 1 < nchunks || t + t_step < t_last);
+            const bool pref = !res2 && nchunks > 1 && (c + 1 < nchunks || t + t_step < t_last);
             const int cnext = c + 1 < nchunks ? c + 1 : 0;
-            const unsigned char* Ab_c = Abuf + cur * CHB;
-            const float* bb_c = bbuf + cur * kMixCK;
+            const int buf = res2 ? c : cur;
+            const unsigned char* Ab_c = Abuf + buf * CHB;
+            const float* bb_c = bbuf + buf * kMixCK;
             // screen: the two smallest keys of this chunk, indexed within the
             // chunk (compile-time constants); chunk base and lane offset are
             // added when the pair joins the running one
