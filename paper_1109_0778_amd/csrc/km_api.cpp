@@ -297,6 +297,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.amb_key = f8 ? nullptr : reinterpret_cast<uint32_t*>(ws + p->off_ambk);
     m.amb_key_in = nullptr;
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
+    m.nbuf = mix_buffers(p->fmt, p->D16, p->kpad);
     // BF16 operands (the FP8 plan's own copy); an FP8 screen's open samples
     // get a BF16 screen of their own (mb), whose keys the refine then shares
     MixArgs mb = m;
@@ -309,6 +310,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
         mb.Xb = reinterpret_cast<const __bf16*>(ws + p->off_xb);
         mb.xn = reinterpret_cast<const float*>(ws + p->off_xn);
         mb.u = 0.00390625f;
+        mb.nbuf = mix_buffers(FMT_BF16, p->D16, p->kpad);
         mb.amb_in = m.amb;
         mb.amb_in_count = m.amb_count;
         mb.amb = reinterpret_cast<int32_t*>(ws + p->off_amb2);
@@ -487,13 +489,15 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         p->IB = 1;
         while ((1 << p->IB) < p->kpad) ++p->IB;
         p->cascade = p->fmt == FMT_FP8 || p->kpad > 2 * kMixCK;
-        const int occ = p->cascade ? mfma_blocks_per_cu(p->fmt, 1, p->D16) : mfma_blocks_per_cu(FMT_BF16, 0, p->D16);
+        const int nbf = mix_buffers(FMT_BF16, p->D16, p->kpad);
+        const int occ = p->cascade ? mfma_blocks_per_cu(p->fmt, 1, p->D16, mix_buffers(p->fmt, p->D16, p->kpad))
+                                   : mfma_blocks_per_cu(FMT_BF16, 0, p->D16, nbf);
         if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
         p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
-        if (p->cascade && (mfma_blocks_per_cu(FMT_BF16, 3, p->D16) < 1 ||
-                           (p->fmt == FMT_FP8 && mfma_blocks_per_cu(FMT_BF16, 2, p->D16) < 1))) {
+        if (p->cascade && (mfma_blocks_per_cu(FMT_BF16, 3, p->D16, nbf) < 1 ||
+                           (p->fmt == FMT_FP8 && mfma_blocks_per_cu(FMT_BF16, 2, p->D16, nbf) < 1))) {
             delete p;
             return fail(KM_EHIP, "occupancy query for the refining MFMA pass failed");
         }

@@ -310,6 +310,8 @@ struct MixArgs {
     const Ctrl* ctrl;
     int32_t iter;
     int32_t count_changed;
+    int32_t nbuf;               // LDS centroid chunk buffers: 0 or 2 stream the chunks through two
+                                // buffers; the chunk count keeps every chunk for the whole block
 };
 
 struct RecheckArgs {
@@ -350,8 +352,14 @@ hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t
 // of the screen's smallest key, recheck queue); stage 0 (the one-pass sweep
 // with running candidate lists) serves short sweeps and the batched path.
 hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s);
-size_t mfma_lds_bytes(int fmt, int D16, int stage);
-int mfma_blocks_per_cu(int fmt, int stage, int D16);
+// Chunk buffers for a plan's MFMA passes: every chunk when there are at
+// least three and they fit in kMixResidentBytes, else two.  The bound keeps
+// a refine block (operands + candidate lists) under 40 KiB, so the four
+// blocks per CU the plans launch stay resident together.
+constexpr int kMixResidentBytes = 24 * 1024;
+int mix_buffers(int fmt, int D16, int kpad);
+size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf = 2);
+int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf = 2);
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
 
 // Batched mixed path: one record per instance.  The per-iteration prep and

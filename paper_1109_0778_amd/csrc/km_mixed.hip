@@ -675,9 +675,11 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     constexpr int SLOTS = kCandSlots;
     constexpr int RQI = kRqInts;
     constexpr int PF = WIDE ? 1 : (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
-    unsigned char* Abuf = smem;                                                   // [2][CK][ROWB]
-    float* bbuf = reinterpret_cast<float*>(smem + 2 * CHB);                       // [2][CK]
-    uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + 2 * kMixCK);              // [waves][NB][SLOTS][64]
+    // centroid chunk buffers: two, or one per chunk (a.nbuf, sized by the host)
+    const int nbuf = !WIDE && a.nbuf > 2 ? a.nbuf : 2;
+    unsigned char* Abuf = smem;                                                   // [nbuf][CK][ROWB]
+    float* bbuf = reinterpret_cast<float*>(smem + (size_t)nbuf * CHB);            // [nbuf][CK]
+    uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + nbuf * kMixCK);           // [waves][NB][SLOTS][64]
     __shared__ int32_t sred[kMixWaves];
     __shared__ int32_t blk_count;           // recheck entries queued by this block
     __shared__ int32_t blk_full;            // ... of which full scans (candidate list overflowed)
@@ -767,16 +769,19 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         }                                                                                 \
         if ((hf_) == 0 && tid < kMixCK) bbuf[(buf_) * kMixCK + tid] = pb;                \
     }
-    // Two chunks (65 to 128 centroids) stay in the two buffers for the whole
-    // block: no reload per tile and no barrier between chunks.
-    const bool res2 = !WIDE && nchunks == 2;
+    // With a buffer per chunk (two chunks, or more that the host sized the
+    // buffers for) every chunk stays in LDS for the whole block: no reload per
+    // tile and no barrier between chunks.
+    const bool resident = !WIDE && nchunks >= 2 && nchunks == nbuf;
     int cur = 0;
     if (t_first < t_last) {
         KM_LOAD_CHUNK(0)
         KM_STORE_CHUNK(0)
-        if (res2) {
-            KM_LOAD_CHUNK(1)
-            KM_STORE_CHUNK(1)
+        if (resident) {
+            for (int c = 1; c < nchunks; ++c) {
+                KM_LOAD_CHUNK(c)
+                KM_STORE_CHUNK(c)
+            }
         }
     }
     __syncthreads();
@@ -880,9 +885,9 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         // --- sweep over the centroids; the next chunk (possibly chunk 0 of the
         // next tile) is fetched into registers while this one is computed
         for (int c = 0; c < nchunks; ++c) {
-            const bool pref = !res2 && nchunks > 1 && (c + 1 < nchunks || t + t_step < t_last);
+            const bool pref = !resident && nchunks > 1 && (c + 1 < nchunks || t + t_step < t_last);
             const int cnext = c + 1 < nchunks ? c + 1 : 0;
-            const int buf = res2 ? c : cur;
+            const int buf = resident ? c : cur;
             const unsigned char* Ab_c = Abuf + buf * CHB;
             const float* bb_c = bbuf + buf * kMixCK;
             // screen: the two smallest keys of this chunk, indexed within the
@@ -1451,18 +1456,27 @@ hipError_t launch_prep_c(int fmt, const float* Cp, int32_t k, int32_t d, int32_t
     return hipGetLastError();
 }
 
-size_t mfma_lds_bytes(int fmt, int D16, int stage)
+static size_t mix_row_bytes(int fmt, int D16) { return (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16; }
+
+int mix_buffers(int fmt, int D16, int kpad)
+{
+    const int nch = kpad / kMixCK;
+    if (D16 <= 0 || nch < 3) return 2;
+    return (size_t)nch * kMixCK * mix_row_bytes(fmt, D16) <= (size_t)kMixResidentBytes ? nch : 2;
+}
+
+size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf)
 {
     // (D16 = 0, rows of more than 128 features: the centroid operands are not staged)
-    const size_t rowb = (size_t)D16 * 16 * (fmt == FMT_FP8 ? 1 : 2) + 16;
-    return 2 * kMixCK * rowb + 2 * kMixCK * sizeof(float) +
+    const size_t nb = (size_t)(D16 > 0 && nbuf > 2 ? nbuf : 2);
+    return nb * kMixCK * mix_row_bytes(fmt, D16) + nb * kMixCK * sizeof(float) +
            (stage == 1 || stage == 2 ? 0 : (size_t)kMixWaves * mix_nb(stage) * kCandSlots * 64 * sizeof(uint32_t));
 }
 
 template <int D16, int FMT, int STAGE>
 static hipError_t launch_mfma_d16(const MixArgs& a, int grid, hipStream_t s)
 {
-    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE);
+    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE, a.nbuf);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1502,9 +1516,9 @@ hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int
 }
 
 template <int D16, int FMT, int STAGE>
-static int occ_mfma()
+static int occ_mfma(int nbuf)
 {
-    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE);
+    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE, nbuf);
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -1517,27 +1531,27 @@ static int occ_mfma()
 }
 
 template <int FMT, int STAGE>
-static int occ_mfma_fs(int D16)
+static int occ_mfma_fs(int D16, int nbuf)
 {
     switch (D16) {
-    case 1: return occ_mfma<1, FMT, STAGE>();
-    case 2: return occ_mfma<2, FMT, STAGE>();
-    case 3: return occ_mfma<3, FMT, STAGE>();
-    case 4: return occ_mfma<4, FMT, STAGE>();
-    case 5: return occ_mfma<5, FMT, STAGE>();
-    case 6: return occ_mfma<6, FMT, STAGE>();
-    case 7: return occ_mfma<7, FMT, STAGE>();
-    case 8: return occ_mfma<8, FMT, STAGE>();
-    default: return D16 <= kMaxD16Wide ? occ_mfma<0, FMT, STAGE>() : -1;
+    case 1: return occ_mfma<1, FMT, STAGE>(nbuf);
+    case 2: return occ_mfma<2, FMT, STAGE>(nbuf);
+    case 3: return occ_mfma<3, FMT, STAGE>(nbuf);
+    case 4: return occ_mfma<4, FMT, STAGE>(nbuf);
+    case 5: return occ_mfma<5, FMT, STAGE>(nbuf);
+    case 6: return occ_mfma<6, FMT, STAGE>(nbuf);
+    case 7: return occ_mfma<7, FMT, STAGE>(nbuf);
+    case 8: return occ_mfma<8, FMT, STAGE>(nbuf);
+    default: return D16 <= kMaxD16Wide ? occ_mfma<0, FMT, STAGE>(nbuf) : -1;
     }
 }
 
-int mfma_blocks_per_cu(int fmt, int stage, int D16)
+int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf)
 {
-    if (stage == 1) return fmt == FMT_FP8 ? occ_mfma_fs<FMT_FP8, 1>(D16) : occ_mfma_fs<FMT_BF16, 1>(D16);
-    if (stage == 2 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 2>(D16);
-    if (stage == 3 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 3>(D16);
-    if (stage == 0 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 0>(D16);
+    if (stage == 1) return fmt == FMT_FP8 ? occ_mfma_fs<FMT_FP8, 1>(D16, nbuf) : occ_mfma_fs<FMT_BF16, 1>(D16, nbuf);
+    if (stage == 2 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 2>(D16, nbuf);
+    if (stage == 3 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 3>(D16, nbuf);
+    if (stage == 0 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 0>(D16, nbuf);
     return -1;
 }
 
