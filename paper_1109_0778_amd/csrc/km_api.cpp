@@ -78,6 +78,7 @@ struct km_plan {
     int D16 = 0, DP = 0, kpad = 0, IB = 0;
     int upd_tiles = 1;   // update pass: tiles listed per step
     int grid_mfma = 0, grid_rc = 0;
+    bool wide_blocks = false;   // MFMA stages 1-3 in blocks of mix_waves(stage, true) waves
     int64_t rq_per_block = 0;
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
@@ -298,6 +299,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     m.amb_key_in = nullptr;
     m.ctrl = ctrl; m.iter = iter; m.count_changed = count_changed;
     m.nbuf = mix_buffers(p->fmt, p->D16, p->kpad);
+    m.wide_blocks = p->wide_blocks ? 1 : 0;
     // BF16 operands (the FP8 plan's own copy); an FP8 screen's open samples
     // get a BF16 screen of their own (mb), whose keys the refine then shares
     MixArgs mb = m;
@@ -490,21 +492,26 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         while ((1 << p->IB) < p->kpad) ++p->IB;
         p->cascade = p->fmt == FMT_FP8 || p->kpad > 2 * kMixCK;
         const int nbf = mix_buffers(FMT_BF16, p->D16, p->kpad);
-        const int occ = p->cascade ? mfma_blocks_per_cu(p->fmt, 1, p->D16, mix_buffers(p->fmt, p->D16, p->kpad))
+        // centroid chunks that stream through LDS are reloaded for every tile:
+        // wider blocks share each load among more samples
+        p->wide_blocks = p->cascade && p->D16 <= 8 && p->kpad / kMixCK > 2 && nbf == 2;
+        const int occ = p->cascade ? mfma_blocks_per_cu(p->fmt, 1, p->D16, mix_buffers(p->fmt, p->D16, p->kpad),
+                                                        p->wide_blocks)
                                    : mfma_blocks_per_cu(FMT_BF16, 0, p->D16, nbf);
         if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
         p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
-        if (p->cascade && (mfma_blocks_per_cu(FMT_BF16, 3, p->D16, nbf) < 1 ||
-                           (p->fmt == FMT_FP8 && mfma_blocks_per_cu(FMT_BF16, 2, p->D16, nbf) < 1))) {
+        if (p->cascade && (mfma_blocks_per_cu(FMT_BF16, 3, p->D16, nbf, p->wide_blocks) < 1 ||
+                           (p->fmt == FMT_FP8 && mfma_blocks_per_cu(FMT_BF16, 2, p->D16, nbf, p->wide_blocks) < 1))) {
             delete p;
             return fail(KM_EHIP, "occupancy query for the refining MFMA pass failed");
         }
         // a block's share of samples, under the screen's tile and the others'
-        const int64_t mt1 = (n + mix_tile(1) - 1) / mix_tile(1);
+        const int tile1 = mix_tile(1, p->wide_blocks);
+        const int64_t mt1 = (n + tile1 - 1) / tile1;
         p->rq_per_block = std::max(((mt + p->grid_mfma - 1) / p->grid_mfma) * kMixTile,
-                                   ((mt1 + p->grid_mfma - 1) / p->grid_mfma) * mix_tile(1));
+                                   ((mt1 + p->grid_mfma - 1) / p->grid_mfma) * tile1);
     }
 
     size_t off = 0;

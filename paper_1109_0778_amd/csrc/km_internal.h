@@ -249,7 +249,20 @@ constexpr int kMixTile = kMixWaves * kMixNB * 32;
 // per wave: each centroid fragment read from LDS feeds two MFMAs.
 constexpr int kMixNBScreen = 2;
 __host__ __device__ constexpr int mix_nb(int stage) { return stage == 1 || stage == 2 ? kMixNBScreen : kMixNB; }
-__host__ __device__ constexpr int mix_tile(int stage) { return kMixWaves * mix_nb(stage) * 32; }
+// A plan whose centroid chunks stream through LDS (more than two, not all
+// resident) runs its screens in blocks of 12 waves and its refine in blocks of
+// 16, one block per CU, so every chunk brought into LDS serves three (four)
+// times the samples; every other MFMA pass runs blocks of kMixWaves.
+constexpr int kMixWavesScreenWide = 12;
+constexpr int kMixWavesRefineWide = 16;
+__host__ __device__ constexpr int mix_waves(int stage, bool wide_blocks)
+{
+    return !wide_blocks ? kMixWaves : stage == 3 ? kMixWavesRefineWide : (stage == 1 || stage == 2) ? kMixWavesScreenWide : kMixWaves;
+}
+__host__ __device__ constexpr int mix_tile(int stage, bool wide_blocks = false)
+{
+    return mix_waves(stage, wide_blocks) * mix_nb(stage) * 32;
+}
 constexpr int kMixCK = 64;                      // centroids per LDS chunk
 // Candidates kept per lane (half a sample's rows).  Candidate lists are only
 // built by BF16 sweeps (an FP8 plan's open samples get a BF16 screen first).
@@ -312,6 +325,7 @@ struct MixArgs {
     int32_t count_changed;
     int32_t nbuf;               // LDS centroid chunk buffers: 0 or 2 stream the chunks through two
                                 // buffers; the chunk count keeps every chunk for the whole block
+    int32_t wide_blocks;        // 1: stages 1-3 launch in blocks of mix_waves(stage, true) waves
 };
 
 struct RecheckArgs {
@@ -358,8 +372,8 @@ hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int
 // blocks per CU the plans launch stay resident together.
 constexpr int kMixResidentBytes = 24 * 1024;
 int mix_buffers(int fmt, int D16, int kpad);
-size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf = 2);
-int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf = 2);
+size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf = 2, int waves = kMixWaves);
+int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf = 2, bool wide_blocks = false);
 hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
 
 // Batched mixed path: one record per instance.  The per-iteration prep and

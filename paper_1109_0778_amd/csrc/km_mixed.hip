@@ -654,7 +654,7 @@ __device__ __forceinline__ uint32_t thr_key(uint32_t m, float W, uint32_t ibm)
 // the samples listed in a.amb_in: the smallest key, and so the band, is the
 // screen's (a.amb_key_in); the sweep lists the keys inside it and nothing
 // more.
-template <int D16, int FMT, int STAGE>
+template <int D16, int FMT, int STAGE, int NW>
 __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int64_t t_end, int64_t t_step,
                                           int region, unsigned char* smem)
 {
@@ -668,19 +668,19 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     const int DPr = WIDE ? a.DP : DP;      // operand row width
     constexpr int ROWB = DP * ES + 16;     // padded LDS row: conflict-free reads
     constexpr int NB = mix_nb(STAGE);
-    constexpr int TILE = mix_tile(STAGE);   // samples per block per tile
+    constexpr int TILE = NW * NB * 32;      // samples per block per tile
     constexpr int CHB = kMixCK * ROWB;     // bytes of one chunk buffer
     constexpr int V = DP * ES / 16;        // uint4 per centroid row
     constexpr int CAP = kCandCap;
     constexpr int SLOTS = kCandSlots;
     constexpr int RQI = kRqInts;
-    constexpr int PF = WIDE ? 1 : (kMixCK * V + 64 * kMixWaves - 1) / (64 * kMixWaves);   // prefetch uint4 per thread
+    constexpr int PF = WIDE ? 1 : (kMixCK * V + 64 * NW - 1) / (64 * NW);   // prefetch uint4 per thread
     // centroid chunk buffers: two, or one per chunk (a.nbuf, sized by the host)
     const int nbuf = !WIDE && a.nbuf > 2 ? a.nbuf : 2;
     unsigned char* Abuf = smem;                                                   // [nbuf][CK][ROWB]
     float* bbuf = reinterpret_cast<float*>(smem + (size_t)nbuf * CHB);            // [nbuf][CK]
     uint32_t* cand = reinterpret_cast<uint32_t*>(bbuf + nbuf * kMixCK);           // [waves][NB][SLOTS][64]
-    __shared__ int32_t sred[kMixWaves];
+    __shared__ int32_t sred[NW];
     __shared__ int32_t blk_count;           // recheck entries queued by this block
     __shared__ int32_t blk_full;            // ... of which full scans (candidate list overflowed)
 
@@ -721,7 +721,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
         const uint4* src_ = reinterpret_cast<const uint4*>(                               \
             static_cast<const unsigned char*>(a.Ab) + (size_t)(c_) * kMixCK * DP * ES);   \
         _Pragma("unroll") for (int i_ = 0; i_ < PF; ++i_) {                               \
-            const int e_ = tid + i_ * 64 * kMixWaves;                                     \
+            const int e_ = tid + i_ * 64 * NW;                                     \
             pr[i_] = (e_ < kMixCK * V) ? src_[e_] : make_uint4(0, 0, 0, 0);               \
         }                                                                                 \
         pb = (tid < kMixCK) ? a.bias[(size_t)(c_) * kMixCK + tid] : 0.0f;                 \
@@ -729,7 +729,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
 #define KM_STORE_CHUNK(buf_)                                                              \
     {                                                                                     \
         _Pragma("unroll") for (int i_ = 0; i_ < PF; ++i_) {                               \
-            const int e_ = tid + i_ * 64 * kMixWaves;                                     \
+            const int e_ = tid + i_ * 64 * NW;                                     \
             if (e_ < kMixCK * V) {                                                        \
                 const int row_ = e_ / V, q_ = e_ - row_ * V;                              \
                 *reinterpret_cast<uint4*>(Abuf + (buf_) * CHB + row_ * ROWB + q_ * 16) = pr[i_]; \
@@ -752,7 +752,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
             static_cast<const unsigned char*>(a.Ab) + (size_t)(c_) * kMixCK * DP * ES);   \
         _Pragma("unroll") for (int i_ = 0; i_ < PFH; ++i_) {                              \
             const int q_ = (hf_) * PFH + i_;                                              \
-            const int e_ = tid + q_ * 64 * kMixWaves;                                     \
+            const int e_ = tid + q_ * 64 * NW;                                     \
             prh[i_] = (q_ < PF && e_ < kMixCK * V) ? src_[e_] : make_uint4(0, 0, 0, 0);   \
         }                                                                                 \
         if ((hf_) == 0) pb = (tid < kMixCK) ? a.bias[(size_t)(c_) * kMixCK + tid] : 0.0f; \
@@ -761,7 +761,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     {                                                                                     \
         _Pragma("unroll") for (int i_ = 0; i_ < PFH; ++i_) {                              \
             const int q_ = (hf_) * PFH + i_;                                              \
-            const int e_ = tid + q_ * 64 * kMixWaves;                                     \
+            const int e_ = tid + q_ * 64 * NW;                                     \
             if (q_ < PF && e_ < kMixCK * V) {                                             \
                 const int row_ = e_ / V, qq_ = e_ - row_ * V;                             \
                 *reinterpret_cast<uint4*>(Abuf + (buf_) * CHB + row_ * ROWB + qq_ * 16) = prh[i_]; \
@@ -1203,7 +1203,7 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
     __syncthreads();
     if (tid == 0) {
         int32_t c = 0;
-        for (int w = 0; w < kMixWaves; ++w) c += sred[w];
+        for (int w = 0; w < NW; ++w) c += sred[w];
         a.changed_part[region] = c;
         if constexpr (SCREEN) {
             a.amb_count[region] = blk_count;
@@ -1217,15 +1217,15 @@ __device__ __forceinline__ void mfma_body(const MixArgs& a, int64_t t_first, int
 // The screen is built for three resident waves per SIMD (its 64 samples per
 // wave hold 64 VGPRs of operands for the whole sweep); the refine after a
 // BF16 screen fits four (128 VGPRs at 128 features).
-template <int D16, int FMT, int STAGE>
-__global__ __launch_bounds__(64 * kMixWaves) __attribute__((amdgpu_waves_per_eu(STAGE == 1 || STAGE == 2 ? 3 : STAGE == 3 ? 4 : 1)))
+template <int D16, int FMT, int STAGE, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(STAGE == 1 || STAGE == 2 ? 3 : STAGE == 3 ? 4 : 1)))
 void mfma_assign(MixArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     if constexpr (STAGE >= 2)
-        mfma_body<D16, FMT, STAGE>(a, 0, INT64_MAX, 1, blockIdx.x, smem);   // block b takes region b's list
+        mfma_body<D16, FMT, STAGE, NW>(a, 0, INT64_MAX, 1, blockIdx.x, smem);   // block b takes region b's list
     else
-        mfma_body<D16, FMT, STAGE>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
+        mfma_body<D16, FMT, STAGE, NW>(a, blockIdx.x, INT64_MAX, gridDim.x, blockIdx.x, smem);
 }
 
 // Batched instances (BF16): row b of the work table runs tiles [t0, t1) of
@@ -1238,7 +1238,7 @@ __global__ __launch_bounds__(64 * kMixWaves) void batch_mfma(const BatchWork* __
     const BatchWork w = work[blockIdx.x];
     MixArgs a = bm[w.inst].m;
     a.iter = iter;
-    mfma_body<D16, FMT_BF16, 0>(a, w.t0, w.t1, 1, w.slot, smem);
+    mfma_body<D16, FMT_BF16, 0, kMixWaves>(a, w.t0, w.t1, 1, w.slot, smem);
 }
 
 // ------------------------------------------------------------ exact recheck
@@ -1465,41 +1465,55 @@ int mix_buffers(int fmt, int D16, int kpad)
     return (size_t)nch * kMixCK * mix_row_bytes(fmt, D16) <= (size_t)kMixResidentBytes ? nch : 2;
 }
 
-size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf)
+size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf, int waves)
 {
     // (D16 = 0, rows of more than 128 features: the centroid operands are not staged)
     const size_t nb = (size_t)(D16 > 0 && nbuf > 2 ? nbuf : 2);
     return nb * kMixCK * mix_row_bytes(fmt, D16) + nb * kMixCK * sizeof(float) +
-           (stage == 1 || stage == 2 ? 0 : (size_t)kMixWaves * mix_nb(stage) * kCandSlots * 64 * sizeof(uint32_t));
+           (stage == 1 || stage == 2 ? 0 : (size_t)waves * mix_nb(stage) * kCandSlots * 64 * sizeof(uint32_t));
 }
 
-template <int D16, int FMT, int STAGE>
+template <int D16, int FMT, int STAGE, int NW>
 static hipError_t launch_mfma_d16(const MixArgs& a, int grid, hipStream_t s)
 {
-    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE, a.nbuf);
+    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE, a.nbuf, NW);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE, NW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((mfma_assign<D16, FMT, STAGE>), dim3(grid), dim3(64 * kMixWaves), lds, s, a);
+    hipLaunchKernelGGL((mfma_assign<D16, FMT, STAGE, NW>), dim3(grid), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
 }
 
-template <int FMT, int STAGE>
+// (blocks of more than kMixWaves waves only for rows of at most 128 features)
+template <int FMT, int STAGE, int NW>
 static hipError_t launch_mfma_fs(int D16, const MixArgs& a, int grid, hipStream_t s)
 {
     switch (D16) {
-    case 1: return launch_mfma_d16<1, FMT, STAGE>(a, grid, s);
-    case 2: return launch_mfma_d16<2, FMT, STAGE>(a, grid, s);
-    case 3: return launch_mfma_d16<3, FMT, STAGE>(a, grid, s);
-    case 4: return launch_mfma_d16<4, FMT, STAGE>(a, grid, s);
-    case 5: return launch_mfma_d16<5, FMT, STAGE>(a, grid, s);
-    case 6: return launch_mfma_d16<6, FMT, STAGE>(a, grid, s);
-    case 7: return launch_mfma_d16<7, FMT, STAGE>(a, grid, s);
-    case 8: return launch_mfma_d16<8, FMT, STAGE>(a, grid, s);
-    default: return D16 <= kMaxD16Wide ? launch_mfma_d16<0, FMT, STAGE>(a, grid, s) : hipErrorInvalidValue;
+    case 1: return launch_mfma_d16<1, FMT, STAGE, NW>(a, grid, s);
+    case 2: return launch_mfma_d16<2, FMT, STAGE, NW>(a, grid, s);
+    case 3: return launch_mfma_d16<3, FMT, STAGE, NW>(a, grid, s);
+    case 4: return launch_mfma_d16<4, FMT, STAGE, NW>(a, grid, s);
+    case 5: return launch_mfma_d16<5, FMT, STAGE, NW>(a, grid, s);
+    case 6: return launch_mfma_d16<6, FMT, STAGE, NW>(a, grid, s);
+    case 7: return launch_mfma_d16<7, FMT, STAGE, NW>(a, grid, s);
+    case 8: return launch_mfma_d16<8, FMT, STAGE, NW>(a, grid, s);
+    default:
+        if constexpr (NW == kMixWaves)
+            return D16 <= kMaxD16Wide ? launch_mfma_d16<0, FMT, STAGE, NW>(a, grid, s) : hipErrorInvalidValue;
+        else
+            return hipErrorInvalidValue;
     }
+}
+
+template <int FMT, int STAGE>
+static hipError_t launch_mfma_nw(int D16, const MixArgs& a, int grid, hipStream_t s)
+{
+    if constexpr (STAGE >= 1) {
+        if (a.wide_blocks) return launch_mfma_fs<FMT, STAGE, mix_waves(STAGE, true)>(D16, a, grid, s);
+    }
+    return launch_mfma_fs<FMT, STAGE, kMixWaves>(D16, a, grid, s);
 }
 
 // The single-instance passes: BF16 and FP8 screens (stage 1), the BF16 screen
@@ -1507,51 +1521,65 @@ static hipError_t launch_mfma_fs(int D16, const MixArgs& a, int grid, hipStream_
 // screen (stage 3), the BF16 one-pass sweep (stage 0).
 hipError_t launch_mfma_assign(int fmt, int stage, int D16, const MixArgs& a, int grid, hipStream_t s)
 {
-    if (stage == 1) return fmt == FMT_FP8 ? launch_mfma_fs<FMT_FP8, 1>(D16, a, grid, s)
-                                          : launch_mfma_fs<FMT_BF16, 1>(D16, a, grid, s);
-    if (stage == 2 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 2>(D16, a, grid, s);
-    if (stage == 3 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 3>(D16, a, grid, s);
-    if (stage == 0 && fmt == FMT_BF16) return launch_mfma_fs<FMT_BF16, 0>(D16, a, grid, s);
+    if (stage == 1) return fmt == FMT_FP8 ? launch_mfma_nw<FMT_FP8, 1>(D16, a, grid, s)
+                                          : launch_mfma_nw<FMT_BF16, 1>(D16, a, grid, s);
+    if (stage == 2 && fmt == FMT_BF16) return launch_mfma_nw<FMT_BF16, 2>(D16, a, grid, s);
+    if (stage == 3 && fmt == FMT_BF16) return launch_mfma_nw<FMT_BF16, 3>(D16, a, grid, s);
+    if (stage == 0 && fmt == FMT_BF16) return launch_mfma_nw<FMT_BF16, 0>(D16, a, grid, s);
     return hipErrorInvalidValue;
 }
 
-template <int D16, int FMT, int STAGE>
+template <int D16, int FMT, int STAGE, int NW>
 static int occ_mfma(int nbuf)
 {
-    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE, nbuf);
+    const size_t lds = mfma_lds_bytes(FMT, D16, STAGE, nbuf, NW);
     if (lds > 64 * 1024 &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&mfma_assign<D16, FMT, STAGE, NW>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return -1;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_assign<D16, FMT, STAGE>, 64 * kMixWaves, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfma_assign<D16, FMT, STAGE, NW>, 64 * NW, lds) !=
         hipSuccess)
         return -1;
     return nb;
 }
 
-template <int FMT, int STAGE>
+template <int FMT, int STAGE, int NW>
 static int occ_mfma_fs(int D16, int nbuf)
 {
     switch (D16) {
-    case 1: return occ_mfma<1, FMT, STAGE>(nbuf);
-    case 2: return occ_mfma<2, FMT, STAGE>(nbuf);
-    case 3: return occ_mfma<3, FMT, STAGE>(nbuf);
-    case 4: return occ_mfma<4, FMT, STAGE>(nbuf);
-    case 5: return occ_mfma<5, FMT, STAGE>(nbuf);
-    case 6: return occ_mfma<6, FMT, STAGE>(nbuf);
-    case 7: return occ_mfma<7, FMT, STAGE>(nbuf);
-    case 8: return occ_mfma<8, FMT, STAGE>(nbuf);
-    default: return D16 <= kMaxD16Wide ? occ_mfma<0, FMT, STAGE>(nbuf) : -1;
+    case 1: return occ_mfma<1, FMT, STAGE, NW>(nbuf);
+    case 2: return occ_mfma<2, FMT, STAGE, NW>(nbuf);
+    case 3: return occ_mfma<3, FMT, STAGE, NW>(nbuf);
+    case 4: return occ_mfma<4, FMT, STAGE, NW>(nbuf);
+    case 5: return occ_mfma<5, FMT, STAGE, NW>(nbuf);
+    case 6: return occ_mfma<6, FMT, STAGE, NW>(nbuf);
+    case 7: return occ_mfma<7, FMT, STAGE, NW>(nbuf);
+    case 8: return occ_mfma<8, FMT, STAGE, NW>(nbuf);
+    default:
+        if constexpr (NW == kMixWaves)
+            return D16 <= kMaxD16Wide ? occ_mfma<0, FMT, STAGE, NW>(nbuf) : -1;
+        else
+            return -1;
     }
 }
 
-int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf)
+template <int FMT, int STAGE>
+static int occ_mfma_nw(int D16, int nbuf, bool wide_blocks)
 {
-    if (stage == 1) return fmt == FMT_FP8 ? occ_mfma_fs<FMT_FP8, 1>(D16, nbuf) : occ_mfma_fs<FMT_BF16, 1>(D16, nbuf);
-    if (stage == 2 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 2>(D16, nbuf);
-    if (stage == 3 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 3>(D16, nbuf);
-    if (stage == 0 && fmt == FMT_BF16) return occ_mfma_fs<FMT_BF16, 0>(D16, nbuf);
+    if constexpr (STAGE >= 1) {
+        if (wide_blocks) return occ_mfma_fs<FMT, STAGE, mix_waves(STAGE, true)>(D16, nbuf);
+    }
+    return occ_mfma_fs<FMT, STAGE, kMixWaves>(D16, nbuf);
+}
+
+int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf, bool wide_blocks)
+{
+    if (stage == 1) return fmt == FMT_FP8 ? occ_mfma_nw<FMT_FP8, 1>(D16, nbuf, wide_blocks)
+                                          : occ_mfma_nw<FMT_BF16, 1>(D16, nbuf, wide_blocks);
+    if (stage == 2 && fmt == FMT_BF16) return occ_mfma_nw<FMT_BF16, 2>(D16, nbuf, wide_blocks);
+    if (stage == 3 && fmt == FMT_BF16) return occ_mfma_nw<FMT_BF16, 3>(D16, nbuf, wide_blocks);
+    if (stage == 0 && fmt == FMT_BF16) return occ_mfma_nw<FMT_BF16, 0>(D16, nbuf, false);
     return -1;
 }
 
