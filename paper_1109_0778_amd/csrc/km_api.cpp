@@ -79,6 +79,7 @@ struct km_plan {
     int upd_tiles = 1;   // update pass: tiles listed per step
     int grid_mfma = 0, grid_rc = 0;
     bool wide_blocks = false;   // MFMA stages 1-3 in blocks of mix_waves(stage, true) waves
+    int rc_split = kRecheckSplit;   // recheck blocks per queue region
     int64_t rq_per_block = 0;
     size_t off_xs = 0, off_pxm = 0, off_pxs = 0, off_ab = 0, off_bias = 0, off_cs = 0, off_rq = 0,
            off_rqc = 0, off_jt = 0;
@@ -356,7 +357,7 @@ hipError_t enqueue_mixed_assign(km_plan* p, const float* X, int32_t* labels, con
     r.nreg = G;
     r.labels = labels; r.changed_part = changed + p->mfma_passes() * G;
     r.ctrl = ctrl; r.iter = iter; r.count_changed = count_changed;
-    return p->wide ? launch_recheck_wide(r, G, s) : launch_recheck(p->D8, r, G, s);
+    return p->wide ? launch_recheck_wide(r, G, s) : launch_recheck(p->D8, r, G, p->rc_split, s);
 }
 
 // Run-level prep of the mixed path (once per call, amortised over its
@@ -501,7 +502,10 @@ km_status km_plan_create(int64_t n, int32_t d, int32_t k, km_precision prec, km_
         if (occ < 1) { delete p; return fail(KM_EHIP, "occupancy query for the MFMA pass failed"); }
         const int64_t mt = (n + kMixTile - 1) / kMixTile;
         p->grid_mfma = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(occ, 4), mt));
-        p->grid_rc = p->grid_mfma * kRecheckSplit;   // blocks (b, *) take the queue region of MFMA block b
+        // blocks (b, *) take the queue region of MFMA block b; wide blocks leave
+        // a third as many (larger) regions, so each gets three times the blocks
+        p->rc_split = p->wide_blocks ? 3 * kRecheckSplit : kRecheckSplit;
+        p->grid_rc = p->grid_mfma * p->rc_split;
         if (p->cascade && (mfma_blocks_per_cu(FMT_BF16, 3, p->D16, nbf, p->wide_blocks) < 1 ||
                            (p->fmt == FMT_FP8 && mfma_blocks_per_cu(FMT_BF16, 2, p->D16, nbf, p->wide_blocks) < 1))) {
             delete p;

@@ -374,7 +374,7 @@ constexpr int kMixResidentBytes = 24 * 1024;
 int mix_buffers(int fmt, int D16, int kpad);
 size_t mfma_lds_bytes(int fmt, int D16, int stage, int nbuf = 2, int waves = kMixWaves);
 int mfma_blocks_per_cu(int fmt, int stage, int D16, int nbuf = 2, bool wide_blocks = false);
-hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s);
+hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, int split, hipStream_t s);
 
 // Batched mixed path: one record per instance.  The per-iteration prep and
 // the |x| statistics run one block per instance; the MFMA pass and the

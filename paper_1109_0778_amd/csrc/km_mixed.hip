@@ -1638,10 +1638,10 @@ hipError_t launch_batch_recheck(int D8, const BatchWork* work, int nwork, const 
     return hipGetLastError();
 }
 
-hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, hipStream_t s)
+hipError_t launch_recheck(int D8, const RecheckArgs& a, int grid, int split, hipStream_t s)
 {
     switch (D8) {
-#define KM_RC(N) case N: hipLaunchKernelGGL((recheck_kernel<N>), dim3(grid, kRecheckSplit), dim3(256), 0, s, a); break;
+#define KM_RC(N) case N: hipLaunchKernelGGL((recheck_kernel<N>), dim3(grid, split), dim3(256), 0, s, a); break;
     KM_RC(1) KM_RC(2) KM_RC(3) KM_RC(4) KM_RC(5) KM_RC(6) KM_RC(7) KM_RC(8)
     KM_RC(9) KM_RC(10) KM_RC(11) KM_RC(12) KM_RC(13) KM_RC(14) KM_RC(15) KM_RC(16)
 #undef KM_RC
